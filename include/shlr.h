@@ -1,0 +1,197 @@
+/*
+ * shlr.h -- C ABI of the MI355X separable low-rank Hankel (SHLR) library.
+ *
+ * The library reconstructs undersampled multi-coil k-space with the
+ * separable Hankel low-rank models of Zhang et al., "Accelerated MRI
+ * Reconstruction with Separable and Enhanced Low-Rank Hankel Regularization"
+ * (arXiv 2107.11650):
+ *   - parallel imaging (model SHLR_MODEL_PI): SHLR, SHLR-S, SHLR-V, SHLR-SV
+ *     (Eqs. 2, 3, 5, 6), solved by the ADMM of Eqs. 9-17 in the order of
+ *     Algorithm S1 (inputs Y, U, G, lambda, lambda1, beta, tau; output X,
+ *     returned here as its k-space K = F^2D X, Eq. 2);
+ *   - parameter imaging (model SHLR_MODEL_PARAM): SHLR-P and SHLR-VP
+ *     (Eqs. 7, 8), solved by Eqs. S1-S9 in the order of Algorithm S2 for every
+ *     frequency-encode position (inputs Y^Parameter, U, lambda, lambda2, beta,
+ *     tau).
+ *
+ * Conventions shared by every entry point
+ *   - Complex data are interleaved (re, im): float pairs (complex64) when
+ *     precision == SHLR_PREC_MIXED, double pairs (complex128) when
+ *     precision == SHLR_PREC_FP64.
+ *   - k-space is centred: the DC sample of an axis of length n sits at index
+ *     n / 2 (integer division).  Every DFT is unitary.
+ *   - "dev" pointers are device (HBM) pointers owned by the caller; "host"
+ *     pointers are host memory owned by the caller.  The library never frees
+ *     caller memory and never keeps a caller pointer past the call, except the
+ *     workspace bound by shlr_bind, which must outlive the plan's use.
+ *   - Every function returns a shlr_status; none throws or aborts.  The text
+ *     of the last error of the calling thread is shlr_last_error().
+ *   - Work is enqueued on the stream given to shlr_bind (a hipStream_t passed
+ *     as void*).  Functions that return results to the host synchronise that
+ *     stream.  A plan must not be used from two threads at once.
+ */
+#ifndef SHLR_H
+#define SHLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHLR_MODEL_PI 0     /* parallel imaging: SHLR(-S/-V/-SV)          */
+#define SHLR_MODEL_PARAM 1  /* parameter imaging: SHLR-P / SHLR-VP         */
+
+#define SHLR_PREC_MIXED 0   /* complex64 data; FP32 MFMA Gram and reprojection; FP64 eigensolves */
+#define SHLR_PREC_FP64 1    /* complex128 data; FP64 everywhere */
+
+#define SHLR_MAX_SLICES 4096
+
+typedef enum {
+    SHLR_OK = 0,
+    SHLR_E_INVALID_ARG = 1,   /* a size, window, weight or pointer is out of range         */
+    SHLR_E_SINGULAR = 2,      /* Eq. 15 / Eq. S7 has a zero pivot (e.g. the k-space centre  */
+                              /* is not sampled while W vanishes there)                     */
+    SHLR_E_NONFINITE = 3,     /* NaN or Inf met in the input or in the iterate               */
+    SHLR_E_WORKSPACE = 4,     /* no workspace bound, or the bound one is too small          */
+    SHLR_E_DEVICE = 5,        /* a HIP runtime call failed                                  */
+    SHLR_E_UNSUPPORTED = 6,   /* a combination the library does not implement               */
+    SHLR_E_STATE = 7          /* call out of order (e.g. iterate before init)               */
+} shlr_status;
+
+/*
+ * Problem description.  All host arrays are read during shlr_plan_create only.
+ *
+ * SHLR_MODEL_PI: n_slices independent slices, slice s of size M[s] x N[s]
+ *   (rows x columns, Table I), J coils.  Row lifts (P_m, Eq. 2) act on lines of
+ *   length N with window k_row; column lifts (Q_n) on lines of length M with
+ *   window k_col.  Data layout [slice][J][M][N] with N fastest, slices packed
+ *   back to back; mask layout [slice][M][N] (uint8, nonzero = acquired,
+ *   shared by all coils).
+ * SHLR_MODEL_PARAM: one series of L echoes (parameter dimension), M
+ *   frequency-encode positions (fully sampled) and N phase-encode positions
+ *   (n_slices must be 1).  PE lifts (Q_l with W, F and optionally H_vc, Eq. 8)
+ *   use window k_row on lines of length N; parameter-direction lifts (P_n, H
+ *   only) use window k_col on lines of length L.  Data layout [L][J][M][N];
+ *   mask layout [L][N] (acquired PE lines of each echo).
+ */
+typedef struct {
+    int32_t model;          /* SHLR_MODEL_PI or SHLR_MODEL_PARAM                        */
+    int32_t precision;      /* SHLR_PREC_MIXED or SHLR_PREC_FP64                          */
+    int32_t n_slices;       /* PI: 1..SHLR_MAX_SLICES; PARAM: 1                           */
+    const int32_t* M;       /* host [n_slices]: rows (PARAM: FE positions)                */
+    const int32_t* N;       /* host [n_slices]: columns (PARAM: PE positions)             */
+    int32_t J;              /* coils, >= 1                                                */
+    int32_t L;              /* echoes (PARAM), >= 2; ignored for PI                       */
+    int32_t k_row;          /* window of row (PI) / PE (PARAM) lifts, 1..line length      */
+    int32_t k_col;          /* window of column (PI) / parameter-direction lifts           */
+    int32_t use_vc;         /* 1: virtual-coil lifts H_vc (Eq. 4; SHLR-V/-SV/-VP)         */
+    int32_t use_w;          /* 1: weighting W (Eq. 2); 0: plain Hankel of F^1D lines      */
+    int32_t spirit_ksize;   /* PI only: 0 = no SPIRiT term; odd kernel size (e.g. 5)       */
+    int32_t hard_dc;        /* 1: lambda = +inf, acquired samples kept exactly             */
+    int32_t normalize;      /* 1: divide Y by max|Y| before iterating, scale back after    */
+    int32_t max_iter;       /* iteration cap used by shlr_reconstruct                      */
+    int32_t n_cg;           /* PCG steps per X-update when the SPIRiT term is on           */
+    double lambda;          /* data-consistency weight (Eq. 2), > 0 unless hard_dc         */
+    double lambda1;         /* SPIRiT weight (Eq. 3), >= 0                                 */
+    double lambda2;         /* parameter-direction weight (Eq. 7), > 0 for PARAM           */
+    double beta;            /* ADMM penalty (Eq. 9), > 0                                   */
+    double tau;             /* multiplier step (Eqs. 13-14), > 0                           */
+    double tol;             /* relative-change stop of Algorithm S1/S2; <= 0: fixed count  */
+    double d0;              /* initial multiplier value (Algorithms S1/S2 use 1)           */
+} shlr_params;
+
+typedef struct {
+    int32_t iters_done;     /* iterations run by the last shlr_iterate / shlr_reconstruct  */
+    int32_t converged;      /* 1 if the tol test stopped it                                */
+    double rel_change;      /* last ||K^{k+1}-K^k||^2 / ||K^k||^2 (max over slices)         */
+    double scale;           /* max|Y| used for normalisation (1 if off)                     */
+    uint32_t device_flags;  /* bit0: non-finite value met                                   */
+} shlr_info;
+
+typedef struct shlr_plan shlr_plan;
+
+/* Validate p and build the plan (host only, no device call).  *out is NULL on error. */
+shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out);
+
+/* Free the plan's host memory (the workspace belongs to the caller).  NULL is accepted. */
+void shlr_plan_destroy(shlr_plan* plan);
+
+/* Bytes of device workspace the plan needs (host only). */
+shlr_status shlr_workspace_size(const shlr_plan* plan, size_t* bytes);
+
+/* Bind a caller-owned device workspace of at least shlr_workspace_size bytes
+ * (256-byte aligned) and the stream to enqueue on; uploads the plan's tables. */
+shlr_status shlr_bind(shlr_plan* plan, void* ws_dev, size_t bytes, void* stream);
+
+/* SPIRiT kernel (Eq. 3) from host memory: g_host[t][s][dm][dn], complex128,
+ * J x J x ks x ks, with K_t(x) ~ sum_{s,d} g[t][s][d] K_s(x + d) (circular).
+ * The per-pixel image-domain operator (G - I)^H (G - I) is built on the device. */
+shlr_status shlr_set_spirit_kernel(shlr_plan* plan, const void* g_host);
+
+/* Calibrate the SPIRiT kernel by Tikhonov least squares on the fully sampled
+ * acs x acs centre of the (normalised) data given to shlr_init, then install it.
+ * Weight reg * trace(A^H A) / n_unknowns.  Requires shlr_init first. */
+shlr_status shlr_calibrate_spirit(shlr_plan* plan, int32_t acs, double reg);
+
+/* Start a reconstruction: copy Y (device, layout above) and the mask
+ * (device, uint8), normalise, set Z = 0, D = d0 and K = Y (Algorithm S1/S2
+ * initialisation). */
+shlr_status shlr_init(shlr_plan* plan, const void* y_dev, const uint8_t* mask_dev);
+
+/* Run n ADMM iterations (X-update Eq. 15 / S7, Z-updates Eqs. 16-17 / S8-S9,
+ * multiplier updates Eqs. 13-14 / S5-S6).  With tol > 0 the relative change is
+ * read back every iteration and the loop stops early; with tol <= 0 nothing is
+ * read back and info (if not NULL) is filled after a stream synchronisation. */
+shlr_status shlr_iterate(shlr_plan* plan, int32_t n, shlr_info* info);
+
+/* Same iterations through a captured HIP graph of one iteration (tol ignored). */
+shlr_status shlr_iterate_graph(shlr_plan* plan, int32_t n, shlr_info* info);
+
+/* Write the current k-space estimate (scaled back) to k_out_dev (layout of Y). */
+shlr_status shlr_get_kspace(const shlr_plan* plan, void* k_out_dev);
+
+/* shlr_init + shlr_iterate(max_iter) + shlr_get_kspace. */
+shlr_status shlr_reconstruct(shlr_plan* plan, const void* y_dev, const uint8_t* mask_dev,
+                             void* k_out_dev, shlr_info* info);
+
+/* ---------------------------------------------------------------------------
+ * Stage entry points (the steps of one iteration, callable on their own).
+ * ------------------------------------------------------------------------- */
+
+/* Centred unitary 1D DFT (F^1D, Eq. 2) of n_lines contiguous lines of length n
+ * (inverse when inverse != 0).  in_dev and out_dev may alias.  n in [1, 4096]. */
+shlr_status shlr_fft_lines(int32_t precision, int32_t n, int32_t n_lines, int32_t inverse,
+                           const void* in_dev, void* out_dev, void* stream);
+
+/* Workspace bytes for shlr_lowrank_lines with these shapes. */
+shlr_status shlr_lowrank_workspace_size(int32_t precision, int32_t n_mat, int32_t J, int32_t n,
+                                        int32_t k, int32_t use_vc, size_t* bytes);
+
+/* One low-rank step on n_mat independent lines (Eqs. 16 and 13, plus the
+ * adjoint lift that feeds Eq. 15):
+ *   T   = lift(h) + D / beta          lift = H~ W~ or H~_vc W~ (Eqs. 2, 4)
+ *   Z   = S_thr(T)                     singular-value threshold (Eq. 16)
+ *   D  <- D + tau (lift(h) - Z)        (Eq. 13), in place
+ *   b   = lift^*(Z - D / beta)         (the term of the Eq. 15 right-hand side)
+ * h_dev: [n_mat][J][n] lines (k-space along the line); d_dev: [n_mat][p][q]
+ * with p = n-k+1, q = k*J*(1+use_vc), column index (v*J + j)*k + b; b_dev:
+ * [n_mat][J][n] output.  use_w selects W.  ranks_dev (may be NULL) receives
+ * the number of singular values above thr of each matrix (int32). */
+shlr_status shlr_lowrank_lines(int32_t precision, int32_t n_mat, int32_t J, int32_t n, int32_t k,
+                               int32_t use_vc, int32_t use_w, double beta, double tau, double thr,
+                               const void* h_dev, void* d_dev, void* b_dev, int32_t* ranks_dev,
+                               void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Text of the calling thread's last error ("" if none). */
+const char* shlr_last_error(void);
+
+/* Library version string. */
+const char* shlr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHLR_H */

@@ -1,0 +1,440 @@
+// Centred unitary 1D DFTs of batched lines, the fused X-update of Eq. 15 /
+// Eq. S7, and small element-wise kernels (gfx950).
+//
+// DFT convention: DC at index n/2 on both sides, 1/sqrt(n) scaling, so the
+// transform is unitary and its adjoint is its inverse (as Eq. 15 requires).
+// The transform itself is a mixed-radix Stockham FFT in LDS (radix 4, 2 and
+// every remaining prime; a prime radix is applied as a direct small DFT).
+// The centring is folded into the load and store indices.
+#include "common.h"
+#include "kernels.h"
+
+namespace shlr {
+
+constexpr int FFT_THREADS = 256;
+__device__ inline int64_t line_off(const LineAddr& a, int g) {
+    const int g1 = g / a.n0, g0 = g - (g / a.n0) * a.n0;
+    return a.base + (int64_t)g1 * a.s1 + (int64_t)g0 * a.s0;
+}
+
+template <typename C>
+__device__ inline void make_twiddles(C* tw, int n, int tid, int nth) {
+    for (int j = tid; j < n; j += nth) {
+        double sn, cs;
+        sincospi(-2.0 * (double)j / (double)n, &sn, &cs);
+        tw[j] = cmk<C>(cs, sn);
+    }
+}
+
+template <typename C>
+__device__ inline C twid(const C* tw, int idx, int n, bool inv) {
+    C w = tw[idx];
+    if (inv) w.y = -w.y;
+    (void)n;
+    return w;
+}
+
+// Runs the stages on NL lines stored contiguously in b0; returns the buffer holding the result.
+template <typename C>
+__device__ C* fft_run(C* b0, C* b1, const C* tw, int n, int NL, const FftPlan& pl, bool inv, int tid, int nth) {
+    int Ns = 1;
+    for (int st = 0; st < pl.nst; ++st) {
+        const int r = pl.radix[st];
+        const int nb = n / r;
+        const int tsc = n / (Ns * r);
+        for (int e = tid; e < NL * nb; e += nth) {
+            const int line = e / nb, j = e - line * nb;
+            const C* in = b0 + line * n;
+            C* out = b1 + line * n;
+            const int kq = j % Ns;
+            const int tstep = kq * tsc;
+            const int od = (j / Ns) * Ns * r + kq;
+            if (r == 4) {
+                C x0 = in[j];
+                C x1 = cmul(in[j + nb], twid(tw, tstep % n, n, inv));
+                C x2 = cmul(in[j + 2 * nb], twid(tw, (2 * tstep) % n, n, inv));
+                C x3 = cmul(in[j + 3 * nb], twid(tw, (3 * tstep) % n, n, inv));
+                C s02 = cadd(x0, x2), d02 = csub(x0, x2);
+                C s13 = cadd(x1, x3), d13 = csub(x1, x3);
+                // forward: -i * d13 ; inverse: +i * d13
+                C jd = inv ? cmk<C>(-d13.y, d13.x) : cmk<C>(d13.y, -d13.x);
+                out[od] = cadd(s02, s13);
+                out[od + Ns] = cadd(d02, jd);
+                out[od + 2 * Ns] = csub(s02, s13);
+                out[od + 3 * Ns] = csub(d02, jd);
+            } else if (r == 2) {
+                C x0 = in[j];
+                C x1 = cmul(in[j + nb], twid(tw, tstep % n, n, inv));
+                out[od] = cadd(x0, x1);
+                out[od + Ns] = csub(x0, x1);
+            } else {
+                for (int u = 0; u < r; ++u) {
+                    C acc = cmk<C>(0, 0);
+                    const int step = tstep + u * nb;
+                    for (int t = 0; t < r; ++t) {
+                        const int idx = (int)(((int64_t)t * step) % n);
+                        acc = cadd(acc, cmul(in[j + t * nb], twid(tw, idx, n, inv)));
+                    }
+                    out[od + u * Ns] = acc;
+                }
+            }
+        }
+        __syncthreads();
+        C* t = b0;
+        b0 = b1;
+        b1 = t;
+        Ns *= r;
+    }
+    return b0;
+}
+
+// dst[line][(i - c) mod n] = src[line][i]  (centred load), for nl lines
+template <typename C>
+__device__ inline void load_lines_centred(C* dst, const C* src, const LineAddr& a, int g0, int nl, int n, int tid,
+                                          int nth) {
+    const int c = n / 2;
+    if (a.es == 1) {
+        for (int e = tid; e < nl * n; e += nth) {
+            const int line = e / n, i = e - line * n;
+            int t = i - c;
+            if (t < 0) t += n;
+            dst[line * n + t] = src[line_off(a, g0 + line) + i];
+        }
+    } else {
+        for (int e = tid; e < nl * n; e += nth) {
+            const int line = e % nl, i = e / nl;
+            int t = i - c;
+            if (t < 0) t += n;
+            dst[line * n + t] = src[line_off(a, g0 + line) + (int64_t)i * a.es];
+        }
+    }
+}
+
+template <typename C, typename R>
+__device__ inline void store_lines_centred(C* dstg, const C* res, const LineAddr& a, int g0, int nl, int n, R scale,
+                                           int tid, int nth) {
+    const int c = n / 2;
+    if (a.es == 1) {
+        for (int e = tid; e < nl * n; e += nth) {
+            const int line = e / n, i = e - line * n;
+            int f = i - c;
+            if (f < 0) f += n;
+            dstg[line_off(a, g0 + line) + i] = cscale(res[line * n + f], scale);
+        }
+    } else {
+        for (int e = tid; e < nl * n; e += nth) {
+            const int line = e % nl, i = e / nl;
+            int f = i - c;
+            if (f < 0) f += n;
+            dstg[line_off(a, g0 + line) + (int64_t)i * a.es] = cscale(res[line * n + f], scale);
+        }
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(const cplx_t<R>* in, cplx_t<R>* out, LineAddr ia,
+                                                           LineAddr oa, FftPlan pl, int n_lines, int NL, int inverse,
+                                                           R scale) {
+    using C = cplx_t<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int n = pl.n;
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    C* b0 = tw + n;
+    C* b1 = b0 + NL * n;
+    const int tid = threadIdx.x;
+    make_twiddles(tw, n, tid, FFT_THREADS);
+    const int g0 = blockIdx.x * NL;
+    const int nl = min(NL, n_lines - g0);
+    load_lines_centred(b0, in, ia, g0, nl, n, tid, FFT_THREADS);
+    __syncthreads();
+    C* res = fft_run(b0, b1, tw, n, nl, pl, inverse != 0, tid, FFT_THREADS);
+    store_lines_centred(out, res, oa, g0, nl, n, scale, tid, FFT_THREADS);
+}
+
+// ---------------------------------------------------------------------------
+// Fused X-update over rows (Eq. 15 for the PI model, Eq. S7 for PARAM):
+//   c   = F(bo_row)                      other-direction adjoint term to k-space
+//   K   = (lam m Y + beta (a + c)) / (lam m + beta (rr[i] + rc[row]))
+//         (hard data consistency: K = Y where m, else (a + c)/(rr + rc))
+//   out = F^-1(K_row)                    hybrid line for the next lifts
+// Row index g -> digits (d2, d1, d0) with sizes (., n1, n0).
+// ---------------------------------------------------------------------------
+__device__ inline void row_digits(const XupdRows& x, int g, int& d2, int& d1, int& d0) {
+    d0 = g % x.n0;
+    const int t = g / x.n0;
+    d1 = t % x.n1;
+    d2 = t / x.n1;
+}
+__device__ inline int64_t row_off(const RowAddr& a, int d2, int d1, int d0) {
+    return (int64_t)d2 * a.s2 + (int64_t)d1 * a.s1 + (int64_t)d0 * a.s0;
+}
+
+template <typename R>
+__global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __restrict__ base_bo,
+                                                           const cplx_t<R>* __restrict__ base_a,
+                                                           const cplx_t<R>* __restrict__ base_y,
+                                                           cplx_t<R>* __restrict__ base_k,
+                                                           cplx_t<R>* __restrict__ base_out,
+                                                           const uint8_t* __restrict__ base_m,
+                                                           const R* __restrict__ rtab, XupdRows x, FftPlan pl,
+                                                           int NL, R lam, R beta, int hard_dc,
+                                                           double* __restrict__ change_acc) {
+    using C = cplx_t<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int n = x.n;
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    C* b0 = tw + n;
+    C* b1 = b0 + NL * n;
+    const int tid = threadIdx.x;
+    make_twiddles(tw, n, tid, FFT_THREADS);
+    const int g0 = blockIdx.x * NL;
+    const int nl = min(NL, x.n_rows - g0);
+    const int c = n / 2;
+    const R sc = (R)(1.0 / sqrt((double)n));
+    // 1. load the other-direction adjoint rows (centred)
+    if (x.bo.es == 1) {
+        for (int e = tid; e < nl * n; e += FFT_THREADS) {
+            const int line = e / n, i = e - line * n;
+            int d2, d1, d0;
+            row_digits(x, g0 + line, d2, d1, d0);
+            int t = i - c;
+            if (t < 0) t += n;
+            b0[line * n + t] = base_bo[row_off(x.bo, d2, d1, d0) + i];
+        }
+    } else {
+        for (int e = tid; e < nl * n; e += FFT_THREADS) {
+            const int line = e % nl, i = e / nl;
+            int d2, d1, d0;
+            row_digits(x, g0 + line, d2, d1, d0);
+            int t = i - c;
+            if (t < 0) t += n;
+            b0[line * n + t] = base_bo[row_off(x.bo, d2, d1, d0) + (int64_t)i * x.bo.es];
+        }
+    }
+    __syncthreads();
+    C* res = fft_run(b0, b1, tw, n, nl, pl, false, tid, FFT_THREADS);
+    C* oth = (res == b0) ? b1 : b0;
+    // 2. combine; write K and stage K (centred) for the inverse transform
+    double dsum = 0, osum = 0;
+    for (int e = tid; e < nl * n; e += FFT_THREADS) {
+        const int line = e / n, i = e - line * n;
+        int d2, d1, d0;
+        row_digits(x, g0 + line, d2, d1, d0);
+        int f = i - c;
+        if (f < 0) f += n;
+        const C cv = cscale(res[line * n + f], sc);
+        const C av = base_a[row_off(x.a, d2, d1, d0) + (int64_t)i * x.a.es];
+        const int64_t yo = row_off(x.y, d2, d1, d0) + (int64_t)i * x.y.es;
+        const int64_t ko = row_off(x.k, d2, d1, d0) + (int64_t)i * x.k.es;
+        const uint8_t mk = base_m[row_off(x.msk, d2, d1, d0) + (int64_t)i * x.msk.es];
+        const int rci = x.rc_digit == 0 ? d0 : (x.rc_digit == 1 ? d1 : d2);
+        const R rsum = rtab[x.rr_off + i] + rtab[x.rc_off + rci];
+        C kv;
+        if (hard_dc) {
+            if (mk) kv = base_y[yo];
+            else kv = cmk<C>((av.x + cv.x) / rsum, (av.y + cv.y) / rsum);
+        } else {
+            const C yv = base_y[yo];
+            const R lm = mk ? lam : (R)0;
+            const R den = lm + beta * rsum;
+            kv = cmk<C>((lm * yv.x + beta * (av.x + cv.x)) / den, (lm * yv.y + beta * (av.y + cv.y)) / den);
+        }
+        if (change_acc) {
+            const C ko_old = base_k[ko];
+            dsum += (double)(kv.x - ko_old.x) * (kv.x - ko_old.x) + (double)(kv.y - ko_old.y) * (kv.y - ko_old.y);
+            osum += (double)ko_old.x * ko_old.x + (double)ko_old.y * ko_old.y;
+        }
+        base_k[ko] = kv;
+        oth[line * n + f] = kv;
+    }
+    if (change_acc) {
+        for (int off = 32; off > 0; off >>= 1) {
+            dsum += __shfl_down(dsum, off, 64);
+            osum += __shfl_down(osum, off, 64);
+        }
+        if ((tid & 63) == 0) {
+            atomicAdd(change_acc, dsum);
+            atomicAdd(change_acc + 1, osum);
+        }
+    }
+    __syncthreads();
+    // 3. inverse transform of K and store the hybrid rows
+    C* res2 = fft_run(oth, res, tw, n, nl, pl, true, tid, FFT_THREADS);
+    if (x.out.es == 1) {
+        for (int e = tid; e < nl * n; e += FFT_THREADS) {
+            const int line = e / n, i = e - line * n;
+            int d2, d1, d0;
+            row_digits(x, g0 + line, d2, d1, d0);
+            int f = i - c;
+            if (f < 0) f += n;
+            base_out[row_off(x.out, d2, d1, d0) + i] = cscale(res2[line * n + f], sc);
+        }
+    } else {
+        for (int e = tid; e < nl * n; e += FFT_THREADS) {
+            const int line = e % nl, i = e / nl;
+            int d2, d1, d0;
+            row_digits(x, g0 + line, d2, d1, d0);
+            int f = i - c;
+            if (f < 0) f += n;
+            base_out[row_off(x.out, d2, d1, d0) + (int64_t)i * x.out.es] = cscale(res2[line * n + f], sc);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// element-wise helpers
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void k_scale_copy(const cplx_t<R>* in, cplx_t<R>* out, int64_t count, const double* scale_ptr, int invert) {
+    const double sc = scale_ptr ? (invert ? 1.0 / scale_ptr[0] : scale_ptr[0]) : 1.0;
+    const R s = (R)sc;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = cscale(in[i], s);
+}
+
+// out[idx] = table[(idx / div) % mod]
+template <typename R>
+__global__ void k_fill_pattern(cplx_t<R>* out, int64_t count, const cplx_t<R>* table, int64_t div, int64_t mod) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = table[(i / div) % mod];
+}
+
+template <typename R>
+__global__ void k_fill_const(cplx_t<R>* out, int64_t count, R re, R im) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = cmk<cplx_t<R>>(re, im);
+}
+
+// running max of |x| (non-negative doubles order like their bit patterns); also flags non-finite values
+template <typename R>
+__global__ void k_maxabs(const cplx_t<R>* in, int64_t count, unsigned long long* out, uint32_t* flags) {
+    double m = 0;
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        const cplx_t<R> v = in[i];
+        const double a = sqrt((double)v.x * v.x + (double)v.y * v.y);
+        if (!(a <= 1.79e308)) bad = true;
+        else m = fmax(m, a);
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+    if (bad && flags) atomicOr(flags, 1u);
+}
+
+__global__ void k_zero_doubles(double* p, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+FftPlan make_fft_plan(int n) {
+    FftPlan p;
+    p.n = n;
+    p.nst = 0;
+    int m = n;
+    while (m % 4 == 0 && p.nst < FFT_MAX_STAGES) { p.radix[p.nst++] = 4; m /= 4; }
+    while (m % 2 == 0 && p.nst < FFT_MAX_STAGES) { p.radix[p.nst++] = 2; m /= 2; }
+    for (int f = 3; m > 1 && p.nst < FFT_MAX_STAGES; f += 2) {
+        while (m % f == 0 && p.nst < FFT_MAX_STAGES) { p.radix[p.nst++] = f; m /= f; }
+    }
+    return p;
+}
+
+template <typename R>
+static int fft_lines_per_block(int n, bool strided) {
+    int budget = (sizeof(R) == 4 ? 2048 : 1024) * (strided ? 2 : 1);
+    int nl = budget / n;
+    if (nl < 1) nl = 1;
+    if (nl > 64) nl = 64;
+    return nl;
+}
+
+template <typename R>
+hipError_t launch_fft_lines(hipStream_t st, const cplx_t<R>* in, cplx_t<R>* out, const LineAddr& ia,
+                            const LineAddr& oa, int n, int n_lines, int inverse, double scale) {
+    if (n_lines <= 0) return hipSuccess;
+    FftPlan pl = make_fft_plan(n);
+    const int NL = fft_lines_per_block<R>(n, ia.es != 1 || oa.es != 1);
+    const size_t lds = (size_t)(n + 2 * NL * n) * sizeof(cplx_t<R>);
+    hipError_t e = hipFuncSetAttribute((const void*)k_fft_lines<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    const int blocks = (n_lines + NL - 1) / NL;
+    hipLaunchKernelGGL((k_fft_lines<R>), dim3(blocks), dim3(FFT_THREADS), lds, st, in, out, ia, oa, pl, n_lines, NL,
+                       inverse, (R)scale);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_xupd_rows(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>* a, const cplx_t<R>* y,
+                            cplx_t<R>* k, cplx_t<R>* out, const uint8_t* m, const R* rtab, const XupdRows& x,
+                            double lam, double beta, int hard_dc, double* change_acc) {
+    if (x.n_rows <= 0) return hipSuccess;
+    FftPlan pl = make_fft_plan(x.n);
+    const int NL = fft_lines_per_block<R>(x.n, x.bo.es != 1 || x.out.es != 1);
+    const size_t lds = (size_t)(x.n + 2 * NL * x.n) * sizeof(cplx_t<R>);
+    hipError_t e = hipFuncSetAttribute((const void*)k_xupd_rows<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    const int blocks = (x.n_rows + NL - 1) / NL;
+    hipLaunchKernelGGL((k_xupd_rows<R>), dim3(blocks), dim3(FFT_THREADS), lds, st, bo, a, y, k, out, m, rtab, x, pl,
+                       NL, (R)lam, (R)beta, hard_dc, change_acc);
+    return hipGetLastError();
+}
+
+static inline int ew_blocks(int64_t count) {
+    int64_t b = (count + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+template <typename R>
+hipError_t launch_scale_copy(hipStream_t st, const cplx_t<R>* in, cplx_t<R>* out, int64_t count,
+                             const double* scale_ptr, int invert) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_scale_copy<R>), dim3(ew_blocks(count)), dim3(256), 0, st, in, out, count, scale_ptr, invert);
+    return hipGetLastError();
+}
+template <typename R>
+hipError_t launch_fill_pattern(hipStream_t st, cplx_t<R>* out, int64_t count, const cplx_t<R>* table, int64_t div,
+                               int64_t mod) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fill_pattern<R>), dim3(ew_blocks(count)), dim3(256), 0, st, out, count, table, div, mod);
+    return hipGetLastError();
+}
+template <typename R>
+hipError_t launch_fill_const(hipStream_t st, cplx_t<R>* out, int64_t count, double re, double im) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fill_const<R>), dim3(ew_blocks(count)), dim3(256), 0, st, out, count, (R)re, (R)im);
+    return hipGetLastError();
+}
+template <typename R>
+hipError_t launch_maxabs(hipStream_t st, const cplx_t<R>* in, int64_t count, unsigned long long* out,
+                         uint32_t* flags) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_maxabs<R>), dim3(ew_blocks(count)), dim3(256), 0, st, in, count, out, flags);
+    return hipGetLastError();
+}
+hipError_t launch_zero_doubles(hipStream_t st, double* p, int count) {
+    hipLaunchKernelGGL(k_zero_doubles, dim3(1), dim3(256), 0, st, p, count);
+    return hipGetLastError();
+}
+
+#define SHLR_INST(R)                                                                                                 \
+    template hipError_t launch_fft_lines<R>(hipStream_t, const cplx_t<R>*, cplx_t<R>*, const LineAddr&,              \
+                                            const LineAddr&, int, int, int, double);                                 \
+    template hipError_t launch_xupd_rows<R>(hipStream_t, const cplx_t<R>*, const cplx_t<R>*, const cplx_t<R>*,       \
+                                            cplx_t<R>*, cplx_t<R>*, const uint8_t*, const R*, const XupdRows&,       \
+                                            double, double, int, double*);                                           \
+    template hipError_t launch_scale_copy<R>(hipStream_t, const cplx_t<R>*, cplx_t<R>*, int64_t, const double*, int); \
+    template hipError_t launch_fill_pattern<R>(hipStream_t, cplx_t<R>*, int64_t, const cplx_t<R>*, int64_t, int64_t); \
+    template hipError_t launch_fill_const<R>(hipStream_t, cplx_t<R>*, int64_t, double, double);                      \
+    template hipError_t launch_maxabs<R>(hipStream_t, const cplx_t<R>*, int64_t, unsigned long long*, uint32_t*);
+SHLR_INST(float)
+SHLR_INST(double)
+
+}  // namespace shlr

@@ -1,0 +1,1007 @@
+// C ABI of the SHLR library: plans, workspace layout and the orchestration of
+// one ADMM iteration on one HIP stream.  All arithmetic runs in the kernels of
+// fft.hip, lowrank.hip, eig.hip and spirit.hip; this file only validates,
+// lays out memory and enqueues launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/shlr.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace shlr;
+
+static thread_local std::string g_last_error;
+
+static shlr_status fail(shlr_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIPCHK(call)                                                                        \
+    do {                                                                                    \
+        hipError_t _e = (call);                                                             \
+        if (_e != hipSuccess)                                                               \
+            return fail(SHLR_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(_e));      \
+    } while (0)
+
+#define STCHK(call)                          \
+    do {                                     \
+        shlr_status _s = (call);             \
+        if (_s != SHLR_OK) return _s;        \
+    } while (0)
+
+extern "C" const char* shlr_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* shlr_version(void) { return "shlr-mi355x 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// host-side tables (FP64), shared by the two precisions
+// ---------------------------------------------------------------------------
+
+// W of Eq. 2: DFT of the circular first difference at the centred frequency
+static void weights_host(int n, std::vector<double>& re, std::vector<double>& im) {
+    re.resize(n);
+    im.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const double f = (double)(i - n / 2);
+        re[i] = 1.0 - cos(2.0 * M_PI * f / n);
+        im[i] = sin(2.0 * M_PI * f / n);
+    }
+}
+
+static int flip_idx(int n, int i) { return ((2 * (n / 2) - i) % n + n) % n; }
+static double hankel_count(int n, int k, int i) {
+    return (double)std::min(std::min(i + 1, k), std::min(n - k + 1, n - i));
+}
+
+// Diagonal of (lift)^*(lift) on one line (the Eq. 15 / S7 Hankel terms)
+static std::vector<double> gram_diag_host(int n, int k, bool use_w, bool vc) {
+    std::vector<double> wr, wi;
+    weights_host(n, wr, wi);
+    std::vector<double> r(n);
+    for (int i = 0; i < n; ++i) {
+        const double a = use_w ? wr[i] * wr[i] + wi[i] * wi[i] : 1.0;
+        r[i] = hankel_count(n, k, i) * a;
+        if (vc) {
+            const int f = flip_idx(n, i);
+            const double af = use_w ? wr[f] * wr[f] + wi[f] * wi[f] : 1.0;
+            r[i] += hankel_count(n, k, f) * af;
+        }
+    }
+    return r;
+}
+
+// lift^*(const * ones): the initial adjoint term for D = d0, Z = 0 (same on every line)
+static void init_adjoint_host(int n, int k, bool use_w, bool vc, double cst, std::vector<double>& re,
+                              std::vector<double>& im) {
+    std::vector<double> wr, wi;
+    weights_host(n, wr, wi);
+    re.assign(n, 0.0);
+    im.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        const double c = hankel_count(n, k, i) * cst;
+        const double ar = use_w ? wr[i] : 1.0, ai = use_w ? wi[i] : 0.0;
+        re[i] += ar * c;  // conj(w) * c
+        im[i] += -ai * c;
+        if (vc) {
+            const int f = flip_idx(n, i);
+            const double cf = hankel_count(n, k, f) * cst;
+            const double fr = use_w ? wr[f] : 1.0, fi = use_w ? wi[f] : 0.0;
+            // conj(conj(w_f) * cf) = w_f * cf
+            re[i] += fr * cf;
+            im[i] += fi * cf;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+
+struct LRGroup {
+    int first, count;  // descriptors [first, first + count)
+    LRDesc proto;
+};
+
+struct SliceLayout {
+    int M, N;
+    // complex offsets (elements of the working complex type)
+    int64_t yn, k, a, hr, hct, br, bct, dr, dc;
+    // PARAM
+    int64_t bp, be, xe, dp, de;
+    int64_t mask_b;        // byte offset of the mask copy
+    int64_t rr, rc;        // real-table offsets (elements of the working real type)
+    int64_t wr, wc;        // complex weight-table offsets (elements)
+    int64_t vr, vc;        // complex init-pattern offsets
+};
+
+struct shlr_plan {
+    shlr_params p;
+    std::vector<int32_t> Ms, Ns;
+    int csize;   // bytes per complex
+    int rsize;   // bytes per real
+    std::vector<SliceLayout> sl;
+    std::vector<LRDesc> descs;
+    std::vector<LRGroup> groups;
+    int s_max = 0;
+    int n_slots = 0;
+    // byte offsets in the workspace
+    size_t off_c = 0, bytes_c = 0;      // complex arena
+    size_t off_r = 0, bytes_r = 0;      // real arena
+    size_t off_m = 0, bytes_m = 0;      // mask arena
+    size_t off_desc = 0, off_g = 0, off_s = 0, off_scr = 0, off_ranks = 0, off_scal = 0;
+    size_t off_spirit = 0, bytes_spirit = 0;
+    size_t total = 0;
+    int64_t g_stride = 0, s_stride = 0, scr_stride = 0;
+    // host tables uploaded at bind
+    std::vector<double> rtab;                      // real table (FP64, converted at upload)
+    std::vector<double> ctab;                      // complex table interleaved (FP64)
+    // device state
+    unsigned char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false, initialised = false;
+    std::vector<double> scales;
+    int64_t total_elems = 0;  // complex elements of Y
+    // spirit
+    bool spirit_ready = false;
+    // graph
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int iters_total = 0;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static shlr_status validate(const shlr_params* p) {
+    if (!p) return fail(SHLR_E_INVALID_ARG, "params is NULL");
+    if (p->model != SHLR_MODEL_PI && p->model != SHLR_MODEL_PARAM)
+        return fail(SHLR_E_INVALID_ARG, "model must be SHLR_MODEL_PI or SHLR_MODEL_PARAM");
+    if (p->precision != SHLR_PREC_MIXED && p->precision != SHLR_PREC_FP64)
+        return fail(SHLR_E_INVALID_ARG, "precision must be SHLR_PREC_MIXED or SHLR_PREC_FP64");
+    if (p->n_slices < 1 || p->n_slices > SHLR_MAX_SLICES)
+        return fail(SHLR_E_INVALID_ARG, "n_slices must be in [1, %d]", SHLR_MAX_SLICES);
+    if (p->model == SHLR_MODEL_PARAM && p->n_slices != 1)
+        return fail(SHLR_E_INVALID_ARG, "the parameter-imaging model takes one series (n_slices = 1)");
+    if (!p->M || !p->N) return fail(SHLR_E_INVALID_ARG, "M and N must be host arrays");
+    if (p->J < 1 || p->J > 64) return fail(SHLR_E_INVALID_ARG, "J must be in [1, 64]");
+    if (!(p->beta > 0) || !isfinite(p->beta)) return fail(SHLR_E_INVALID_ARG, "beta must be positive and finite");
+    if (!(p->tau > 0) || !isfinite(p->tau)) return fail(SHLR_E_INVALID_ARG, "tau must be positive and finite");
+    if (!p->hard_dc && (!(p->lambda > 0) || !isfinite(p->lambda)))
+        return fail(SHLR_E_INVALID_ARG, "lambda must be positive and finite (or set hard_dc)");
+    if (!(p->lambda1 >= 0) || !isfinite(p->lambda1)) return fail(SHLR_E_INVALID_ARG, "lambda1 must be >= 0");
+    if (!isfinite(p->d0)) return fail(SHLR_E_INVALID_ARG, "d0 must be finite");
+    if (p->max_iter < 0) return fail(SHLR_E_INVALID_ARG, "max_iter must be >= 0");
+    if (p->model == SHLR_MODEL_PARAM) {
+        if (p->L < 2 || p->L > 512) return fail(SHLR_E_INVALID_ARG, "L must be in [2, 512]");
+        if (!(p->lambda2 > 0) || !isfinite(p->lambda2)) return fail(SHLR_E_INVALID_ARG, "lambda2 must be positive");
+        if (p->spirit_ksize != 0) return fail(SHLR_E_UNSUPPORTED, "the SPIRiT term is defined for the PI model only");
+    }
+    if (p->spirit_ksize < 0 || (p->spirit_ksize > 0 && (p->spirit_ksize % 2 == 0 || p->spirit_ksize > 9)))
+        return fail(SHLR_E_INVALID_ARG, "spirit_ksize must be 0 or odd in [1, 9]");
+    if (p->spirit_ksize > 0 && p->hard_dc) return fail(SHLR_E_UNSUPPORTED, "SPIRiT with hard data consistency");
+    if (p->spirit_ksize > 0 && p->n_cg < 1) return fail(SHLR_E_INVALID_ARG, "n_cg must be >= 1 with SPIRiT");
+    for (int s = 0; s < p->n_slices; ++s) {
+        const int M = p->M[s], N = p->N[s];
+        if (M < 1 || N < 1 || M > 4096 || N > 4096) return fail(SHLR_E_INVALID_ARG, "slice %d: bad size %dx%d", s, M, N);
+        const int nr = N, nc = (p->model == SHLR_MODEL_PI) ? M : p->L;
+        if (p->k_row < 1 || p->k_row > nr) return fail(SHLR_E_INVALID_ARG, "k_row must be in [1, %d]", nr);
+        if (p->k_col < 1 || p->k_col > nc) return fail(SHLR_E_INVALID_ARG, "k_col must be in [1, %d]", nc);
+        const int V = p->use_vc ? 2 : 1;
+        const int pr = nr - p->k_row + 1, qr = p->k_row * p->J * V;
+        const int Vc = (p->model == SHLR_MODEL_PI) ? V : 1;
+        const int pc = nc - p->k_col + 1, qc = p->k_col * p->J * Vc;
+        if (std::min(pr, qr) > 320 || std::min(pc, qc) > 320)
+            return fail(SHLR_E_UNSUPPORTED, "lifted matrices with min(p, q) > 320 are not supported");
+        if (std::max(pr, qr) > 4096 || std::max(pc, qc) > 4096)
+            return fail(SHLR_E_UNSUPPORTED, "lifted matrices with max(p, q) > 4096 are not supported");
+    }
+    return SHLR_OK;
+}
+
+static LRDesc make_desc(int64_t h_off, int h_cs, int h_es, int64_t b_off, int b_cs, int b_es, int64_t d_off, int n,
+                        int k, int J, int V, int use_w, int64_t w_off, double thr) {
+    LRDesc d;
+    d.h_off = h_off;
+    d.b_off = b_off;
+    d.d_off = d_off;
+    d.h_cs = h_cs;
+    d.h_es = h_es;
+    d.b_cs = b_cs;
+    d.b_es = b_es;
+    d.n = n;
+    d.k = k;
+    d.J = J;
+    d.V = V;
+    d.use_w = use_w;
+    d.w_off = (int32_t)w_off;
+    d.thr = thr;
+    return d;
+}
+
+static const size_t SLOT_BUDGET = (size_t)3 << 30;   // eigen-solver scratch for one chunk
+
+static void layout_slots(shlr_plan* P, int n_mat) {
+    const int s = P->s_max;
+    P->g_stride = (int64_t)s * s;                       // double2
+    P->s_stride = (int64_t)s * s;                       // working complex
+    P->scr_stride = eig_scratch_doubles(s);             // doubles
+    const size_t per = P->g_stride * 16 + P->s_stride * P->csize + P->scr_stride * 8 + 3 * 256;
+    int slots = (int)std::max<size_t>(1, SLOT_BUDGET / per);
+    P->n_slots = std::min(n_mat, slots);
+}
+
+extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
+    if (!out) return fail(SHLR_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    STCHK(validate(p));
+    shlr_plan* P = new shlr_plan();
+    P->p = *p;
+    P->Ms.assign(p->M, p->M + p->n_slices);
+    P->Ns.assign(p->N, p->N + p->n_slices);
+    P->p.M = nullptr;
+    P->p.N = nullptr;
+    P->csize = p->precision == SHLR_PREC_MIXED ? 8 : 16;
+    P->rsize = p->precision == SHLR_PREC_MIXED ? 4 : 8;
+    const int J = p->J, V = p->use_vc ? 2 : 1;
+    int64_t c = 0, r = 0, m = 0;
+    auto cal = [&](int64_t n) { int64_t o = c; c += n; c = (c + 31) & ~(int64_t)31; return o; };
+    auto ral = [&](int64_t n) { int64_t o = r; r += n; r = (r + 63) & ~(int64_t)63; return o; };
+    auto mal = [&](int64_t n) { int64_t o = m; m += n; m = (m + 255) & ~(int64_t)255; return o; };
+    std::vector<double>& rt = P->rtab;
+    std::vector<double>& ct = P->ctab;
+    auto put_real = [&](int64_t off, const std::vector<double>& v) {
+        if ((int64_t)rt.size() < off + (int64_t)v.size()) rt.resize(off + v.size(), 0.0);
+        for (size_t i = 0; i < v.size(); ++i) rt[off + i] = v[i];
+    };
+    std::vector<double> ctmp;
+    // complex host table (weights + init patterns): stored densely, copied into the complex arena
+    auto put_cplx = [&](const std::vector<double>& re, const std::vector<double>& im) {
+        int64_t o = (int64_t)ct.size() / 2;
+        for (size_t i = 0; i < re.size(); ++i) {
+            ct.push_back(re[i]);
+            ct.push_back(im[i]);
+        }
+        return o;
+    };
+    std::vector<double> wr, wi, vr, vi;
+    const double thr_rc = 1.0 / p->beta;
+    if (p->model == SHLR_MODEL_PI) {
+        for (int s = 0; s < p->n_slices; ++s) {
+            SliceLayout L{};
+            const int M = P->Ms[s], N = P->Ns[s];
+            L.M = M;
+            L.N = N;
+            const int64_t e = (int64_t)J * M * N;
+            L.yn = cal(e);
+            L.k = cal(e);
+            L.a = cal(e);
+            L.hr = cal(e);
+            L.hct = cal(e);
+            L.br = cal(e);
+            L.bct = cal(e);
+            const int pr = N - p->k_row + 1, qr = p->k_row * J * V;
+            const int pc = M - p->k_col + 1, qc = p->k_col * J * V;
+            L.dr = cal((int64_t)M * pr * qr);
+            L.dc = cal((int64_t)N * pc * qc);
+            L.mask_b = mal((int64_t)M * N);
+            L.rr = ral(N);
+            L.rc = ral(M);
+            put_real(L.rr, gram_diag_host(N, p->k_row, p->use_w, p->use_vc));
+            put_real(L.rc, gram_diag_host(M, p->k_col, p->use_w, p->use_vc));
+            P->total_elems += e;
+            P->sl.push_back(L);
+        }
+        // complex tables after the per-slice arrays
+        for (int s = 0; s < p->n_slices; ++s) {
+            SliceLayout& L = P->sl[s];
+            weights_host(L.N, wr, wi);
+            L.wr = put_cplx(wr, wi);
+            weights_host(L.M, wr, wi);
+            L.wc = put_cplx(wr, wi);
+            init_adjoint_host(L.N, p->k_row, p->use_w, p->use_vc, -p->d0 / p->beta, vr, vi);
+            L.vr = put_cplx(vr, vi);
+            init_adjoint_host(L.M, p->k_col, p->use_w, p->use_vc, -p->d0 / p->beta, vr, vi);
+            L.vc = put_cplx(vr, vi);
+        }
+    } else {
+        SliceLayout L{};
+        const int M = P->Ms[0], N = P->Ns[0], Lh = p->L;
+        L.M = M;
+        L.N = N;
+        const int64_t e = (int64_t)Lh * J * M * N;
+        L.yn = cal(e);
+        L.k = cal(e);
+        L.bp = cal(e);
+        L.be = cal(e);
+        L.xe = cal(e);
+        const int pp = N - p->k_row + 1, qp = p->k_row * J * V;
+        const int pe = Lh - p->k_col + 1, qe = p->k_col * J;
+        L.dp = cal((int64_t)M * Lh * pp * qp);
+        L.de = cal((int64_t)M * N * pe * qe);
+        L.mask_b = mal((int64_t)Lh * N);
+        L.rr = ral(N);
+        L.rc = ral(Lh);
+        put_real(L.rr, gram_diag_host(N, p->k_row, p->use_w, p->use_vc));
+        put_real(L.rc, gram_diag_host(Lh, p->k_col, false, false));
+        weights_host(N, wr, wi);
+        L.wr = put_cplx(wr, wi);
+        L.wc = L.wr;
+        init_adjoint_host(N, p->k_row, p->use_w, p->use_vc, -p->d0 / p->beta, vr, vi);
+        L.vr = put_cplx(vr, vi);
+        init_adjoint_host(Lh, p->k_col, false, false, -p->d0 / p->beta, vr, vi);
+        L.vc = put_cplx(vr, vi);
+        P->total_elems = e;
+        P->sl.push_back(L);
+    }
+    // the complex table lives at the end of the complex arena
+    const int64_t ctab_off = cal((int64_t)P->ctab.size() / 2 + 1);
+    for (auto& L : P->sl) {
+        L.wr += ctab_off;
+        L.wc += ctab_off;
+        L.vr += ctab_off;
+        L.vc += ctab_off;
+    }
+    // descriptors
+    if (p->model == SHLR_MODEL_PI) {
+        for (int s = 0; s < p->n_slices; ++s) {
+            const SliceLayout& L = P->sl[s];
+            const int M = L.M, N = L.N;
+            const int pr = N - p->k_row + 1, qr = p->k_row * J * V;
+            const int pc = M - p->k_col + 1, qc = p->k_col * J * V;
+            LRGroup g;
+            g.first = (int)P->descs.size();
+            g.count = M;
+            for (int mm = 0; mm < M; ++mm)
+                P->descs.push_back(make_desc(L.hr + (int64_t)mm * N, M * N, 1, L.br + (int64_t)mm * N, M * N, 1,
+                                             L.dr + (int64_t)mm * pr * qr, N, p->k_row, J, V, p->use_w, L.wr, thr_rc));
+            g.proto = P->descs[g.first];
+            P->groups.push_back(g);
+            g.first = (int)P->descs.size();
+            g.count = N;
+            for (int nn = 0; nn < N; ++nn)
+                P->descs.push_back(make_desc(L.hct + (int64_t)nn * M, N * M, 1, L.bct + (int64_t)nn * M, N * M, 1,
+                                             L.dc + (int64_t)nn * pc * qc, M, p->k_col, J, V, p->use_w, L.wc, thr_rc));
+            g.proto = P->descs[g.first];
+            P->groups.push_back(g);
+        }
+    } else {
+        const SliceLayout& L = P->sl[0];
+        const int M = L.M, N = L.N, Lh = p->L;
+        const int pp = N - p->k_row + 1, qp = p->k_row * J * V;
+        const int pe = Lh - p->k_col + 1, qe = p->k_col * J;
+        const int64_t LJN = (int64_t)Lh * J * N;
+        LRGroup g;
+        g.first = (int)P->descs.size();
+        g.count = M * Lh;
+        for (int mm = 0; mm < M; ++mm)
+            for (int l = 0; l < Lh; ++l) {
+                const int64_t o = mm * LJN + (int64_t)l * J * N;
+                P->descs.push_back(make_desc(L.k + o, N, 1, L.bp + o, N, 1,
+                                             L.dp + ((int64_t)mm * Lh + l) * pp * qp, N, p->k_row, J, V, p->use_w,
+                                             L.wr, thr_rc));
+            }
+        g.proto = P->descs[g.first];
+        P->groups.push_back(g);
+        g.first = (int)P->descs.size();
+        g.count = M * N;
+        for (int mm = 0; mm < M; ++mm)
+            for (int nn = 0; nn < N; ++nn) {
+                const int64_t o = mm * LJN + nn;
+                P->descs.push_back(make_desc(L.xe + o, N, J * N, L.be + o, N, J * N,
+                                             L.de + ((int64_t)mm * N + nn) * pe * qe, Lh, p->k_col, J, 1, 0, L.wr,
+                                             p->lambda2 / p->beta));
+            }
+        g.proto = P->descs[g.first];
+        P->groups.push_back(g);
+    }
+    for (auto& d : P->descs) P->s_max = std::max(P->s_max, lr_s(d));
+    int maxcount = 0;
+    for (auto& g : P->groups) maxcount = std::max(maxcount, g.count);
+    layout_slots(P, maxcount);
+    // workspace
+    size_t off = 0;
+    P->off_c = off;
+    P->bytes_c = (size_t)c * P->csize;
+    off = align256(off + P->bytes_c);
+    P->off_r = off;
+    P->bytes_r = (size_t)std::max<int64_t>(r, (int64_t)P->rtab.size()) * P->rsize;
+    off = align256(off + P->bytes_r);
+    P->off_m = off;
+    P->bytes_m = (size_t)m;
+    off = align256(off + P->bytes_m);
+    P->off_desc = off;
+    off = align256(off + P->descs.size() * sizeof(LRDesc));
+    P->off_g = off;
+    off = align256(off + (size_t)P->n_slots * P->g_stride * 16);
+    P->off_s = off;
+    off = align256(off + (size_t)P->n_slots * P->s_stride * P->csize);
+    P->off_scr = off;
+    off = align256(off + (size_t)P->n_slots * P->scr_stride * 8);
+    P->off_ranks = off;
+    off = align256(off + P->descs.size() * 4);
+    P->off_scal = off;   // scale (n_slices doubles), maxabs (n_slices u64), flags (u32), change (2 doubles per slice)
+    off = align256(off + (size_t)p->n_slices * 32 + 64);
+    P->off_spirit = off;
+    P->bytes_spirit = 0;
+    if (p->spirit_ksize > 0) {
+        int64_t pix = 0;
+        for (auto& L : P->sl) pix = std::max<int64_t>(pix, (int64_t)L.M * L.N);
+        // per-pixel (G-I)^H(G-I): J*J complex per pixel, plus PCG vectors (5 complex J*M*N) and scalars
+        int64_t emax = 0;
+        for (auto& L : P->sl) emax = std::max<int64_t>(emax, (int64_t)J * L.M * L.N);
+        P->bytes_spirit = align256((size_t)pix * J * J * P->csize) + 6 * align256((size_t)emax * P->csize) + 4096;
+    }
+    off = align256(off + P->bytes_spirit);
+    P->total = off;
+    P->scales.assign(p->n_slices, 1.0);
+    *out = P;
+    return SHLR_OK;
+}
+
+extern "C" void shlr_plan_destroy(shlr_plan* plan) {
+    if (!plan) return;
+    if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+    delete plan;
+}
+
+extern "C" shlr_status shlr_workspace_size(const shlr_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return fail(SHLR_E_INVALID_ARG, "NULL argument");
+    *bytes = plan->total;
+    return SHLR_OK;
+}
+
+template <typename R>
+static shlr_status upload_tables(shlr_plan* P) {
+    using C = cplx_t<R>;
+    std::vector<R> rt(P->rtab.begin(), P->rtab.end());
+    if (!rt.empty())
+        HIPCHK(hipMemcpyAsync(P->ws + P->off_r, rt.data(), rt.size() * sizeof(R), hipMemcpyHostToDevice, P->stream));
+    std::vector<C> ct(P->ctab.size() / 2);
+    for (size_t i = 0; i < ct.size(); ++i) {
+        ct[i].x = (R)P->ctab[2 * i];
+        ct[i].y = (R)P->ctab[2 * i + 1];
+    }
+    if (!ct.empty()) {
+        const int64_t off = P->sl[0].wr;  // first complex-table entry
+        HIPCHK(hipMemcpyAsync(P->ws + P->off_c + off * sizeof(C), ct.data(), ct.size() * sizeof(C),
+                              hipMemcpyHostToDevice, P->stream));
+    }
+    HIPCHK(hipMemcpyAsync(P->ws + P->off_desc, P->descs.data(), P->descs.size() * sizeof(LRDesc),
+                          hipMemcpyHostToDevice, P->stream));
+    HIPCHK(hipStreamSynchronize(P->stream));   // host vectors go out of scope
+    return SHLR_OK;
+}
+
+extern "C" shlr_status shlr_bind(shlr_plan* plan, void* ws_dev, size_t bytes, void* stream) {
+    if (!plan) return fail(SHLR_E_INVALID_ARG, "plan is NULL");
+    if (!ws_dev) return fail(SHLR_E_WORKSPACE, "workspace is NULL");
+    if (bytes < plan->total) return fail(SHLR_E_WORKSPACE, "workspace has %zu bytes, %zu needed", bytes, plan->total);
+    if (((uintptr_t)ws_dev) & 255) return fail(SHLR_E_WORKSPACE, "workspace must be 256-byte aligned");
+    plan->ws = (unsigned char*)ws_dev;
+    plan->stream = (hipStream_t)stream;
+    plan->bound = true;
+    plan->initialised = false;
+    plan->spirit_ready = false;
+    if (plan->graph_exec) {
+        (void)hipGraphExecDestroy(plan->graph_exec);
+        plan->graph_exec = nullptr;
+    }
+    if (plan->p.precision == SHLR_PREC_MIXED) return upload_tables<float>(plan);
+    return upload_tables<double>(plan);
+}
+
+// ---------------------------------------------------------------------------
+// iteration
+// ---------------------------------------------------------------------------
+
+template <typename R>
+struct Ptrs {
+    using C = cplx_t<R>;
+    C* c;
+    R* r;
+    uint8_t* m;
+    LRDesc* desc;
+    double2* g;
+    C* s;
+    double* scr;
+    int32_t* ranks;
+    double* scale;
+    unsigned long long* maxabs;
+    uint32_t* flags;
+    double* change;
+    explicit Ptrs(const shlr_plan* P) {
+        c = (C*)(P->ws + P->off_c);
+        r = (R*)(P->ws + P->off_r);
+        m = P->ws + P->off_m;
+        desc = (LRDesc*)(P->ws + P->off_desc);
+        g = (double2*)(P->ws + P->off_g);
+        s = (C*)(P->ws + P->off_s);
+        scr = (double*)(P->ws + P->off_scr);
+        ranks = (int32_t*)(P->ws + P->off_ranks);
+        unsigned char* sc = P->ws + P->off_scal;
+        const int S = P->p.n_slices;
+        scale = (double*)sc;
+        maxabs = (unsigned long long*)(sc + 8 * S);
+        change = (double*)(sc + 16 * S);
+        flags = (uint32_t*)(sc + 32 * S);
+    }
+};
+
+template <typename R>
+static shlr_status spirit_xupdate(shlr_plan* P, int si);
+
+static double ortol_for(const shlr_plan* P) { return P->p.precision == SHLR_PREC_MIXED ? 1e-5 : 1e-3; }
+
+template <typename R>
+static shlr_status run_lowrank_groups(shlr_plan* P, const std::vector<LRGroup>& groups, cplx_t<R>* hb, cplx_t<R>* db,
+                                      cplx_t<R>* bb, const cplx_t<R>* wtab, LRDesc* desc_dev, double2* G,
+                                      cplx_t<R>* S, double* scr, int32_t* ranks, uint32_t* flags, int n_slots,
+                                      int64_t g_stride, int64_t s_stride, int64_t scr_stride) {
+    const double ortol = ortol_for(P);
+    for (const LRGroup& g : groups) {
+        for (int c0 = 0; c0 < g.count; c0 += n_slots) {
+            const int cnt = std::min(n_slots, g.count - c0);
+            const int m0 = g.first + c0;
+            HIPCHK(launch_lift_gram<R>(P->stream, hb, db, wtab, desc_dev, g.proto, m0, cnt, G, g_stride, P->p.beta));
+            HIPCHK(launch_heig_svt<cplx_t<R>>(P->stream, desc_dev, m0, cnt, G, g_stride, S, s_stride, scr, scr_stride,
+                                              ranks, ortol, flags));
+            HIPCHK(launch_reproj<R>(P->stream, hb, db, bb, wtab, desc_dev, g.proto, m0, cnt, S, s_stride, P->p.beta,
+                                    P->p.tau));
+        }
+    }
+    return SHLR_OK;
+}
+
+template <typename R>
+static shlr_status iterate_once(shlr_plan* P, bool track_change) {
+    Ptrs<R> Q(P);
+    const shlr_params& p = P->p;
+    const int J = p.J;
+    if (track_change) HIPCHK(launch_zero_doubles(P->stream, Q.change, 2 * p.n_slices));
+    if (p.model == SHLR_MODEL_PI) {
+        for (int si = 0; si < p.n_slices; ++si) {
+            const SliceLayout& L = P->sl[si];
+            const int M = L.M, N = L.N;
+            const int64_t MN = (int64_t)M * N;
+            // A = F_m(B_row): lines (j, n) along m
+            LineAddr col{0, MN, 1, N, N};
+            HIPCHK(launch_fft_lines<R>(P->stream, Q.c + L.br, Q.c + L.a, col, col, M, J * N, 0, 1.0 / sqrt((double)M)));
+            if (p.spirit_ksize > 0 && p.lambda1 > 0) {
+                STCHK(spirit_xupdate<R>(P, si));
+            } else {
+                XupdRows x;
+                x.n = N;
+                x.n1 = J;
+                x.n0 = M;
+                x.n_rows = J * M;
+                x.rc_digit = 0;
+                x.bo = RowAddr{0, MN, 1, M};
+                x.a = RowAddr{0, MN, N, 1};
+                x.y = x.a;
+                x.k = x.a;
+                x.out = RowAddr{0, MN, 1, M};
+                x.msk = RowAddr{0, 0, N, 1};
+                x.rr_off = L.rr;
+                x.rc_off = L.rc;
+                HIPCHK(launch_xupd_rows<R>(P->stream, Q.c + L.bct, Q.c + L.a, Q.c + L.yn, Q.c + L.k, Q.c + L.hct,
+                                           Q.m + L.mask_b, Q.r, x, p.lambda, p.beta, p.hard_dc,
+                                           track_change ? Q.change + 2 * si : nullptr));
+            }
+            // H_row = F_m^-1(K)
+            HIPCHK(launch_fft_lines<R>(P->stream, Q.c + L.k, Q.c + L.hr, col, col, M, J * N, 1, 1.0 / sqrt((double)M)));
+        }
+    } else {
+        const SliceLayout& L = P->sl[0];
+        const int M = L.M, N = L.N, Lh = p.L;
+        XupdRows x;
+        x.n = N;
+        x.n1 = Lh;
+        x.n0 = J;
+        x.n_rows = M * Lh * J;
+        x.rc_digit = 1;
+        x.bo = RowAddr{(int64_t)Lh * J * N, (int64_t)J * N, N, 1};
+        x.a = x.bo;
+        x.y = x.bo;
+        x.k = x.bo;
+        x.out = x.bo;
+        x.msk = RowAddr{0, N, 0, 1};
+        x.rr_off = L.rr;
+        x.rc_off = L.rc;
+        HIPCHK(launch_xupd_rows<R>(P->stream, Q.c + L.be, Q.c + L.bp, Q.c + L.yn, Q.c + L.k, Q.c + L.xe,
+                                   Q.m + L.mask_b, Q.r, x, p.lambda, p.beta, p.hard_dc,
+                                   track_change ? Q.change : nullptr));
+    }
+    STCHK(run_lowrank_groups<R>(P, P->groups, Q.c, Q.c, Q.c, Q.c, Q.desc, Q.g, Q.s, Q.scr, Q.ranks, Q.flags,
+                                P->n_slots, P->g_stride, P->s_stride, P->scr_stride));
+    return SHLR_OK;
+}
+
+template <typename R>
+static shlr_status init_impl(shlr_plan* P, const void* y_dev, const uint8_t* mask_dev) {
+    using C = cplx_t<R>;
+    Ptrs<R> Q(P);
+    const shlr_params& p = P->p;
+    const int J = p.J;
+    const C* Y = (const C*)y_dev;
+    HIPCHK(hipMemsetAsync(P->ws + P->off_scal, 0, (size_t)p.n_slices * 32 + 64, P->stream));
+    if (p.model == SHLR_MODEL_PI) {
+        int64_t yoff = 0, moff = 0;
+        for (int si = 0; si < p.n_slices; ++si) {
+            const SliceLayout& L = P->sl[si];
+            const int64_t e = (int64_t)J * L.M * L.N;
+            HIPCHK(launch_maxabs<R>(P->stream, Y + yoff, e, Q.maxabs + si, Q.flags));
+            yoff += e;
+            moff += (int64_t)L.M * L.N;
+        }
+        std::vector<unsigned long long> mx(p.n_slices);
+        HIPCHK(hipMemcpyAsync(mx.data(), Q.maxabs, mx.size() * 8, hipMemcpyDeviceToHost, P->stream));
+        uint32_t fl = 0;
+        HIPCHK(hipMemcpyAsync(&fl, Q.flags, 4, hipMemcpyDeviceToHost, P->stream));
+        HIPCHK(hipStreamSynchronize(P->stream));
+        if (fl & 1u) return fail(SHLR_E_NONFINITE, "Y holds NaN or Inf");
+        for (int si = 0; si < p.n_slices; ++si) {
+            double v;
+            memcpy(&v, &mx[si], 8);
+            P->scales[si] = (p.normalize && v > 0) ? v : 1.0;
+        }
+        HIPCHK(hipMemcpyAsync(Q.scale, P->scales.data(), 8 * p.n_slices, hipMemcpyHostToDevice, P->stream));
+        yoff = 0;
+        moff = 0;
+        for (int si = 0; si < p.n_slices; ++si) {
+            const SliceLayout& L = P->sl[si];
+            const int M = L.M, N = L.N;
+            const int64_t e = (int64_t)J * M * N;
+            HIPCHK(launch_scale_copy<R>(P->stream, Y + yoff, Q.c + L.yn, e, Q.scale + si, 1));
+            HIPCHK(hipMemcpyAsync(Q.c + L.k, Q.c + L.yn, e * sizeof(C), hipMemcpyDeviceToDevice, P->stream));
+            HIPCHK(hipMemcpyAsync(Q.m + L.mask_b, mask_dev + moff, (size_t)M * N, hipMemcpyDeviceToDevice, P->stream));
+            const int V = p.use_vc ? 2 : 1;
+            const int64_t dr = (int64_t)M * (N - p.k_row + 1) * p.k_row * J * V;
+            const int64_t dc = (int64_t)N * (M - p.k_col + 1) * p.k_col * J * V;
+            HIPCHK(launch_fill_const<R>(P->stream, Q.c + L.dr, dr, p.d0, 0.0));
+            HIPCHK(launch_fill_const<R>(P->stream, Q.c + L.dc, dc, p.d0, 0.0));
+            HIPCHK(launch_fill_pattern<R>(P->stream, Q.c + L.br, e, Q.c + L.vr, 1, N));
+            HIPCHK(launch_fill_pattern<R>(P->stream, Q.c + L.bct, e, Q.c + L.vc, 1, M));
+            // Eq. 15 is singular at the k-space centre (W vanishes there) unless it is sampled
+            uint8_t centre = 0;
+            HIPCHK(hipMemcpyAsync(&centre, mask_dev + moff + (int64_t)(M / 2) * N + N / 2, 1, hipMemcpyDeviceToHost,
+                                  P->stream));
+            HIPCHK(hipStreamSynchronize(P->stream));
+            const double rc = P->rtab[L.rr + N / 2] + P->rtab[L.rc + M / 2];
+            if (!(rc > 0) && !centre)
+                return fail(SHLR_E_SINGULAR, "slice %d: the k-space centre is not sampled and the lifted terms vanish there", si);
+            yoff += e;
+            moff += (int64_t)M * N;
+        }
+    } else {
+        const SliceLayout& L = P->sl[0];
+        const int M = L.M, N = L.N, Lh = p.L;
+        const int64_t e = (int64_t)Lh * J * M * N;
+        HIPCHK(launch_maxabs<R>(P->stream, Y, e, Q.maxabs, Q.flags));
+        unsigned long long mx = 0;
+        uint32_t fl = 0;
+        HIPCHK(hipMemcpyAsync(&mx, Q.maxabs, 8, hipMemcpyDeviceToHost, P->stream));
+        HIPCHK(hipMemcpyAsync(&fl, Q.flags, 4, hipMemcpyDeviceToHost, P->stream));
+        HIPCHK(hipStreamSynchronize(P->stream));
+        if (fl & 1u) return fail(SHLR_E_NONFINITE, "Y holds NaN or Inf");
+        double v;
+        memcpy(&v, &mx, 8);
+        P->scales[0] = (p.normalize && v > 0) ? v : 1.0;
+        HIPCHK(hipMemcpyAsync(Q.scale, P->scales.data(), 8, hipMemcpyHostToDevice, P->stream));
+        // inverse DFT along FE, into [M][L][J][N], normalised
+        LineAddr ia{0, (int64_t)M * N, 1, N, N};
+        LineAddr oa{0, N, 1, N, (int32_t)((int64_t)Lh * J * N)};
+        HIPCHK(launch_fft_lines<R>(P->stream, Y, Q.c + L.yn, ia, oa, M, Lh * J * N, 1,
+                                   1.0 / (sqrt((double)M) * P->scales[0])));
+        HIPCHK(hipMemcpyAsync(Q.c + L.k, Q.c + L.yn, e * sizeof(C), hipMemcpyDeviceToDevice, P->stream));
+        HIPCHK(hipMemcpyAsync(Q.m + L.mask_b, mask_dev, (size_t)Lh * N, hipMemcpyDeviceToDevice, P->stream));
+        const int V = p.use_vc ? 2 : 1;
+        const int64_t dp = (int64_t)M * Lh * (N - p.k_row + 1) * p.k_row * J * V;
+        const int64_t de = (int64_t)M * N * (Lh - p.k_col + 1) * p.k_col * J;
+        HIPCHK(launch_fill_const<R>(P->stream, Q.c + L.dp, dp, p.d0, 0.0));
+        HIPCHK(launch_fill_const<R>(P->stream, Q.c + L.de, de, p.d0, 0.0));
+        HIPCHK(launch_fill_pattern<R>(P->stream, Q.c + L.bp, e, Q.c + L.vr, 1, N));
+        HIPCHK(launch_fill_pattern<R>(P->stream, Q.c + L.be, e, Q.c + L.vc, (int64_t)J * N, Lh));
+    }
+    HIPCHK(hipStreamSynchronize(P->stream));
+    P->initialised = true;
+    P->iters_total = 0;
+    return SHLR_OK;
+}
+
+extern "C" shlr_status shlr_init(shlr_plan* plan, const void* y_dev, const uint8_t* mask_dev) {
+    if (!plan) return fail(SHLR_E_INVALID_ARG, "plan is NULL");
+    if (!plan->bound) return fail(SHLR_E_WORKSPACE, "no workspace bound");
+    if (!y_dev || !mask_dev) return fail(SHLR_E_INVALID_ARG, "NULL data pointer");
+    if (plan->p.precision == SHLR_PREC_MIXED) return init_impl<float>(plan, y_dev, mask_dev);
+    return init_impl<double>(plan, y_dev, mask_dev);
+}
+
+template <typename R>
+static shlr_status iterate_impl(shlr_plan* P, int n, shlr_info* info) {
+    Ptrs<R> Q(P);
+    const bool track = P->p.tol > 0;
+    int done = 0;
+    bool conv = false;
+    double last = 0;
+    for (int it = 0; it < n; ++it) {
+        STCHK(iterate_once<R>(P, track));
+        ++done;
+        if (track) {
+            std::vector<double> ch(2 * P->p.n_slices);
+            HIPCHK(hipMemcpyAsync(ch.data(), Q.change, ch.size() * 8, hipMemcpyDeviceToHost, P->stream));
+            HIPCHK(hipStreamSynchronize(P->stream));
+            double worst = 0;
+            for (int s = 0; s < P->p.n_slices; ++s)
+                worst = std::max(worst, ch[2 * s + 1] > 0 ? ch[2 * s] / ch[2 * s + 1] : INFINITY);
+            last = worst;
+            if (worst < P->p.tol) {
+                conv = true;
+                break;
+            }
+        }
+    }
+    P->iters_total += done;
+    if (info) {
+        uint32_t fl = 0;
+        HIPCHK(hipMemcpyAsync(&fl, Q.flags, 4, hipMemcpyDeviceToHost, P->stream));
+        HIPCHK(hipStreamSynchronize(P->stream));
+        info->iters_done = done;
+        info->converged = conv;
+        info->rel_change = last;
+        info->scale = P->scales[0];
+        info->device_flags = fl;
+        if (fl & 1u) return fail(SHLR_E_NONFINITE, "a non-finite value was met during the iterations");
+    }
+    return SHLR_OK;
+}
+
+extern "C" shlr_status shlr_iterate(shlr_plan* plan, int32_t n, shlr_info* info) {
+    if (!plan) return fail(SHLR_E_INVALID_ARG, "plan is NULL");
+    if (!plan->initialised) return fail(SHLR_E_STATE, "shlr_init must come first");
+    if (n < 0) return fail(SHLR_E_INVALID_ARG, "n must be >= 0");
+    if (plan->p.spirit_ksize > 0 && plan->p.lambda1 > 0 && !plan->spirit_ready)
+        return fail(SHLR_E_STATE, "the SPIRiT kernel is not set (shlr_set_spirit_kernel / shlr_calibrate_spirit)");
+    if (plan->p.precision == SHLR_PREC_MIXED) return iterate_impl<float>(plan, n, info);
+    return iterate_impl<double>(plan, n, info);
+}
+
+template <typename R>
+static shlr_status build_graph(shlr_plan* P) {
+    if (!P->cap_stream) HIPCHK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = P->stream;
+    P->stream = P->cap_stream;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        P->stream = user;
+        return fail(SHLR_E_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    shlr_status st = iterate_once<R>(P, false);
+    e = hipStreamEndCapture(P->cap_stream, &graph);
+    P->stream = user;
+    if (st != SHLR_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(SHLR_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&P->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        P->graph_exec = nullptr;
+        return fail(SHLR_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    return SHLR_OK;
+}
+
+extern "C" shlr_status shlr_iterate_graph(shlr_plan* plan, int32_t n, shlr_info* info) {
+    if (!plan) return fail(SHLR_E_INVALID_ARG, "plan is NULL");
+    if (!plan->initialised) return fail(SHLR_E_STATE, "shlr_init must come first");
+    if (n < 0) return fail(SHLR_E_INVALID_ARG, "n must be >= 0");
+    if (plan->p.spirit_ksize > 0 && plan->p.lambda1 > 0 && !plan->spirit_ready)
+        return fail(SHLR_E_STATE, "the SPIRiT kernel is not set");
+    if (!plan->graph_exec) {
+        if (plan->p.precision == SHLR_PREC_MIXED) STCHK(build_graph<float>(plan));
+        else STCHK(build_graph<double>(plan));
+    }
+    for (int i = 0; i < n; ++i) HIPCHK(hipGraphLaunch(plan->graph_exec, plan->stream));
+    plan->iters_total += n;
+    if (info) {
+        uint32_t fl = 0;
+        HIPCHK(hipMemcpyAsync(&fl, plan->ws + plan->off_scal + 32 * plan->p.n_slices, 4, hipMemcpyDeviceToHost,
+                              plan->stream));
+        HIPCHK(hipStreamSynchronize(plan->stream));
+        info->iters_done = n;
+        info->converged = 0;
+        info->rel_change = 0;
+        info->scale = plan->scales[0];
+        info->device_flags = fl;
+        if (fl & 1u) return fail(SHLR_E_NONFINITE, "a non-finite value was met during the iterations");
+    }
+    return SHLR_OK;
+}
+
+template <typename R>
+static shlr_status get_impl(const shlr_plan* P, void* out) {
+    using C = cplx_t<R>;
+    Ptrs<R> Q(P);
+    const shlr_params& p = P->p;
+    const int J = p.J;
+    C* O = (C*)out;
+    if (p.model == SHLR_MODEL_PI) {
+        int64_t off = 0;
+        for (int si = 0; si < p.n_slices; ++si) {
+            const SliceLayout& L = P->sl[si];
+            const int64_t e = (int64_t)J * L.M * L.N;
+            HIPCHK(launch_scale_copy<R>(P->stream, Q.c + L.k, O + off, e, Q.scale + si, 0));
+            off += e;
+        }
+    } else {
+        const SliceLayout& L = P->sl[0];
+        const int M = L.M, N = L.N, Lh = p.L;
+        LineAddr ia{0, N, 1, N, (int32_t)((int64_t)Lh * J * N)};
+        LineAddr oa{0, (int64_t)M * N, 1, N, N};
+        HIPCHK(launch_fft_lines<R>(P->stream, Q.c + L.k, O, ia, oa, M, Lh * J * N, 0,
+                                   P->scales[0] / sqrt((double)M)));
+    }
+    HIPCHK(hipStreamSynchronize(P->stream));
+    return SHLR_OK;
+}
+
+extern "C" shlr_status shlr_get_kspace(const shlr_plan* plan, void* k_out_dev) {
+    if (!plan) return fail(SHLR_E_INVALID_ARG, "plan is NULL");
+    if (!plan->initialised) return fail(SHLR_E_STATE, "shlr_init must come first");
+    if (!k_out_dev) return fail(SHLR_E_INVALID_ARG, "k_out is NULL");
+    if (plan->p.precision == SHLR_PREC_MIXED) return get_impl<float>(plan, k_out_dev);
+    return get_impl<double>(plan, k_out_dev);
+}
+
+extern "C" shlr_status shlr_reconstruct(shlr_plan* plan, const void* y_dev, const uint8_t* mask_dev, void* k_out_dev,
+                                        shlr_info* info) {
+    STCHK(shlr_init(plan, y_dev, mask_dev));
+    if (plan->p.spirit_ksize > 0 && plan->p.lambda1 > 0 && !plan->spirit_ready)
+        return fail(SHLR_E_STATE, "the SPIRiT kernel is not set");
+    STCHK(shlr_iterate(plan, plan->p.max_iter, info));
+    return shlr_get_kspace(plan, k_out_dev);
+}
+
+// ---------------------------------------------------------------------------
+// stage entry points
+// ---------------------------------------------------------------------------
+
+extern "C" shlr_status shlr_fft_lines(int32_t precision, int32_t n, int32_t n_lines, int32_t inverse,
+                                      const void* in_dev, void* out_dev, void* stream) {
+    if (precision != SHLR_PREC_MIXED && precision != SHLR_PREC_FP64) return fail(SHLR_E_INVALID_ARG, "bad precision");
+    if (n < 1 || n > 4096) return fail(SHLR_E_INVALID_ARG, "n must be in [1, 4096]");
+    if (n_lines < 0) return fail(SHLR_E_INVALID_ARG, "n_lines must be >= 0");
+    if (n_lines == 0) return SHLR_OK;
+    if (!in_dev || !out_dev) return fail(SHLR_E_INVALID_ARG, "NULL pointer");
+    LineAddr a{0, n, 0, 1, 1};
+    const double sc = 1.0 / sqrt((double)n);
+    if (precision == SHLR_PREC_MIXED)
+        HIPCHK(launch_fft_lines<float>((hipStream_t)stream, (const float2*)in_dev, (float2*)out_dev, a, a, n, n_lines,
+                                       inverse, sc));
+    else
+        HIPCHK(launch_fft_lines<double>((hipStream_t)stream, (const double2*)in_dev, (double2*)out_dev, a, a, n,
+                                        n_lines, inverse, sc));
+    return SHLR_OK;
+}
+
+struct LRLayout {
+    size_t off_desc, off_g, off_s, off_scr, off_w, off_flags, total;
+    int slots, s;
+    int64_t gst, sst, scst;
+};
+
+static shlr_status lr_layout(int32_t precision, int32_t n_mat, int32_t J, int32_t n, int32_t k, int32_t use_vc,
+                             LRLayout* L) {
+    if (precision != SHLR_PREC_MIXED && precision != SHLR_PREC_FP64) return fail(SHLR_E_INVALID_ARG, "bad precision");
+    if (n_mat < 0 || J < 1 || n < 1 || k < 1 || k > n) return fail(SHLR_E_INVALID_ARG, "bad shape");
+    LRDesc d = make_desc(0, 0, 0, 0, 0, 0, 0, n, k, J, use_vc ? 2 : 1, 0, 0, 0.0);
+    const int s = lr_s(d);
+    if (s > 320) return fail(SHLR_E_UNSUPPORTED, "min(p, q) > 320");
+    if (lr_l(d) > 4096) return fail(SHLR_E_UNSUPPORTED, "max(p, q) > 4096");
+    const int cs = precision == SHLR_PREC_MIXED ? 8 : 16;
+    L->s = s;
+    L->gst = (int64_t)s * s;
+    L->sst = (int64_t)s * s;
+    L->scst = eig_scratch_doubles(s);
+    const size_t per = L->gst * 16 + L->sst * cs + L->scst * 8 + 3 * 256;
+    L->slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::max(n_mat, 1), SLOT_BUDGET / per));
+    size_t off = 0;
+    L->off_desc = off;
+    off = align256(off + (size_t)std::max(n_mat, 1) * sizeof(LRDesc));
+    L->off_g = off;
+    off = align256(off + (size_t)L->slots * L->gst * 16);
+    L->off_s = off;
+    off = align256(off + (size_t)L->slots * L->sst * cs);
+    L->off_scr = off;
+    off = align256(off + (size_t)L->slots * L->scst * 8);
+    L->off_w = off;
+    off = align256(off + (size_t)n * cs);
+    L->off_flags = off;
+    off = align256(off + 256);
+    L->total = off;
+    return SHLR_OK;
+}
+
+extern "C" shlr_status shlr_lowrank_workspace_size(int32_t precision, int32_t n_mat, int32_t J, int32_t n, int32_t k,
+                                                   int32_t use_vc, size_t* bytes) {
+    if (!bytes) return fail(SHLR_E_INVALID_ARG, "bytes is NULL");
+    LRLayout L;
+    STCHK(lr_layout(precision, n_mat, J, n, k, use_vc, &L));
+    *bytes = L.total;
+    return SHLR_OK;
+}
+
+template <typename R>
+static shlr_status lowrank_impl(int32_t n_mat, int32_t J, int32_t n, int32_t k, int32_t use_vc, int32_t use_w,
+                                double beta, double tau, double thr, const void* h_dev, void* d_dev, void* b_dev,
+                                int32_t* ranks_dev, unsigned char* ws, const LRLayout& L, hipStream_t st) {
+    using C = cplx_t<R>;
+    const int V = use_vc ? 2 : 1;
+    const int p = n - k + 1, q = k * J * V;
+    std::vector<LRDesc> descs(n_mat);
+    for (int i = 0; i < n_mat; ++i)
+        descs[i] = make_desc((int64_t)i * J * n, n, 1, (int64_t)i * J * n, n, 1, (int64_t)i * p * q, n, k, J, V, use_w,
+                             0, thr);
+    std::vector<double> wr, wi;
+    weights_host(n, wr, wi);
+    std::vector<C> w(n);
+    for (int i = 0; i < n; ++i) {
+        w[i].x = (R)wr[i];
+        w[i].y = (R)wi[i];
+    }
+    HIPCHK(hipMemcpyAsync(ws + L.off_desc, descs.data(), descs.size() * sizeof(LRDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws + L.off_w, w.data(), w.size() * sizeof(C), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(ws + L.off_flags, 0, 4, st));
+    LRGroup g;
+    g.first = 0;
+    g.count = n_mat;
+    g.proto = descs[0];
+    shlr_plan tmp;
+    tmp.p.beta = beta;
+    tmp.p.tau = tau;
+    tmp.p.precision = sizeof(R) == 4 ? SHLR_PREC_MIXED : SHLR_PREC_FP64;
+    tmp.stream = st;
+    STCHK(run_lowrank_groups<R>(&tmp, std::vector<LRGroup>{g}, (C*)h_dev, (C*)d_dev, (C*)b_dev,
+                                (const C*)(ws + L.off_w), (LRDesc*)(ws + L.off_desc), (double2*)(ws + L.off_g),
+                                (C*)(ws + L.off_s), (double*)(ws + L.off_scr), ranks_dev,
+                                (uint32_t*)(ws + L.off_flags), L.slots, L.gst, L.sst, L.scst));
+    HIPCHK(hipStreamSynchronize(st));   // host descriptor vectors go out of scope
+    return SHLR_OK;
+}
+
+extern "C" shlr_status shlr_lowrank_lines(int32_t precision, int32_t n_mat, int32_t J, int32_t n, int32_t k,
+                                          int32_t use_vc, int32_t use_w, double beta, double tau, double thr,
+                                          const void* h_dev, void* d_dev, void* b_dev, int32_t* ranks_dev,
+                                          void* ws_dev, size_t ws_bytes, void* stream) {
+    LRLayout L;
+    STCHK(lr_layout(precision, n_mat, J, n, k, use_vc, &L));
+    if (n_mat == 0) return SHLR_OK;
+    if (!(beta > 0) || !(tau > 0) || !(thr >= 0)) return fail(SHLR_E_INVALID_ARG, "beta, tau > 0 and thr >= 0 required");
+    if (!h_dev || !d_dev || !b_dev) return fail(SHLR_E_INVALID_ARG, "NULL data pointer");
+    if (!ws_dev || ws_bytes < L.total) return fail(SHLR_E_WORKSPACE, "workspace too small (%zu < %zu)", ws_bytes, L.total);
+    if (((uintptr_t)ws_dev) & 255) return fail(SHLR_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (precision == SHLR_PREC_MIXED)
+        return lowrank_impl<float>(n_mat, J, n, k, use_vc, use_w, beta, tau, thr, h_dev, d_dev, b_dev, ranks_dev,
+                                   (unsigned char*)ws_dev, L, (hipStream_t)stream);
+    return lowrank_impl<double>(n_mat, J, n, k, use_vc, use_w, beta, tau, thr, h_dev, d_dev, b_dev, ranks_dev,
+                                (unsigned char*)ws_dev, L, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// SPIRiT (Eq. 3): set / calibrate the kernel; X-update by PCG
+// ---------------------------------------------------------------------------
+#include "spirit_host.inc"

@@ -1,0 +1,72 @@
+// Launchers of the SHLR kernels (host side) and the structs they take.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace shlr {
+
+constexpr int FFT_MAX_STAGES = 24;
+
+struct FftPlan {
+    int n;
+    int nst;
+    int radix[FFT_MAX_STAGES];
+};
+
+// line g -> g1 = g / n0, g0 = g % n0; element t at base + g1*s1 + g0*s0 + t*es
+struct LineAddr {
+    int64_t base, s1, s0;
+    int32_t n0, es;
+};
+
+// row g -> digits (d2, d1, d0); element i at d2*s2 + d1*s1 + d0*s0 + i*es
+struct RowAddr {
+    int64_t s2, s1, s0;
+    int32_t es;
+};
+
+struct XupdRows {
+    int n, n1, n0, n_rows;
+    int rc_digit;                   // which digit indexes the rc table
+    RowAddr bo, a, y, k, out, msk;  // msk counts bytes
+    int64_t rr_off, rc_off;         // offsets into the real table
+};
+
+FftPlan make_fft_plan(int n);
+
+template <typename R>
+hipError_t launch_fft_lines(hipStream_t st, const cplx_t<R>* in, cplx_t<R>* out, const LineAddr& ia,
+                            const LineAddr& oa, int n, int n_lines, int inverse, double scale);
+template <typename R>
+hipError_t launch_xupd_rows(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>* a, const cplx_t<R>* y,
+                            cplx_t<R>* k, cplx_t<R>* out, const uint8_t* m, const R* rtab, const XupdRows& x,
+                            double lam, double beta, int hard_dc, double* change_acc);
+template <typename R>
+hipError_t launch_scale_copy(hipStream_t st, const cplx_t<R>* in, cplx_t<R>* out, int64_t count,
+                             const double* scale_ptr, int invert);
+template <typename R>
+hipError_t launch_fill_pattern(hipStream_t st, cplx_t<R>* out, int64_t count, const cplx_t<R>* table, int64_t div,
+                               int64_t mod);
+template <typename R>
+hipError_t launch_fill_const(hipStream_t st, cplx_t<R>* out, int64_t count, double re, double im);
+template <typename R>
+hipError_t launch_maxabs(hipStream_t st, const cplx_t<R>* in, int64_t count, unsigned long long* out, uint32_t* flags);
+hipError_t launch_zero_doubles(hipStream_t st, double* p, int count);
+
+template <typename R>
+hipError_t launch_lift_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* wtab,
+                            const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, double2* Gs,
+                            int64_t g_stride, double beta);
+template <typename R>
+hipError_t launch_reproj(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cplx_t<R>* bb, const cplx_t<R>* wtab,
+                         const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, const cplx_t<R>* Ss,
+                         int64_t s_stride, double beta, double tau);
+template <typename OC>
+hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
+                           OC* Ss, int64_t s_stride, double* scr, int64_t scr_stride, int32_t* ranks,
+                           double ortol_rel, uint32_t* flags);
+
+}  // namespace shlr

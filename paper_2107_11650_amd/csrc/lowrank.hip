@@ -1,0 +1,452 @@
+// Lift + Gram and reprojection + multiplier + adjoint-lift kernels (gfx950).
+//
+// One lifted matrix per line (Eq. 2 / Eq. 4 of the paper):
+//   T[a][c] = w[a+b] * u_{v,j}[a+b] + D[a][c] / beta,  c = (v*J + j)*k + b,
+//   u_{0,j} = h_j (the line of coil j) and u_{1,j} = h_j^dagger (virtual coils).
+// T is never stored in HBM: chunks of it are rebuilt in LDS from the line
+// (kept in LDS) and the multiplier D (streamed from HBM).
+//
+// The SVT of Eq. 16 is computed on the smaller side s of T through its Gram
+// matrix G = A^H A, with A = T (q <= p) or A = T^H (p < q), A of size l x s:
+//   k_lift_gram : G = A^H A on the matrix cores (FP32 or FP64 MFMA 16x16x4),
+//   (k_heig_svt in eig.hip: S = V f(Lambda) V^H in FP64),
+//   k_reproj    : Y = A S; Z = Y (side 0) or Y^H (side 1); then
+//                 D' = D + tau (lift - Z)   (Eq. 13)
+//                 b  = lift^*(Z - D'/beta)  (Eq. 15 right-hand-side term)
+// The adjoint lift sums anti-diagonals in a fixed order (no atomics), so the
+// results are bitwise reproducible.
+#include "common.h"
+
+namespace shlr {
+
+constexpr int LR_THREADS = 512;     // 8 waves
+constexpr int LR_WAVES = LR_THREADS / 64;
+
+// Build the lifted line table u[v][j][i] = w[i] * (v == 0 ? h_j[i] : conj(h_j[flip(i)]))
+template <typename R>
+__device__ inline void load_line_table(cplx_t<R>* U, const cplx_t<R>* hb, const cplx_t<R>* wtab,
+                                       const LRDesc& d, int tid, int nth) {
+    using C = cplx_t<R>;
+    const int n = d.n, J = d.J, V = d.V;
+    const int c = n / 2;
+    for (int e = tid; e < V * J * n; e += nth) {
+        int i = e % n;
+        int blk = e / n;
+        int v = blk / J, j = blk % J;
+        C h;
+        if (v == 0) {
+            h = hb[d.h_off + (int64_t)j * d.h_cs + (int64_t)i * d.h_es];
+        } else {
+            int fi = (2 * c - i) % n;
+            if (fi < 0) fi += n;
+            h = cconj(hb[d.h_off + (int64_t)j * d.h_cs + (int64_t)fi * d.h_es]);
+        }
+        if (d.use_w) h = cmul(wtab[d.w_off + i], h);
+        U[e] = h;
+    }
+}
+
+// Value of T (without the D term) at (a, col).
+template <typename C>
+__device__ inline C lift_val(const C* U, int n, int k, int a, int col) {
+    int blk = col / k;
+    int b = col - blk * k;
+    return U[blk * n + a + b];
+}
+
+// ---------------------------------------------------------------------------
+// Stage a chunk of A rows [r0, r0 + KC) into LDS as split real/imag planes,
+// zero padded to s_pad columns and KC rows.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ inline void stage_A_chunk(R* Ar, R* Ai, int ldA, const cplx_t<R>* U, const cplx_t<R>* Dm,
+                                     const LRDesc& d, R inv_beta, int r0, int KC, int s_pad, int tid, int nth) {
+    using C = cplx_t<R>;
+    const int p = lr_p(d), q = lr_q(d), side = lr_side(d);
+    const int s = side == 0 ? q : p;
+    const int l = side == 0 ? p : q;
+    const int total = KC * s_pad;
+    if (side == 0) {
+        for (int e = tid; e < total; e += nth) {
+            int r = e / s_pad, cidx = e - r * s_pad;
+            int a = r0 + r;
+            R re = 0, im = 0;
+            if (a < l && cidx < s) {
+                C dv = Dm[(int64_t)a * q + cidx];
+                C lv = lift_val(U, d.n, d.k, a, cidx);
+                re = lv.x + dv.x * inv_beta;
+                im = lv.y + dv.y * inv_beta;
+            }
+            Ar[r * ldA + cidx] = re;
+            Ai[r * ldA + cidx] = im;
+        }
+    } else {
+        // A[r][c] = conj(T[c][r]): rows of A are columns of T; read D with r fastest.
+        for (int e = tid; e < total; e += nth) {
+            int cidx = e / KC, r = e - cidx * KC;
+            int col = r0 + r;
+            R re = 0, im = 0;
+            if (col < l && cidx < s) {
+                C dv = Dm[(int64_t)cidx * q + col];
+                C lv = lift_val(U, d.n, d.k, cidx, col);
+                re = lv.x + dv.x * inv_beta;
+                im = -(lv.y + dv.y * inv_beta);
+            }
+            Ar[r * ldA + cidx] = re;
+            Ai[r * ldA + cidx] = im;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_lift_gram
+//   grid.x: matrices of the chunk; grid.y: groups of 8 "units".
+//   The upper-triangular 16x16 tiles of G are grouped into units: the pair of
+//   tile rows (I, nt-1-I), or the middle row alone, which balances the waves.
+//   Each wave owns one unit (<= nt + 1 tiles) for the whole l loop.
+// ---------------------------------------------------------------------------
+template <typename R, int MAXT>
+__global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __restrict__ hb,
+                                                          const cplx_t<R>* __restrict__ db,
+                                                          const cplx_t<R>* __restrict__ wtab,
+                                                          const LRDesc* __restrict__ descs, int m0,
+                                                          double2* __restrict__ Gs, int64_t g_stride,
+                                                          R inv_beta, int KC) {
+    using C = cplx_t<R>;
+    using A4 = acc4_t<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const LRDesc d = descs[m0 + blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int s = lr_s(d), l = lr_l(d);
+    const int nt = (s + 15) / 16;
+    const int s_pad = nt * 16;
+    const int ldA = s_pad + 4;
+    C* U = reinterpret_cast<C*>(smem_raw);
+    const int utab = d.V * d.J * d.n;
+    R* Ar = reinterpret_cast<R*>(U + utab);
+    R* Ai = Ar + KC * ldA;
+
+    // unit of this wave
+    const int n_units = (nt + 1) / 2;
+    const int unit = blockIdx.y * LR_WAVES + wave;
+    const bool active = unit < n_units;
+    int I1 = unit, I2 = nt - 1 - unit;
+    if (I2 == I1) I2 = -1;  // middle row alone
+    const int cnt1 = active ? nt - I1 : 0;
+    const int cnt2 = (active && I2 >= 0) ? nt - I2 : 0;
+    const int count = cnt1 + cnt2;
+
+    A4 accR[MAXT], accI[MAXT];
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+        accR[t] = A4{0, 0, 0, 0};
+        accI[t] = A4{0, 0, 0, 0};
+    }
+
+    load_line_table<R>(U, hb, wtab, d, tid, LR_THREADS);
+    const C* Dm = db + d.d_off;
+    const int li = lane & 15, lk = lane >> 4;
+
+    for (int r0 = 0; r0 < l; r0 += KC) {
+        __syncthreads();
+        stage_A_chunk<R>(Ar, Ai, ldA, U, Dm, d, inv_beta, r0, KC, s_pad, tid, LR_THREADS);
+        __syncthreads();
+        if (!active) continue;
+        for (int kk = 0; kk < KC; kk += 4) {
+            const int row = (kk + lk) * ldA + li;
+            const R a1r = Ar[row + I1 * 16], a1i = Ai[row + I1 * 16];
+            R a2r = 0, a2i = 0;
+            if (I2 >= 0) { a2r = Ar[row + I2 * 16]; a2i = Ai[row + I2 * 16]; }
+#pragma unroll
+            for (int t = 0; t < MAXT; ++t) {
+                if (t < count) {
+                    const bool first = t < cnt1;
+                    const int Jb = first ? I1 + t : I2 + (t - cnt1);
+                    const R ar = first ? a1r : a2r;
+                    const R ai = first ? a1i : a2i;
+                    const R br = Ar[row + Jb * 16], bi = Ai[row + Jb * 16];
+                    accR[t] = mfma16(ar, br, accR[t]);
+                    accR[t] = mfma16(ai, bi, accR[t]);
+                    accI[t] = mfma16(ar, bi, accI[t]);
+                    accI[t] = mfma16(-ai, br, accI[t]);
+                }
+            }
+        }
+    }
+    if (!active) return;
+    // write G (column-major, ld = s), both triangles
+    double2* G = Gs + (int64_t)blockIdx.x * g_stride;
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+        if (t < count) {
+            const bool first = t < cnt1;
+            const int Ib = first ? I1 : I2;
+            const int Jb = first ? I1 + t : I2 + (t - cnt1);
+            const int col = Jb * 16 + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = Ib * 16 + lk * 4 + r;
+                if (row < s && col < s) {
+                    double2 v = make_double2((double)accR[t][r], (double)accI[t][r]);
+                    G[(int64_t)col * s + row] = v;
+                    if (Ib != Jb) G[(int64_t)row * s + col] = make_double2(v.x, -v.y);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_reproj
+//   One workgroup per matrix.  Loop over chunks of KC rows of A:
+//     Y_chunk = A_chunk (KC x s) * S (s x s)   on the matrix cores,
+//   then per element the multiplier update and R = Z - D'/beta staged in LDS,
+//   then fixed-order anti-diagonal sums into the LDS accumulator Bacc.
+// ---------------------------------------------------------------------------
+template <typename R, int MAXT>
+__global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restrict__ hb,
+                                                       cplx_t<R>* __restrict__ db,
+                                                       cplx_t<R>* __restrict__ bb,
+                                                       const cplx_t<R>* __restrict__ wtab,
+                                                       const LRDesc* __restrict__ descs, int m0,
+                                                       const cplx_t<R>* __restrict__ Ss, int64_t s_stride,
+                                                       R inv_beta, R tau, int KC) {
+    using C = cplx_t<R>;
+    using A4 = acc4_t<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const LRDesc d = descs[m0 + blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int p = lr_p(d), q = lr_q(d), side = lr_side(d);
+    const int s = side == 0 ? q : p;
+    const int l = side == 0 ? p : q;
+    const int n = d.n, k = d.k, J = d.J, V = d.V;
+    const int nt = (s + 15) / 16;
+    const int s_pad = nt * 16;
+    const int ldA = s_pad + 4;
+    const int utab = V * J * n;
+    C* U = reinterpret_cast<C*>(smem_raw);
+    C* Bacc = U + utab;
+    R* Ar = reinterpret_cast<R*>(Bacc + utab);
+    R* Ai = Ar + KC * ldA;
+    C* Rst = reinterpret_cast<C*>(Ar);  // R staging reuses the A planes: KC x s_pad complex fits in 2*KC*ldA reals
+
+    load_line_table<R>(U, hb, wtab, d, tid, LR_THREADS);
+    for (int e = tid; e < utab; e += LR_THREADS) Bacc[e] = cmk<C>(0, 0);
+
+    C* Dm = db + d.d_off;
+    const C* S = Ss + (int64_t)blockIdx.x * s_stride;
+    const int li = lane & 15, lk = lane >> 4;
+    const int rt = KC / 16;               // row tiles per chunk
+    const int ntile = rt * nt;            // tiles per chunk
+
+    for (int r0 = 0; r0 < l; r0 += KC) {
+        __syncthreads();
+        stage_A_chunk<R>(Ar, Ai, ldA, U, Dm, d, inv_beta, r0, KC, s_pad, tid, LR_THREADS);
+        __syncthreads();
+        A4 accR[MAXT], accI[MAXT];
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+            accR[t] = A4{0, 0, 0, 0};
+            accI[t] = A4{0, 0, 0, 0};
+        }
+        // tiles of this wave: t-th tile = wave + t * LR_WAVES
+        for (int kk = 0; kk < s_pad; kk += 4) {
+            const int kidx = kk + lk;
+#pragma unroll
+            for (int t = 0; t < MAXT; ++t) {
+                const int tile = wave + t * LR_WAVES;
+                if (tile < ntile) {
+                    const int It = tile / nt, Jt = tile - It * nt;
+                    const int arow = (It * 16 + li) * ldA + kidx;
+                    const R ar = Ar[arow], ai = Ai[arow];
+                    const int col = Jt * 16 + li;
+                    R sr = 0, si = 0;
+                    if (kidx < s && col < s) {
+                        const C sv = S[(int64_t)kidx * s + col];
+                        sr = sv.x;
+                        si = sv.y;
+                    }
+                    accR[t] = mfma16(ar, sr, accR[t]);
+                    accR[t] = mfma16(-ai, si, accR[t]);
+                    accI[t] = mfma16(ar, si, accI[t]);
+                    accI[t] = mfma16(ai, sr, accI[t]);
+                }
+            }
+        }
+        __syncthreads();  // A planes are dead from here on; reuse them for R
+        // epilogue: multiplier update and R staging
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+            const int tile = wave + t * LR_WAVES;
+            if (tile < ntile) {
+                const int It = tile / nt, Jt = tile - It * nt;
+                const int col = Jt * 16 + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rloc = It * 16 + lk * 4 + r;
+                    const int row = r0 + rloc;
+                    C rv = cmk<C>(0, 0);
+                    if (row < l && col < s) {
+                        int a, c;
+                        C z;
+                        if (side == 0) { a = row; c = col; z = cmk<C>(accR[t][r], accI[t][r]); }
+                        else { a = col; c = row; z = cmk<C>(accR[t][r], -accI[t][r]); }
+                        const C lv = lift_val(U, n, k, a, c);
+                        const int64_t di = (int64_t)a * q + c;
+                        const C dv = Dm[di];
+                        C dn;
+                        dn.x = dv.x + tau * (lv.x - z.x);
+                        dn.y = dv.y + tau * (lv.y - z.y);
+                        Dm[di] = dn;
+                        rv.x = z.x - dn.x * inv_beta;
+                        rv.y = z.y - dn.y * inv_beta;
+                    }
+                    Rst[rloc * s_pad + col] = rv;
+                }
+            }
+        }
+        __syncthreads();
+        // anti-diagonal sums of this chunk, fixed order, one owner per entry
+        const int rows_here = min(KC, l - r0);
+        for (int e = tid; e < utab; e += LR_THREADS) {
+            const int i = e % n, blk = e / n;
+            C acc = Bacc[e];
+            if (side == 0) {
+                // chunk rows are a in [r0, r0 + rows_here): b = i - a in [0, k)
+                int a_lo = max(r0, i - k + 1), a_hi = min(r0 + rows_here - 1, min(i, p - 1));
+                for (int a = a_lo; a <= a_hi; ++a) {
+                    const C v = Rst[(a - r0) * s_pad + blk * k + (i - a)];
+                    acc.x += v.x;
+                    acc.y += v.y;
+                }
+            } else {
+                // chunk rows are columns c of T: c = blk*k + b, a = i - b in [0, p)
+                int c_lo = max(r0, blk * k + max(0, i - p + 1));
+                int c_hi = min(r0 + rows_here - 1, blk * k + min(k - 1, i));
+                for (int c = c_lo; c <= c_hi; ++c) {
+                    const int b = c - blk * k;
+                    const C v = Rst[(c - r0) * s_pad + (i - b)];
+                    acc.x += v.x;
+                    acc.y += v.y;
+                }
+            }
+            Bacc[e] = acc;
+        }
+    }
+    __syncthreads();
+    // b_j[i] = conj(w[i]) Bacc[0][j][i] + (virtual coils) conj(conj(w[f]) Bacc[1][j][f]), f = flip(i)
+    const int cc = n / 2;
+    for (int e = tid; e < J * n; e += LR_THREADS) {
+        const int i = e % n, j = e / n;
+        C w = d.use_w ? wtab[d.w_off + i] : cmk<C>(1, 0);
+        C out = cmulc(w, Bacc[j * n + i]);
+        if (V == 2) {
+            int fi = (2 * cc - i) % n;
+            if (fi < 0) fi += n;
+            C wf = d.use_w ? wtab[d.w_off + fi] : cmk<C>(1, 0);
+            C g = cmulc(wf, Bacc[(J + j) * n + fi]);
+            out.x += g.x;
+            out.y -= g.y;
+        }
+        bb[d.b_off + (int64_t)j * d.b_cs + (int64_t)i * d.b_es] = out;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+template <typename R>
+static size_t gram_lds_bytes(int V, int J, int n, int s, int KC) {
+    int s_pad = ((s + 15) / 16) * 16;
+    return (size_t)V * J * n * sizeof(cplx_t<R>) + 2 * (size_t)KC * (s_pad + 4) * sizeof(R);
+}
+template <typename R>
+static size_t reproj_lds_bytes(int V, int J, int n, int s, int KC) {
+    int s_pad = ((s + 15) / 16) * 16;
+    return 2 * (size_t)V * J * n * sizeof(cplx_t<R>) + 2 * (size_t)KC * (s_pad + 4) * sizeof(R);
+}
+
+constexpr size_t LDS_LIMIT = 160 * 1024;
+
+template <typename R, int MAXT>
+static hipError_t launch_gram_t(dim3 grid, size_t lds, hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db,
+                                const cplx_t<R>* wtab, const LRDesc* descs, int m0, double2* Gs, int64_t gst,
+                                R inv_beta, int KC) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_lift_gram<R, MAXT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_lift_gram<R, MAXT>), grid, dim3(LR_THREADS), lds, st, hb, db, wtab, descs, m0, Gs, gst,
+                       inv_beta, KC);
+    return hipGetLastError();
+}
+
+// Launch the Gram kernel for matrices [m0, m0 + count) that share (V, J, n, k).
+template <typename R>
+hipError_t launch_lift_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* wtab,
+                            const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, double2* Gs,
+                            int64_t g_stride, double beta) {
+    const int s = lr_s(proto);
+    const int nt = (s + 15) / 16;
+    const int n_units = (nt + 1) / 2;
+    const int groups = (n_units + LR_WAVES - 1) / LR_WAVES;
+    int KC = 16;
+    while (KC > 4 && gram_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT) KC /= 2;
+    if (gram_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT) return hipErrorInvalidValue;
+    const size_t lds = gram_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC);
+    dim3 grid(count, groups);
+    const R ib = (R)(1.0 / beta);
+    const int need = nt + 1;
+    if (need <= 4) return launch_gram_t<R, 4>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
+    if (need <= 8) return launch_gram_t<R, 8>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
+    if (need <= 12) return launch_gram_t<R, 12>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
+    if (need <= 16) return launch_gram_t<R, 16>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
+    if (need <= 21) return launch_gram_t<R, 21>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
+    return hipErrorInvalidValue;  // s > 320
+}
+
+template <typename R, int MAXT>
+static hipError_t launch_reproj_t(dim3 grid, size_t lds, hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db,
+                                  cplx_t<R>* bb, const cplx_t<R>* wtab, const LRDesc* descs, int m0,
+                                  const cplx_t<R>* Ss, int64_t sst, R inv_beta, R tau, int KC) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_reproj<R, MAXT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_reproj<R, MAXT>), grid, dim3(LR_THREADS), lds, st, hb, db, bb, wtab, descs, m0, Ss, sst,
+                       inv_beta, tau, KC);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_reproj(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cplx_t<R>* bb, const cplx_t<R>* wtab,
+                         const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, const cplx_t<R>* Ss,
+                         int64_t s_stride, double beta, double tau) {
+    const int s = lr_s(proto), l = lr_l(proto);
+    const int nt = (s + 15) / 16;
+    int KC = 64;
+    while (KC > 16 && (reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT || KC > ((l + 15) / 16) * 16))
+        KC -= 16;
+    const size_t lds = reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC);
+    if (lds > LDS_LIMIT) return hipErrorInvalidValue;
+    const int tiles = (KC / 16) * nt;
+    const int need = (tiles + LR_WAVES - 1) / LR_WAVES;
+    dim3 grid(count);
+    const R ib = (R)(1.0 / beta), tt = (R)tau;
+    if (need <= 2) return launch_reproj_t<R, 2>(grid, lds, st, hb, db, bb, wtab, descs_dev, m0, Ss, s_stride, ib, tt, KC);
+    if (need <= 4) return launch_reproj_t<R, 4>(grid, lds, st, hb, db, bb, wtab, descs_dev, m0, Ss, s_stride, ib, tt, KC);
+    if (need <= 8) return launch_reproj_t<R, 8>(grid, lds, st, hb, db, bb, wtab, descs_dev, m0, Ss, s_stride, ib, tt, KC);
+    if (need <= 12) return launch_reproj_t<R, 12>(grid, lds, st, hb, db, bb, wtab, descs_dev, m0, Ss, s_stride, ib, tt, KC);
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_lift_gram<float>(hipStream_t, const float2*, const float2*, const float2*, const LRDesc*,
+                                            const LRDesc&, int, int, double2*, int64_t, double);
+template hipError_t launch_lift_gram<double>(hipStream_t, const double2*, const double2*, const double2*,
+                                             const LRDesc*, const LRDesc&, int, int, double2*, int64_t, double);
+template hipError_t launch_reproj<float>(hipStream_t, const float2*, float2*, float2*, const float2*, const LRDesc*,
+                                         const LRDesc&, int, int, const float2*, int64_t, double, double);
+template hipError_t launch_reproj<double>(hipStream_t, const double2*, double2*, double2*, const double2*,
+                                          const LRDesc*, const LRDesc&, int, int, const double2*, int64_t, double,
+                                          double);
+
+}  // namespace shlr

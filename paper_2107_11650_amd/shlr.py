@@ -1,0 +1,279 @@
+"""Thin Python binding of the SHLR C ABI (``include/shlr.h``).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+kernels of ``libshlr.so``.  PyTorch supplies device memory and the stream.
+Importing this module raises if the shared library is missing; there is no
+fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshlr.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2107_11650_amd.build` "
+                      "(or __graft_entry__.build()); there is no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MODEL_PI = 0
+MODEL_PARAM = 1
+PREC_MIXED = 0
+PREC_FP64 = 1
+
+STATUS = {
+    0: "SHLR_OK", 1: "SHLR_E_INVALID_ARG", 2: "SHLR_E_SINGULAR", 3: "SHLR_E_NONFINITE",
+    4: "SHLR_E_WORKSPACE", 5: "SHLR_E_DEVICE", 6: "SHLR_E_UNSUPPORTED", 7: "SHLR_E_STATE",
+}
+
+EXPORTED = [
+    "shlr_plan_create", "shlr_plan_destroy", "shlr_workspace_size", "shlr_bind", "shlr_set_spirit_kernel",
+    "shlr_calibrate_spirit", "shlr_init", "shlr_iterate", "shlr_iterate_graph", "shlr_get_kspace",
+    "shlr_reconstruct", "shlr_fft_lines", "shlr_lowrank_workspace_size", "shlr_lowrank_lines",
+    "shlr_last_error", "shlr_version",
+]
+
+
+class ShlrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CParams(ctypes.Structure):
+    _fields_ = [
+        ("model", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_slices", ctypes.c_int32),
+        ("M", ctypes.POINTER(ctypes.c_int32)), ("N", ctypes.POINTER(ctypes.c_int32)),
+        ("J", ctypes.c_int32), ("L", ctypes.c_int32), ("k_row", ctypes.c_int32), ("k_col", ctypes.c_int32),
+        ("use_vc", ctypes.c_int32), ("use_w", ctypes.c_int32), ("spirit_ksize", ctypes.c_int32),
+        ("hard_dc", ctypes.c_int32), ("normalize", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+        ("n_cg", ctypes.c_int32),
+        ("lam", ctypes.c_double), ("lambda1", ctypes.c_double), ("lambda2", ctypes.c_double),
+        ("beta", ctypes.c_double), ("tau", ctypes.c_double), ("tol", ctypes.c_double), ("d0", ctypes.c_double),
+    ]
+
+
+class CInfo(ctypes.Structure):
+    _fields_ = [("iters_done", ctypes.c_int32), ("converged", ctypes.c_int32), ("rel_change", ctypes.c_double),
+                ("scale", ctypes.c_double), ("device_flags", ctypes.c_uint32)]
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_lib.shlr_plan_create.argtypes = [ctypes.POINTER(CParams), ctypes.POINTER(_vp)]
+_lib.shlr_plan_destroy.argtypes = [_vp]
+_lib.shlr_plan_destroy.restype = None
+_lib.shlr_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+_lib.shlr_bind.argtypes = [_vp, _vp, ctypes.c_size_t, _vp]
+_lib.shlr_set_spirit_kernel.argtypes = [_vp, _vp]
+_lib.shlr_calibrate_spirit.argtypes = [_vp, _i32, ctypes.c_double]
+_lib.shlr_init.argtypes = [_vp, _vp, _vp]
+_lib.shlr_iterate.argtypes = [_vp, _i32, ctypes.POINTER(CInfo)]
+_lib.shlr_iterate_graph.argtypes = [_vp, _i32, ctypes.POINTER(CInfo)]
+_lib.shlr_get_kspace.argtypes = [_vp, _vp]
+_lib.shlr_reconstruct.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(CInfo)]
+_lib.shlr_fft_lines.argtypes = [_i32, _i32, _i32, _i32, _vp, _vp, _vp]
+_lib.shlr_lowrank_workspace_size.argtypes = [_i32, _i32, _i32, _i32, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)]
+_lib.shlr_lowrank_lines.argtypes = [_i32, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.shlr_last_error.restype = ctypes.c_char_p
+_lib.shlr_version.restype = ctypes.c_char_p
+for _f in EXPORTED:
+    if _f not in ("shlr_plan_destroy", "shlr_last_error", "shlr_version"):
+        getattr(_lib, _f).restype = ctypes.c_int
+
+
+def _check(code):
+    if code != 0:
+        raise ShlrError(code, _lib.shlr_last_error().decode())
+
+
+def version() -> str:
+    return _lib.shlr_version().decode()
+
+
+def library():
+    return _lib
+
+
+@dataclass
+class Params:
+    """Mirror of ``shlr_params`` (see include/shlr.h for the meaning of each field)."""
+    model: int = MODEL_PI
+    precision: int = PREC_MIXED
+    M: tuple = (64,)
+    N: tuple = (64,)
+    J: int = 4
+    L: int = 1
+    k_row: int = 8
+    k_col: int = 8
+    use_vc: bool = False
+    use_w: bool = True
+    spirit_ksize: int = 0
+    hard_dc: bool = False
+    normalize: bool = True
+    max_iter: int = 20
+    n_cg: int = 10
+    lam: float = 1e4
+    lambda1: float = 0.0
+    lambda2: float = 2.0
+    beta: float = 10.0
+    tau: float | None = None
+    tol: float = 0.0
+    d0: float = 1.0
+
+    def to_c(self):
+        n = len(self.M)
+        Ma = (ctypes.c_int32 * n)(*[int(v) for v in self.M])
+        Na = (ctypes.c_int32 * n)(*[int(v) for v in self.N])
+        c = CParams(model=self.model, precision=self.precision, n_slices=n, M=Ma, N=Na, J=self.J, L=self.L,
+                    k_row=self.k_row, k_col=self.k_col, use_vc=int(self.use_vc), use_w=int(self.use_w),
+                    spirit_ksize=self.spirit_ksize, hard_dc=int(self.hard_dc), normalize=int(self.normalize),
+                    max_iter=self.max_iter, n_cg=self.n_cg, lam=self.lam, lambda1=self.lambda1,
+                    lambda2=self.lambda2, beta=self.beta, tau=self.beta if self.tau is None else self.tau,
+                    tol=self.tol, d0=self.d0)
+        return c, (Ma, Na)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A bound SHLR plan: workspace from torch, work on torch's current stream."""
+
+    def __init__(self, params: Params, device="cuda"):
+        import torch
+        self.params = params
+        c, keep = params.to_c()
+        h = ctypes.c_void_p()
+        _check(_lib.shlr_plan_create(ctypes.byref(c), ctypes.byref(h)))
+        self._h = h
+        nb = ctypes.c_size_t()
+        _check(_lib.shlr_workspace_size(h, ctypes.byref(nb)))
+        self.ws_bytes = nb.value
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.ws.data_ptr()) % 256
+        self._ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
+        _check(_lib.shlr_bind(h, self._ws_ptr, ctypes.c_size_t(self.ws_bytes), _stream()))
+
+    @property
+    def cdtype(self):
+        import torch
+        return torch.complex64 if self.params.precision == PREC_MIXED else torch.complex128
+
+    def _prep(self, y, mask):
+        import torch
+        y = y.to(self.cdtype).contiguous()
+        mask = mask.to(torch.uint8).contiguous()
+        return y, mask
+
+    def init(self, y, mask):
+        y, mask = self._prep(y, mask)
+        self._y, self._mask = y, mask
+        _check(_lib.shlr_init(self._h, _ptr(y), _ptr(mask)))
+
+    def set_spirit_kernel(self, g):
+        import numpy as np
+        g = np.ascontiguousarray(np.asarray(g, dtype=np.complex128))
+        _check(_lib.shlr_set_spirit_kernel(self._h, g.ctypes.data_as(ctypes.c_void_p)))
+
+    def calibrate_spirit(self, acs=24, reg=1e-3):
+        _check(_lib.shlr_calibrate_spirit(self._h, int(acs), float(reg)))
+
+    def iterate(self, n, graph=False):
+        info = CInfo()
+        f = _lib.shlr_iterate_graph if graph else _lib.shlr_iterate
+        _check(f(self._h, int(n), ctypes.byref(info)))
+        return info
+
+    def iterate_async(self, n, graph=False):
+        f = _lib.shlr_iterate_graph if graph else _lib.shlr_iterate
+        _check(f(self._h, int(n), None))
+
+    def kspace(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(self._y)
+        _check(_lib.shlr_get_kspace(self._h, _ptr(out)))
+        return out
+
+    def reconstruct(self, y, mask):
+        import torch
+        y, mask = self._prep(y, mask)
+        self._y, self._mask = y, mask
+        out = torch.empty_like(y)
+        info = CInfo()
+        _check(_lib.shlr_reconstruct(self._h, _ptr(y), _ptr(mask), _ptr(out), ctypes.byref(info)))
+        return out, info
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.shlr_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_check(params: Params):
+    """Validate params on the host only; returns the workspace size in bytes."""
+    c, keep = params.to_c()
+    h = ctypes.c_void_p()
+    _check(_lib.shlr_plan_create(ctypes.byref(c), ctypes.byref(h)))
+    nb = ctypes.c_size_t()
+    try:
+        _check(_lib.shlr_workspace_size(h, ctypes.byref(nb)))
+    finally:
+        _lib.shlr_plan_destroy(h)
+    return nb.value
+
+
+def fft_lines(x, inverse=False):
+    """Centred unitary DFT of the rows of a contiguous complex tensor (…, n)."""
+    import torch
+    prec = PREC_MIXED if x.dtype == torch.complex64 else PREC_FP64
+    x = x.contiguous()
+    out = torch.empty_like(x)
+    n = x.shape[-1]
+    _check(_lib.shlr_fft_lines(prec, n, x.numel() // max(n, 1), int(inverse), _ptr(x), _ptr(out), _stream()))
+    return out
+
+
+def lowrank_workspace_size(precision, n_mat, J, n, k, use_vc):
+    nb = ctypes.c_size_t()
+    _check(_lib.shlr_lowrank_workspace_size(precision, n_mat, J, n, k, int(use_vc), ctypes.byref(nb)))
+    return nb.value
+
+
+def lowrank_lines(h, D, k, beta, tau, thr, use_vc=False, use_w=True, ranks=False):
+    """One Z/D step on a batch of lines (see shlr_lowrank_lines). D is updated in place.
+
+    h: (B, J, n) complex; D: (B, p, q) complex.  Returns b (B, J, n) [and ranks (B,)].
+    """
+    import torch
+    prec = PREC_MIXED if h.dtype == torch.complex64 else PREC_FP64
+    B, J, n = h.shape
+    assert D.is_contiguous() and h.is_contiguous()
+    nb = lowrank_workspace_size(prec, B, J, n, k, use_vc)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=h.device)
+    off = (-ws.data_ptr()) % 256
+    b = torch.empty_like(h)
+    rk = torch.zeros(B, dtype=torch.int32, device=h.device) if ranks else None
+    _check(_lib.shlr_lowrank_lines(prec, B, J, n, k, int(use_vc), int(use_w), float(beta), float(tau), float(thr),
+                                   _ptr(h), _ptr(D), _ptr(b), _ptr(rk) if ranks else None,
+                                   ctypes.c_void_p(ws.data_ptr() + off), ctypes.c_size_t(nb), _stream()))
+    return (b, rk) if ranks else b

@@ -1,0 +1,93 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared
+symbol, and validates plans without touching a GPU."""
+
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "shlr.h")
+LIB = os.path.join(ROOT, "paper_2107_11650_amd", "libshlr.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libshlr.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(shlr_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    from paper_2107_11650_amd import shlr
+    assert sorted(shlr.EXPORTED) == declared_functions()
+
+
+def test_version_string():
+    from paper_2107_11650_amd import shlr
+    assert "gfx950" in shlr.version()
+
+
+def _p(**kw):
+    from paper_2107_11650_amd import shlr
+    return shlr.Params(**kw)
+
+
+def test_valid_plans_report_workspace():
+    from paper_2107_11650_amd import shlr
+    b1 = shlr.plan_check(_p(M=(64,), N=(64,), J=4, k_row=8, k_col=8))
+    b2 = shlr.plan_check(_p(M=(256,), N=(256,), J=8, k_row=25, k_col=25))
+    assert 0 < b1 < b2
+    # FP64 form needs more memory than the mixed form
+    assert shlr.plan_check(_p(precision=shlr.PREC_FP64)) > b1
+    # ragged slices and the parameter model
+    assert shlr.plan_check(_p(M=(40, 64), N=(48, 32), J=2, k_row=5, k_col=5)) > 0
+    assert shlr.plan_check(_p(model=shlr.MODEL_PARAM, M=(8,), N=(64,), L=8, J=4, k_row=8, k_col=4, use_vc=True)) > 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(beta=0.0), 1),
+    (dict(beta=float("nan")), 1),
+    (dict(tau=-1.0), 1),
+    (dict(lam=0.0), 1),
+    (dict(k_row=65), 1),
+    (dict(k_col=0), 1),
+    (dict(J=0), 1),
+    (dict(M=(0,), N=(64,)), 1),
+    (dict(model=7), 1),
+    (dict(precision=3), 1),
+    (dict(spirit_ksize=4), 1),
+    (dict(spirit_ksize=5, hard_dc=True), 6),
+    (dict(M=(1024,), N=(1024,), J=16, k_row=25, k_col=25), 6),   # min(p, q) > 320
+])
+def test_invalid_plans_are_rejected(kw, code):
+    from paper_2107_11650_amd import shlr
+    with pytest.raises(shlr.ShlrError) as ei:
+        shlr.plan_check(_p(**kw))
+    assert ei.value.code == code
+    assert str(ei.value)
+
+
+def test_param_model_validation():
+    from paper_2107_11650_amd import shlr
+    with pytest.raises(shlr.ShlrError):
+        shlr.plan_check(_p(model=shlr.MODEL_PARAM, M=(8, 8), N=(64, 64), L=8))   # one series only
+    with pytest.raises(shlr.ShlrError):
+        shlr.plan_check(_p(model=shlr.MODEL_PARAM, M=(8,), N=(64,), L=8, lambda2=0.0))
+    with pytest.raises(shlr.ShlrError):
+        shlr.plan_check(_p(model=shlr.MODEL_PARAM, M=(8,), N=(64,), L=8, k_col=9))
+
+
+def test_lowrank_workspace_size_and_errors():
+    from paper_2107_11650_amd import shlr
+    assert shlr.lowrank_workspace_size(shlr.PREC_MIXED, 16, 4, 64, 8, False) > 0
+    with pytest.raises(shlr.ShlrError):
+        shlr.lowrank_workspace_size(shlr.PREC_MIXED, 16, 4, 64, 65, False)
+    with pytest.raises(shlr.ShlrError):
+        shlr.lowrank_workspace_size(5, 16, 4, 64, 8, False)
