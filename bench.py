@@ -1,0 +1,182 @@
+#!/usr/bin/env python
+"""SHLR throughput on one MI355X: iterations/s of the full ADMM iteration.
+
+Workload (the 8-coil parallel-imaging configuration): 8 coils, 256 x 256
+complex64 k-space of the seeded ellipse phantom with smooth quadratic phase
+and Gaussian coil maps, 2D Poisson-disc mask at R = 4 with a fully sampled
+24 x 24 centre, Hankel window 25 on rows and columns, SPIRiT 5 x 5 kernel
+calibrated on the centre, 10 PCG steps per X-update, lambda = 1e4,
+lambda1 = 10, beta = tau = 30.  One step = one ADMM iteration (X-update,
+Z-updates of all 512 row/column lifts, multiplier updates).
+
+Prints one JSON line with the throughput, the roofline of the dominant kernel
+(timed live with HIP events on the plan's stream), the FP64 oracle timed on
+the host as a CPU baseline, and the NMSE of the GPU iterate against the
+oracle after the same iterations from the same inputs.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SHLR iterations/sec (256² k-space × coils) at NMSE≤1e-5 vs FP64 oracle; % roofline"
+
+PEAK_TFLOPS_FP32_MFMA = 157.3
+PEAK_TFLOPS_FP64 = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def workload(J=8, M=256, N=256, seed=0):
+    import numpy as np
+    from paper_2107_11650_amd import inputs
+    k = inputs.phantom_kspace(J, M, N, seed=1000 + seed)
+    mask = inputs.mask_poisson_disc(M, N, R=4.0, acs=24, seed=2000 + seed)
+    return inputs.undersample(k, mask), mask.astype(np.uint8)
+
+
+def lowrank_work(p, q, csize):
+    """Algorithmic work of one lifted matrix (Gram, eigen, reprojection)."""
+    s, l = min(p, q), max(p, q)
+    return {
+        "gram_flops": 4.0 * l * s * s,          # Hermitian product, complex MAC = 8 flops, half the tiles
+        "reproj_flops": 8.0 * l * s * s,        # full product A S
+        "eig_flops": 13.3 * s ** 3,             # tridiagonalisation + back-transform bookkeeping
+        "gram_bytes": p * q * csize,            # read the multiplier D
+        "reproj_bytes": 2 * p * q * csize,      # read and write D
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--check-iters", type=int, default=2,
+                    help="iterations compared with the FP64 oracle (also the CPU-baseline sample)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n-cg", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by slice / FE position "
+              "with no communication, so N > 1 is not measured here", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2107_11650_amd import shlr
+
+    J, M, N, kw = 8, 256, 256, 25
+    lam, lam1, beta = 1e4, 10.0, 30.0
+    Y, mask = workload(J, M, N)
+    prec = shlr.PREC_MIXED if args.precision == "mixed" else shlr.PREC_FP64
+    p = shlr.Params(M=(M,), N=(N,), J=J, k_row=kw, k_col=kw, lam=lam, lambda1=lam1, beta=beta, tau=beta,
+                    spirit_ksize=5, n_cg=args.n_cg, precision=prec, max_iter=100)
+    plan = shlr.Plan(p)
+    yd = torch.from_numpy(Y).to(plan.cdtype).cuda()
+    md = torch.from_numpy(mask).cuda()
+    plan.init(yd, md)
+    plan.calibrate_spirit(acs=24, reg=1e-3)
+
+    # accuracy check leg: K after check_iters iterations from the initial state
+    plan.iterate(args.check_iters)
+    k_check = plan.kspace().cpu().numpy().astype(np.complex128)
+
+    plan.iterate(args.warmup)
+    torch.cuda.synchronize()
+    plan.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.iterate_async(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = plan.timing_read()
+    plan.timing_enable(False)
+    elapsed = t1 - t0
+    value = args.steps / elapsed
+
+    # roofline of the dominant kernel
+    csize = 8 if prec == shlr.PREC_MIXED else 16
+    pr, qr = N - kw + 1, kw * J
+    pc, qc = M - kw + 1, kw * J
+    wr, wc = lowrank_work(pr, qr, csize), lowrank_work(pc, qc, csize)
+    per_launch = {  # one launch of each low-rank kernel covers every row and column matrix of the step
+        "gram": (M * wr["gram_flops"] + N * wc["gram_flops"]) / 2,
+        "eig": (M * wr["eig_flops"] + N * wc["eig_flops"]) / 2,
+        "reproj": (M * wr["reproj_flops"] + N * wc["reproj_flops"]) / 2,
+    }
+    # rows and columns are two launches per phase per step
+    dom = max(("gram", "eig", "reproj", "xupdate", "spirit"), key=lambda k: phases[k][0])
+    ms_dom, n_dom = phases[dom]
+    avg_ms = ms_dom / max(n_dom, 1)
+    if dom in ("gram", "reproj"):
+        peak = PEAK_TFLOPS_FP32_MFMA if prec == shlr.PREC_MIXED else PEAK_TFLOPS_FP64
+        achieved = per_launch[dom] / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "unit": "TFLOP/s"}
+    elif dom == "eig":
+        peak = PEAK_TFLOPS_FP64
+        achieved = per_launch[dom] / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "unit": "TFLOP/s"}
+    else:
+        # transform phases: one read and one write of each J x M x N array touched per launch
+        peak = PEAK_HBM_GBS
+        bytes_launch = 6 * J * M * N * csize
+        achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "unit": "GB/s"}
+    roof.update({"kernel": dom, "achieved": achieved, "peak": peak, "frac": achieved / peak, "traffic": None,
+                 "avg_launch_ms": avg_ms, "launches": n_dom})
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == shlr.PREC_MIXED else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "SHLR-S iteration, 8 coils, 256x256 complex64 ellipse phantom (quadratic phase, Gaussian "
+                        "coils), 2D Poisson-disc R=4 + 24x24 centre, Hankel window 25 rows/cols (512 lifts of "
+                        "232x200), SPIRiT 5x5, 10 PCG steps, lambda=1e4, lambda1=10, beta=tau=30",
+            "coils": J, "M": M, "N": N, "window": kw, "spirit_kernel": 5, "n_cg": args.n_cg,
+            "eig_dtype": "f64",
+        },
+        "phases_ms_per_step": {k: v[0] / args.steps for k, v in phases.items()},
+        "roofline": roof,
+    }
+
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_info
+        from oracle import shlr_oracle as O
+        Yn = Y / np.abs(Y).max()
+        g = O.spirit_calibrate(Yn, acs=24, ks=5)
+        prm = O.PIParams(k_row=kw, k_col=kw, lam=lam, lam1=lam1, beta=beta, n_cg=args.n_cg,
+                         iters=args.check_iters)
+        c0 = time.perf_counter()
+        k_ref = O.shlr_pi(Y, mask.astype(bool), prm, g=g)
+        c1 = time.perf_counter()
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+        result["cpu_baseline"] = {
+            "value": args.check_iters / (c1 - c0), "unit": "iterations/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {args.check_iters} iterations of the same workload (NumPy FP64, LAPACK SVD "
+                      f"per lift, SPIRiT kernel calibrated beforehand)",
+        }
+        result["nmse_vs_oracle"] = O.nmse(k_check, k_ref)
+        result["nmse_iters"] = args.check_iters
+    plan.close()
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -156,6 +156,19 @@ shlr_status shlr_get_kspace(const shlr_plan* plan, void* k_out_dev);
 shlr_status shlr_reconstruct(shlr_plan* plan, const void* y_dev, const uint8_t* mask_dev,
                              void* k_out_dev, shlr_info* info);
 
+/* Per-phase device timing of later shlr_iterate calls, measured with HIP events
+ * recorded on the plan's stream around every launch of a phase.  enable != 0
+ * starts (and resets) the accumulation; enable == 0 stops it.  shlr_iterate_graph
+ * is not timed. */
+#define SHLR_TIMING_PHASES 5
+shlr_status shlr_timing_enable(shlr_plan* plan, int32_t enable);
+
+/* Read the accumulated times (synchronises the stream).  Phase index:
+ * 0 transforms and X-update (Eq. 15 / S7), 1 lift + Gram, 2 eigen-solve and
+ * threshold (Eq. 16), 3 reprojection + multiplier update (Eq. 13) + adjoint
+ * lift, 4 SPIRiT PCG.  ms_out[5] milliseconds, launches_out[5] launch counts. */
+shlr_status shlr_timing_read(shlr_plan* plan, double* ms_out, int32_t* launches_out);
+
 /* ---------------------------------------------------------------------------
  * Stage entry points (the steps of one iteration, callable on their own).
  * ------------------------------------------------------------------------- */

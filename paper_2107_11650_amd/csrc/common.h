@@ -36,14 +36,19 @@ template <> struct acc4_of<double> { using type = doublex4; };
 template <typename R> using acc4_t = typename acc4_of<R>::type;
 
 // 16x16x4 matrix-core step: D[i][j] += sum_k A[i][k] B[k][j].
-// Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; it holds
-// D[4 * (l / 16) + r][l % 16] in element r of the accumulator.
+// Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16].  Element r of the
+// accumulator of lane l holds D[acc_row<R>(l / 16, r)][l % 16]: row
+// 4 * (l / 16) + r for the FP32 instruction, (l / 16) + 4 * r for FP64
+// (both checked on gfx950).
 __device__ inline floatx4 mfma16(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 __device__ inline doublex4 mfma16(double a, double b, doublex4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+template <typename R> __device__ inline int acc_row(int lk, int r);
+template <> __device__ inline int acc_row<float>(int lk, int r) { return 4 * lk + r; }
+template <> __device__ inline int acc_row<double>(int lk, int r) { return lk + 4 * r; }
 
 // Geometry and addressing of one lifted matrix (one line of J coils).
 // Offsets count complex elements from the base pointers given to the kernels.

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
                                                            const uint8_t* __restrict__ base_m,
                                                            const R* __restrict__ rtab, XupdRows x, FftPlan pl,
                                                            int NL, R lam, R beta, int hard_dc,
-                                                           double* __restrict__ change_acc) {
+                                                           double* __restrict__ change_acc, int rhs_only) {
     using C = cplx_t<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = x.n;
@@ -230,6 +230,12 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
         const int rci = x.rc_digit == 0 ? d0 : (x.rc_digit == 1 ? d1 : d2);
         const R rsum = rtab[x.rr_off + i] + rtab[x.rc_off + rci];
         C kv;
+        if (rhs_only) {
+            const C yv = base_y[yo];
+            const R lm = mk ? lam : (R)0;
+            base_k[ko] = cmk<C>(lm * yv.x + beta * (av.x + cv.x), lm * yv.y + beta * (av.y + cv.y));
+            continue;
+        }
         if (hard_dc) {
             if (mk) kv = base_y[yo];
             else kv = cmk<C>((av.x + cv.x) / rsum, (av.y + cv.y) / rsum);
@@ -247,6 +253,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
         base_k[ko] = kv;
         oth[line * n + f] = kv;
     }
+    if (rhs_only) return;   // uniform: the right-hand side of Eq. 15 only
     if (change_acc) {
         for (int off = 32; off > 0; off >>= 1) {
             dsum += __shfl_down(dsum, off, 64);
@@ -381,7 +388,24 @@ hipError_t launch_xupd_rows(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>
     if (e != hipSuccess) return e;
     const int blocks = (x.n_rows + NL - 1) / NL;
     hipLaunchKernelGGL((k_xupd_rows<R>), dim3(blocks), dim3(FFT_THREADS), lds, st, bo, a, y, k, out, m, rtab, x, pl,
-                       NL, (R)lam, (R)beta, hard_dc, change_acc);
+                       NL, (R)lam, (R)beta, hard_dc, change_acc, 0);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_xupd_rows_rhs(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>* a, const cplx_t<R>* y,
+                                cplx_t<R>* rhs, const uint8_t* m, const R* rtab, const XupdRows& x, double lam,
+                                double beta) {
+    if (x.n_rows <= 0) return hipSuccess;
+    FftPlan pl = make_fft_plan(x.n);
+    const int NL = fft_lines_per_block<R>(x.n, x.bo.es != 1 || x.out.es != 1);
+    const size_t lds = (size_t)(x.n + 2 * NL * x.n) * sizeof(cplx_t<R>);
+    hipError_t e = hipFuncSetAttribute((const void*)k_xupd_rows<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    const int blocks = (x.n_rows + NL - 1) / NL;
+    hipLaunchKernelGGL((k_xupd_rows<R>), dim3(blocks), dim3(FFT_THREADS), lds, st, bo, a, y, rhs, (cplx_t<R>*)nullptr,
+                       m, rtab, x, pl, NL, (R)lam, (R)beta, 0, (double*)nullptr, 1);
     return hipGetLastError();
 }
 
@@ -430,6 +454,9 @@ hipError_t launch_zero_doubles(hipStream_t st, double* p, int count) {
     template hipError_t launch_xupd_rows<R>(hipStream_t, const cplx_t<R>*, const cplx_t<R>*, const cplx_t<R>*,       \
                                             cplx_t<R>*, cplx_t<R>*, const uint8_t*, const R*, const XupdRows&,       \
                                             double, double, int, double*);                                           \
+    template hipError_t launch_xupd_rows_rhs<R>(hipStream_t, const cplx_t<R>*, const cplx_t<R>*, const cplx_t<R>*,   \
+                                                cplx_t<R>*, const uint8_t*, const R*, const XupdRows&, double,        \
+                                                double);                                                              \
     template hipError_t launch_scale_copy<R>(hipStream_t, const cplx_t<R>*, cplx_t<R>*, int64_t, const double*, int); \
     template hipError_t launch_fill_pattern<R>(hipStream_t, cplx_t<R>*, int64_t, const cplx_t<R>*, int64_t, int64_t); \
     template hipError_t launch_fill_const<R>(hipStream_t, cplx_t<R>*, int64_t, double, double);                      \

@@ -159,9 +159,56 @@ struct shlr_plan {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int iters_total = 0;
+    // per-phase HIP-event timing (phase: 0 transforms + X-update, 1 Gram, 2 eigen-SVT, 3 reprojection, 4 SPIRiT)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, std::pair<size_t, size_t>>> ev_marks;  // (phase, (start, stop))
+    double t_ms[8] = {0};
+    int t_cnt[8] = {0};
 };
 
+// event helpers: a phase is bracketed by two events on the plan's stream
+static shlr_status ev_get(shlr_plan* P, size_t* idx) {
+    if (P->ev_used == P->ev_pool.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        P->ev_pool.push_back(e);
+    }
+    *idx = P->ev_used++;
+    return SHLR_OK;
+}
+static shlr_status phase_begin(shlr_plan* P, size_t* start) {
+    if (!P->timing) return SHLR_OK;
+    STCHK(ev_get(P, start));
+    HIPCHK(hipEventRecord(P->ev_pool[*start], P->stream));
+    return SHLR_OK;
+}
+static shlr_status phase_end(shlr_plan* P, int phase, size_t start) {
+    if (!P->timing) return SHLR_OK;
+    size_t stop;
+    STCHK(ev_get(P, &stop));
+    HIPCHK(hipEventRecord(P->ev_pool[stop], P->stream));
+    P->ev_marks.push_back({phase, {start, stop}});
+    return SHLR_OK;
+}
+static shlr_status timing_collect(shlr_plan* P) {
+    if (P->ev_marks.empty()) return SHLR_OK;
+    HIPCHK(hipStreamSynchronize(P->stream));
+    for (auto& m : P->ev_marks) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, P->ev_pool[m.second.first], P->ev_pool[m.second.second]));
+        P->t_ms[m.first] += ms;
+        P->t_cnt[m.first] += 1;
+    }
+    P->ev_marks.clear();
+    P->ev_used = 0;
+    return SHLR_OK;
+}
+
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t spirit_bytes(const shlr_plan* P);
 
 static shlr_status validate(const shlr_params* p) {
     if (!p) return fail(SHLR_E_INVALID_ARG, "params is NULL");
@@ -433,15 +480,7 @@ extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
     P->off_scal = off;   // scale (n_slices doubles), maxabs (n_slices u64), flags (u32), change (2 doubles per slice)
     off = align256(off + (size_t)p->n_slices * 32 + 64);
     P->off_spirit = off;
-    P->bytes_spirit = 0;
-    if (p->spirit_ksize > 0) {
-        int64_t pix = 0;
-        for (auto& L : P->sl) pix = std::max<int64_t>(pix, (int64_t)L.M * L.N);
-        // per-pixel (G-I)^H(G-I): J*J complex per pixel, plus PCG vectors (5 complex J*M*N) and scalars
-        int64_t emax = 0;
-        for (auto& L : P->sl) emax = std::max<int64_t>(emax, (int64_t)J * L.M * L.N);
-        P->bytes_spirit = align256((size_t)pix * J * J * P->csize) + 6 * align256((size_t)emax * P->csize) + 4096;
-    }
+    P->bytes_spirit = spirit_bytes(P);
     off = align256(off + P->bytes_spirit);
     P->total = off;
     P->scales.assign(p->n_slices, 1.0);
@@ -451,6 +490,7 @@ extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
 
 extern "C" void shlr_plan_destroy(shlr_plan* plan) {
     if (!plan) return;
+    for (auto e : plan->ev_pool) (void)hipEventDestroy(e);
     if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
@@ -554,11 +594,18 @@ static shlr_status run_lowrank_groups(shlr_plan* P, const std::vector<LRGroup>& 
         for (int c0 = 0; c0 < g.count; c0 += n_slots) {
             const int cnt = std::min(n_slots, g.count - c0);
             const int m0 = g.first + c0;
+            size_t e0 = 0;
+            STCHK(phase_begin(P, &e0));
             HIPCHK(launch_lift_gram<R>(P->stream, hb, db, wtab, desc_dev, g.proto, m0, cnt, G, g_stride, P->p.beta));
+            STCHK(phase_end(P, 1, e0));
+            STCHK(phase_begin(P, &e0));
             HIPCHK(launch_heig_svt<cplx_t<R>>(P->stream, desc_dev, m0, cnt, G, g_stride, S, s_stride, scr, scr_stride,
                                               ranks, ortol, flags));
+            STCHK(phase_end(P, 2, e0));
+            STCHK(phase_begin(P, &e0));
             HIPCHK(launch_reproj<R>(P->stream, hb, db, bb, wtab, desc_dev, g.proto, m0, cnt, S, s_stride, P->p.beta,
                                     P->p.tau));
+            STCHK(phase_end(P, 3, e0));
         }
     }
     return SHLR_OK;
@@ -570,6 +617,8 @@ static shlr_status iterate_once(shlr_plan* P, bool track_change) {
     const shlr_params& p = P->p;
     const int J = p.J;
     if (track_change) HIPCHK(launch_zero_doubles(P->stream, Q.change, 2 * p.n_slices));
+    size_t e0 = 0;
+    STCHK(phase_begin(P, &e0));
     if (p.model == SHLR_MODEL_PI) {
         for (int si = 0; si < p.n_slices; ++si) {
             const SliceLayout& L = P->sl[si];
@@ -623,6 +672,7 @@ static shlr_status iterate_once(shlr_plan* P, bool track_change) {
                                    Q.m + L.mask_b, Q.r, x, p.lambda, p.beta, p.hard_dc,
                                    track_change ? Q.change : nullptr));
     }
+    STCHK(phase_end(P, 0, e0));
     STCHK(run_lowrank_groups<R>(P, P->groups, Q.c, Q.c, Q.c, Q.c, Q.desc, Q.g, Q.s, Q.scr, Q.ranks, Q.flags,
                                 P->n_slots, P->g_stride, P->s_stride, P->scr_stride));
     return SHLR_OK;
@@ -763,6 +813,27 @@ static shlr_status iterate_impl(shlr_plan* P, int n, shlr_info* info) {
         info->scale = P->scales[0];
         info->device_flags = fl;
         if (fl & 1u) return fail(SHLR_E_NONFINITE, "a non-finite value was met during the iterations");
+    }
+    return SHLR_OK;
+}
+
+extern "C" shlr_status shlr_timing_enable(shlr_plan* plan, int32_t enable) {
+    if (!plan) return fail(SHLR_E_INVALID_ARG, "plan is NULL");
+    STCHK(timing_collect(plan));
+    plan->timing = enable != 0;
+    for (int i = 0; i < 8; ++i) {
+        plan->t_ms[i] = 0;
+        plan->t_cnt[i] = 0;
+    }
+    return SHLR_OK;
+}
+
+extern "C" shlr_status shlr_timing_read(shlr_plan* plan, double* ms_out, int32_t* launches_out) {
+    if (!plan || !ms_out || !launches_out) return fail(SHLR_E_INVALID_ARG, "NULL argument");
+    STCHK(timing_collect(plan));
+    for (int i = 0; i < SHLR_TIMING_PHASES; ++i) {
+        ms_out[i] = plan->t_ms[i];
+        launches_out[i] = plan->t_cnt[i];
     }
     return SHLR_OK;
 }

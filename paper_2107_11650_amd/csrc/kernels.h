@@ -45,6 +45,10 @@ hipError_t launch_xupd_rows(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>
                             cplx_t<R>* k, cplx_t<R>* out, const uint8_t* m, const R* rtab, const XupdRows& x,
                             double lam, double beta, int hard_dc, double* change_acc);
 template <typename R>
+hipError_t launch_xupd_rows_rhs(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>* a, const cplx_t<R>* y,
+                                cplx_t<R>* rhs, const uint8_t* m, const R* rtab, const XupdRows& x, double lam,
+                                double beta);
+template <typename R>
 hipError_t launch_scale_copy(hipStream_t st, const cplx_t<R>* in, cplx_t<R>* out, int64_t count,
                              const double* scale_ptr, int invert);
 template <typename R>

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
             const int col = Jb * 16 + li;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = Ib * 16 + lk * 4 + r;
+                const int row = Ib * 16 + acc_row<R>(lk, r);
                 if (row < s && col < s) {
                     double2 v = make_double2((double)accR[t][r], (double)accI[t][r]);
                     G[(int64_t)col * s + row] = v;
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
                 const int col = Jt * 16 + li;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int rloc = It * 16 + lk * 4 + r;
+                    const int rloc = It * 16 + acc_row<R>(lk, r);
                     const int row = r0 + rloc;
                     C rv = cmk<C>(0, 0);
                     if (row < l && col < s) {

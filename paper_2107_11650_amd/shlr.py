@@ -35,8 +35,9 @@ EXPORTED = [
     "shlr_plan_create", "shlr_plan_destroy", "shlr_workspace_size", "shlr_bind", "shlr_set_spirit_kernel",
     "shlr_calibrate_spirit", "shlr_init", "shlr_iterate", "shlr_iterate_graph", "shlr_get_kspace",
     "shlr_reconstruct", "shlr_fft_lines", "shlr_lowrank_workspace_size", "shlr_lowrank_lines",
-    "shlr_last_error", "shlr_version",
+    "shlr_last_error", "shlr_version", "shlr_timing_enable", "shlr_timing_read",
 ]
+TIMING_PHASES = ("xupdate", "gram", "eig", "reproj", "spirit")
 
 
 class ShlrError(RuntimeError):
@@ -81,6 +82,8 @@ _lib.shlr_fft_lines.argtypes = [_i32, _i32, _i32, _i32, _vp, _vp, _vp]
 _lib.shlr_lowrank_workspace_size.argtypes = [_i32, _i32, _i32, _i32, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)]
 _lib.shlr_lowrank_lines.argtypes = [_i32, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.shlr_timing_enable.argtypes = [_vp, _i32]
+_lib.shlr_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
 _lib.shlr_last_error.restype = ctypes.c_char_p
 _lib.shlr_version.restype = ctypes.c_char_p
 for _f in EXPORTED:
@@ -200,6 +203,16 @@ class Plan:
     def iterate_async(self, n, graph=False):
         f = _lib.shlr_iterate_graph if graph else _lib.shlr_iterate
         _check(f(self._h, int(n), None))
+
+    def timing_enable(self, on=True):
+        _check(_lib.shlr_timing_enable(self._h, int(on)))
+
+    def timing_read(self):
+        """Accumulated per-phase device time: {phase: (ms, launches)}."""
+        ms = (ctypes.c_double * len(TIMING_PHASES))()
+        cnt = (ctypes.c_int32 * len(TIMING_PHASES))()
+        _check(_lib.shlr_timing_read(self._h, ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(TIMING_PHASES)}
 
     def kspace(self, out=None):
         import torch

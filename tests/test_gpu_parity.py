@@ -111,10 +111,11 @@ def test_lowrank_step_zero_and_full_threshold():
     lift = O.LineLift(n, k, True, False)
     h = inputs.random_complex((B, J, n), seed=7)
     D = inputs.random_complex((B, lift.p, lift.q(J)), seed=8)
+    # tau != beta: with tau == beta and thr == 0 the new multiplier is exactly zero
     for thr in (0.0, 1e6):
-        Dn_ref, b_ref = O.lowrank_step(lift, h, D, 2.0, 2.0, thr)
+        Dn_ref, b_ref = O.lowrank_step(lift, h, D, 2.0, 1.0, thr)
         Dd = dev(D, torch.complex128)
-        b = shlr.lowrank_lines(dev(h, torch.complex128), Dd, k, 2.0, 2.0, thr)
+        b = shlr.lowrank_lines(dev(h, torch.complex128), Dd, k, 2.0, 1.0, thr)
         torch.cuda.synchronize()
         assert nmse(host(Dd), Dn_ref) < 1e-20
         assert nmse(host(b), b_ref) < 1e-20
@@ -242,4 +243,59 @@ def test_param_iterations(vc, prec, tol):
     out = run_param_gpu(Y, mask, prm, shlr.PREC_FP64 if prec == "fp64" else shlr.PREC_MIXED)
     e = nmse(out, ref)
     print(f"PARAM vc={vc} {prec}: nmse={e:.3e}", flush=True)
+    assert e < tol
+
+
+# ---------------------------------------------------------------------------
+# SPIRiT term (Eq. 3) with the PCG X-update
+# ---------------------------------------------------------------------------
+
+def spirit_problem(J=4, M=48, N=40, seed=7):
+    k = inputs.phantom_kspace(J, M, N, seed=1000 + seed)
+    mask = inputs.mask_poisson_disc(M, N, R=3.0, acs=16, seed=2000 + seed)
+    return inputs.undersample(k, mask), mask
+
+
+def run_spirit_gpu(Y, mask, prm, precision, g=None, acs=16):
+    shlr = _lib()
+    J, M, N = Y.shape
+    p = shlr.Params(M=(M,), N=(N,), J=J, k_row=prm.k_row, k_col=prm.k_col, use_vc=prm.vc, lam=prm.lam,
+                    lambda1=prm.lam1, beta=prm.beta, tau=prm.t(), n_cg=prm.n_cg, spirit_ksize=5,
+                    precision=precision, max_iter=prm.iters)
+    plan = shlr.Plan(p)
+    plan.init(dev(Y, plan.cdtype), dev(mask.astype(np.uint8), torch.uint8))
+    if g is not None:
+        plan.set_spirit_kernel(g)
+    else:
+        plan.calibrate_spirit(acs=acs, reg=1e-3)
+    plan.iterate(prm.iters)
+    out = host(plan.kspace())
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("vc", [False, True])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-20), ("mixed", 1e-5)])
+def test_spirit_given_kernel(vc, prec, tol):
+    shlr = _lib()
+    Y, mask = spirit_problem()
+    g = O.spirit_calibrate(Y / np.abs(Y).max(), acs=16, ks=5)
+    prm = O.PIParams(k_row=6, k_col=6, lam=1e4, lam1=10.0, beta=10.0, vc=vc, n_cg=6, iters=5)
+    ref = O.shlr_pi(Y, mask, prm, g=g)
+    out = run_spirit_gpu(Y, mask, prm, shlr.PREC_FP64 if prec == "fp64" else shlr.PREC_MIXED, g=g)
+    e = nmse(out, ref)
+    print(f"SPIRiT given kernel vc={vc} {prec}: nmse={e:.3e}", flush=True)
+    assert e < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-16), ("mixed", 1e-5)])
+def test_spirit_calibrated_on_device(prec, tol):
+    shlr = _lib()
+    Y, mask = spirit_problem(seed=8)
+    g = O.spirit_calibrate(Y / np.abs(Y).max(), acs=16, ks=5)
+    prm = O.PIParams(k_row=6, k_col=6, lam=1e4, lam1=10.0, beta=10.0, n_cg=6, iters=5)
+    ref = O.shlr_pi(Y, mask, prm, g=g)
+    out = run_spirit_gpu(Y, mask, prm, shlr.PREC_FP64 if prec == "fp64" else shlr.PREC_MIXED, g=None, acs=16)
+    e = nmse(out, ref)
+    print(f"SPIRiT calibrated {prec}: nmse={e:.3e}", flush=True)
     assert e < tol
