@@ -50,6 +50,60 @@ template <typename R> __device__ inline int acc_row(int lk, int r);
 template <> __device__ inline int acc_row<float>(int lk, int r) { return 4 * lk + r; }
 template <> __device__ inline int acc_row<double>(int lk, int r) { return lk + 4 * r; }
 
+// Sum of a double over the 64 lanes of a wave with DPP row shifts and row
+// broadcasts (no LDS traffic).  The total is valid in lane 63 only.
+__device__ inline double dpp_shift_d(double v, int ctrl_sel) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    int rlo, rhi;
+    switch (ctrl_sel) {
+        case 1: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xf, 0xf, true);
+                rhi = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xf, 0xf, true); break;   // row_shr:1
+        case 2: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x112, 0xf, 0xf, true);
+                rhi = __builtin_amdgcn_update_dpp(0, hi, 0x112, 0xf, 0xf, true); break;   // row_shr:2
+        case 4: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x114, 0xf, 0xf, true);
+                rhi = __builtin_amdgcn_update_dpp(0, hi, 0x114, 0xf, 0xf, true); break;   // row_shr:4
+        case 8: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x118, 0xf, 0xf, true);
+                rhi = __builtin_amdgcn_update_dpp(0, hi, 0x118, 0xf, 0xf, true); break;   // row_shr:8
+        case 15: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x142, 0xa, 0xf, false);
+                 rhi = __builtin_amdgcn_update_dpp(0, hi, 0x142, 0xa, 0xf, false); break;  // row_bcast:15
+        default: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x143, 0xc, 0xf, false);
+                 rhi = __builtin_amdgcn_update_dpp(0, hi, 0x143, 0xc, 0xf, false); break;  // row_bcast:31
+    }
+    return __hiloint2double(rhi, rlo);
+}
+__device__ inline double wave_sum_to63(double v) {
+    v += dpp_shift_d(v, 1);
+    v += dpp_shift_d(v, 2);
+    v += dpp_shift_d(v, 4);
+    v += dpp_shift_d(v, 8);
+    v += dpp_shift_d(v, 15);
+    v += dpp_shift_d(v, 31);
+    return v;
+}
+// the same total broadcast to every lane
+__device__ inline double wave_sum_all(double v) {
+    v = wave_sum_to63(v);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+// Raw buffer access (gfx9 descriptor): 32-bit byte offsets from a wave-uniform
+// base; an offset past the end reads 0 and a store there is dropped, which
+// gives branch-free masked memory operations.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr unsigned BUF_OOB = 0x7ffffff0u;   // an offset beyond any buffer used here
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline double2 buf_load_d2(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    return __builtin_bit_cast(double2, v);
+}
+__device__ inline void buf_store_d2(__amdgpu_buffer_rsrc_t r, unsigned off, double2 x) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x), r, (int)off, 0, 0);
+}
+
 // Geometry and addressing of one lifted matrix (one line of J coils).
 // Offsets count complex elements from the base pointers given to the kernels.
 struct LRDesc {
@@ -71,7 +125,11 @@ __host__ __device__ inline int lr_side(const LRDesc& d) { return lr_q(d) <= lr_p
 __host__ __device__ inline int lr_s(const LRDesc& d) { return lr_side(d) == 0 ? lr_q(d) : lr_p(d); }
 __host__ __device__ inline int lr_l(const LRDesc& d) { return lr_side(d) == 0 ? lr_p(d) : lr_q(d); }
 
+// Packed lower triangle of an s x s Hermitian matrix, column-major: entry (r, c), r >= c.
+__host__ __device__ inline int64_t pk(int r, int c, int s) { return (int64_t)c * (2 * s - c - 1) / 2 + r; }
+__host__ __device__ inline int64_t packed_size(int s) { return (int64_t)s * (s + 1) / 2; }
+
 // Per-slot scratch of the eigen-solver, in doubles, for matrices of order s.
-__host__ __device__ inline int64_t eig_scratch_doubles(int s) { return 7LL * s * s + 16LL * s + 64; }
+__host__ __device__ inline int64_t eig_scratch_doubles(int s) { return 3LL * s * s + 16LL * s + 64; }
 
 }  // namespace shlr

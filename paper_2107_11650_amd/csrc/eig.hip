@@ -10,8 +10,9 @@
 //     P = I - u u^H / h (the matrix lives in the per-slot scratch in HBM/L2);
 //  2. a diagonal unitary makes the off-diagonal real and non-negative;
 //  3. Sturm-sequence bisection for every eigenvalue above thr^2, in parallel;
-//  4. inverse iteration (tridiagonal LU with partial pivoting) per eigenvalue,
-//     eigenvalues closer than ortol are grouped and re-orthogonalised (MGS);
+//  4. eigenvectors from a twisted factorisation of T - lambda I per eigenvalue;
+//     eigenvalues closer than ortol are grouped, refined by inverse iteration
+//     and re-orthogonalised (MGS);
 //  5. back-transformation through the reflectors, scaling by sqrt(f), and
 //     S = X X^H written in the working precision (row-major, ld = s).
 #include <float.h>
@@ -20,7 +21,9 @@
 
 namespace shlr {
 
-constexpr int EIG_THREADS = 256;
+constexpr int EIG_THREADS = 512;
+constexpr int EIG_MAXS = 320;                    // largest supported order
+constexpr int EIG_STAGE = 6 + EIG_THREADS / 64;  // smax-sized double2 rows of LDS region A (staging)
 
 __device__ inline double block_sum(double v, double* red) {
     // all threads must call; returns the total to every thread
@@ -71,135 +74,261 @@ __device__ inline double start_entry(int i, int k) {
     return ((double)(x & 0xffffff) / (double)0xffffff) * 2.0 - 1.0;
 }
 
-template <typename OC>
-__global__ __launch_bounds__(EIG_THREADS) void k_heig_svt(const LRDesc* __restrict__ descs, int m0,
-                                                          double2* __restrict__ Gs, int64_t g_stride,
-                                                          OC* __restrict__ Ss, int64_t s_stride,
-                                                          double* __restrict__ scr, int64_t scr_stride,
-                                                          int32_t* __restrict__ ranks, double ortol_rel,
-                                                          uint32_t* __restrict__ flags) {
-    __shared__ double red[EIG_THREADS / 64];
-    __shared__ double2 uvec[512];
-    __shared__ double2 pvec[512];
-    __shared__ double sh[8];
-    __shared__ double sdd[512];
-    __shared__ double se2[512];
+template <typename OC, int SL>
+__global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __restrict__ descs, int m0,
+                                                             double2* __restrict__ Gs, int64_t g_stride,
+                                                             OC* __restrict__ Ss, int64_t s_stride,
+                                                             double* __restrict__ scr, int64_t scr_stride,
+                                                             int32_t* __restrict__ ranks, double ortol_rel,
+                                                             uint32_t* __restrict__ flags, int smax) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int UNR = SL <= 3 ? 4 : (SL == 4 ? 3 : 2);   // columns per wave with loads in flight
     const LRDesc dsc = descs[m0 + blockIdx.x];
     const int s = lr_s(dsc);
     const double thr = dsc.thr;
     const int tid = threadIdx.x;
-    double2* A = Gs + (int64_t)blockIdx.x * g_stride;   // column-major, ld = s
+    const int nw = EIG_THREADS / 64;
+    const int lane = tid & 63, wave = tid >> 6;
+    // LDS: region A (tridiagonalisation work, later staging) + small persistent arrays
+    double2* uvec = reinterpret_cast<double2*>(smem_raw);
+    double2* pvec = uvec + smax;
+    double2* up = pvec + smax;
+    double2* qp = up + smax;
+    double2* pcol = qp + smax;
+    double2* xraw = pcol + smax;
+    double2* prow = xraw + smax;                       // nw * smax
+    double2* stage = uvec;                             // region A reused: EIG_STAGE * smax double2
+    double* sdd = reinterpret_cast<double*>(prow + nw * smax);
+    double* se2 = sdd + smax;
+    double* see = se2 + smax;
+    double* shv = see + smax;
+    double* secr = shv + smax;
+    double* seci = secr + smax;
+    double* sdre = seci + smax;
+    double* sdim = sdre + smax;
+    double* slam = sdim + smax;
+    double* red = slam + smax;                         // nw
+    double* red2 = red + nw;                           // nw
+    double* sh = red2 + nw;                            // 8
+    double2* A = Gs + (int64_t)blockIdx.x * g_stride;   // packed lower triangle
     OC* S = Ss + (int64_t)blockIdx.x * s_stride;
     double* base = scr + (int64_t)blockIdx.x * scr_stride;
-    double* hv = base;                 // s
-    double* dd = hv + s;               // s
-    double* ee = dd + s;               // s
-    double* e2 = ee + s;               // s
-    double* dre = e2 + s;              // s   phase re
-    double* dim_ = dre + s;            // s   phase im
-    double* lam = dim_ + s;            // s
-    double* ecr = lam + s;             // s   complex sub-diagonal re
-    double* eci = ecr + s;             // s   complex sub-diagonal im
     double* W = base + 16 * s + 64;    // s*s interleaved [i*s + k]
-    double* LU = W + (int64_t)s * s;   // 5*s*s interleaved (du1, du2, lmul, u0, x)
-    double2* X = reinterpret_cast<double2*>(LU);  // s*s complex, reused after inverse iteration
+    double* LU = W + (int64_t)s * s;   // 2*s*s: X (double2, column-major) of the back-transform
 
-    // ---- 1. tridiagonalisation -------------------------------------------
+    // ---- 1. tridiagonalisation ---------------------------------------------
+    // Step i: x = column i below the diagonal, P_i = I - u u^H / h maps x to
+    // -phase |x| e_1, and the trailing block becomes A - u q^H - q u^H with
+    // p = A u / h, q = p - (u^H p / 2h) u.  The rank-2 update of step i is
+    // applied lazily during the Hermitian matrix-vector product of step i+1,
+    // which reads (and writes back) only the lower triangle, one column per
+    // wave with lanes over rows (coalesced).  The column that step i+1 reduces
+    // is captured during that sweep and finished in LDS, so each step makes a
+    // single round trip to memory.
+    double2* xcur = uvec;                      // x_i, then u_i
+    double2* xnxt = pvec;                      // x_{i+1} being formed
+    bool pend = false;
+    double part = 0;
+    for (int t = tid; t + 1 < s; t += EIG_THREADS) {
+        const double2 v = A[pk(1 + t, 0, s)];
+        xcur[t] = v;
+        if (t > 0) part += cabs2(v);
+    }
+    if (tid == 0) sdd[0] = A[pk(0, 0, s)].x;
+    double tail = block_sum(part, red);
     for (int i = 0; i + 1 < s; ++i) {
         const int ni = s - i - 1;
-        double part = 0;
-        for (int t = tid; t < ni; t += EIG_THREADS) {
-            double2 v = A[(int64_t)i * s + i + 1 + t];
-            uvec[t] = v;
-            if (t > 0) part += cabs2(v);
+        const double2 alpha = xcur[0];
+        const bool refl = tail > 0.0;
+        double hh = 1.0;
+        double2 ph = make_double2(1.0, 0.0);
+        double xn = 0.0;
+        if (refl) {
+            const double aabs = sqrt(cabs2(alpha));
+            xn = sqrt(aabs * aabs + tail);
+            if (aabs > 0) ph = make_double2(alpha.x / aabs, alpha.y / aabs);
+            hh = xn * xn + aabs * xn;
         }
-        const double tail = block_sum(part, red);  // has barriers
-        const double2 alpha = uvec[0];
-        if (tid == 0) dd[i] = A[(int64_t)i * s + i].x;
-        if (!(tail > 0.0)) {
-            if (tid == 0) { ecr[i] = alpha.x; eci[i] = alpha.y; hv[i] = 0.0; }
-            __syncthreads();
-            continue;
-        }
-        const double aabs = sqrt(cabs2(alpha));
-        const double xn = sqrt(aabs * aabs + tail);
-        double2 ph = aabs > 0 ? make_double2(alpha.x / aabs, alpha.y / aabs) : make_double2(1.0, 0.0);
-        const double hh = xn * xn + aabs * xn;
-        __syncthreads();
+        __syncthreads();   // every thread has read xcur[0]
         if (tid == 0) {
-            uvec[0] = make_double2(alpha.x + ph.x * xn, alpha.y + ph.y * xn);
-            ecr[i] = -ph.x * xn;
-            eci[i] = -ph.y * xn;
-            hv[i] = hh;
-        }
-        __syncthreads();
-        // p = A22 u / h
-        for (int r = tid; r < ni; r += EIG_THREADS) {
-            double ar = 0, ai = 0;
-            const double2* col = A + (int64_t)(i + 1) * s + i + 1 + r;
-            for (int c = 0; c < ni; ++c) {
-                const double2 a = col[(int64_t)c * s];
-                const double2 u = uvec[c];
-                ar += a.x * u.x - a.y * u.y;
-                ai += a.x * u.y + a.y * u.x;
+            if (refl) {
+                xcur[0] = make_double2(alpha.x + ph.x * xn, alpha.y + ph.y * xn);
+                secr[i] = -ph.x * xn;
+                seci[i] = -ph.y * xn;
+                shv[i] = hh;
+            } else {
+                secr[i] = alpha.x;
+                seci[i] = alpha.y;
+                shv[i] = 0.0;
             }
-            pvec[r] = make_double2(ar / hh, ai / hh);
         }
         __syncthreads();
-        // K = u^H p / (2h) (real)
-        double kp = 0;
-        for (int t = tid; t < ni; t += EIG_THREADS) kp += uvec[t].x * pvec[t].x + uvec[t].y * pvec[t].y;
-        const double Kc = block_sum(kp, red) / (2.0 * hh);
+        // fused sweep: trailing block -= pending update (written back); p = A u;
+        // column i+1 captured into xraw.  UNR columns per wave at a time with all
+        // their loads issued first; slots outside a column are skipped.
+        double2 accr[SL];
+#pragma unroll
+        for (int sl = 0; sl < SL; ++sl) accr[sl] = make_double2(0.0, 0.0);
+        double wur = 0;   // this wave's share of u^H (h p)
+        const int ncol = (pend || refl) ? ni : 1;
+        for (int tc0 = wave; tc0 < ncol; tc0 += UNR * nw) {
+            double2 av[UNR][SL];
+#pragma unroll
+            for (int uu = 0; uu < UNR; ++uu) {
+                const int tc = tc0 + uu * nw;
+#pragma unroll
+                for (int sl = 0; sl < SL; ++sl) {
+                    const int t = sl * 64 + lane;
+                    av[uu][sl] = make_double2(0.0, 0.0);
+                    if (tc < ncol && t >= tc && t < ni) av[uu][sl] = A[pk(i + 1 + t, i + 1 + tc, s)];
+                }
+            }
+            double pcr[UNR], pci[UNR];
+#pragma unroll
+            for (int uu = 0; uu < UNR; ++uu) {
+                pcr[uu] = 0;
+                pci[uu] = 0;
+                const int tc = tc0 + uu * nw;
+                if (tc >= ncol) continue;   // uniform across the wave
+                const int c = i + 1 + tc;
+                const double2 uc = refl ? xcur[tc] : make_double2(0.0, 0.0);
+                double2 upc = make_double2(0.0, 0.0), qpc = make_double2(0.0, 0.0);
+                if (pend) { upc = up[c]; qpc = qp[c]; }
+#pragma unroll
+                for (int sl = 0; sl < SL; ++sl) {
+                    const int t = sl * 64 + lane;
+                    if (t >= tc && t < ni) {
+                        const int r = i + 1 + t;
+                        double2 a = av[uu][sl];
+                        if (pend) {
+                            const double2 qr = qp[r], ur = up[r];
+                            a.x -= qr.x * upc.x + qr.y * upc.y + ur.x * qpc.x + ur.y * qpc.y;
+                            a.y -= qr.y * upc.x - qr.x * upc.y + ur.y * qpc.x - ur.x * qpc.y;
+                            if (tc > 0) A[pk(r, c, s)] = a;   // column i+1 is finished in LDS instead
+                        }
+                        if (tc == 0) xraw[t] = a;
+                        if (refl) {
+                            accr[sl].x += a.x * uc.x - a.y * uc.y;
+                            accr[sl].y += a.x * uc.y + a.y * uc.x;
+                            if (t > tc) {
+                                const double2 ut = xcur[t];
+                                pcr[uu] += a.x * ut.x + a.y * ut.y;   // conj(a) * u_t
+                                pci[uu] += a.x * ut.y - a.y * ut.x;
+                            }
+                        }
+                    }
+                }
+            }
+            if (refl) {
+#pragma unroll
+                for (int uu = 0; uu < UNR; ++uu) {
+                    pcr[uu] = wave_sum_to63(pcr[uu]);
+                    pci[uu] = wave_sum_to63(pci[uu]);
+                }
+                if (lane == 63) {
+#pragma unroll
+                    for (int uu = 0; uu < UNR; ++uu) {
+                        const int tc = tc0 + uu * nw;
+                        if (tc < ncol) {
+                            const double2 uc = xcur[tc];
+                            pcol[tc] = make_double2(pcr[uu], pci[uu]);
+                            wur += uc.x * pcr[uu] + uc.y * pci[uu];   // conj(u_tc) * pcol[tc]
+                        }
+                    }
+                }
+            }
+        }
+        if (refl) {
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) {
+                const int t = sl * 64 + lane;
+                if (t < ni) {
+                    prow[wave * smax + t] = accr[sl];
+                    const double2 ut = xcur[t];
+                    wur += ut.x * accr[sl].x + ut.y * accr[sl].y;
+                }
+            }
+            wur = wave_sum_to63(wur);
+            if (lane == 63) red2[wave] = wur;
+        }
+        __syncthreads();
+        // p, q = p - K u (the new pending update), u stored for the back-transform,
+        // and x_{i+1} = column i+1 with this step's update, plus its tail norm
+        double Kc = 0.0;
+        double2 q0 = make_double2(0.0, 0.0);
+        const double2 u0 = refl ? xcur[0] : make_double2(0.0, 0.0);
+        if (refl) {
+            double uhp = 0;
+            for (int w = 0; w < nw; ++w) uhp += red2[w];
+            Kc = uhp / (2.0 * hh * hh);
+            double pr = pcol[0].x, pi = pcol[0].y;
+            for (int w = 0; w < nw; ++w) {
+                pr += prow[w * smax].x;
+                pi += prow[w * smax].y;
+            }
+            q0 = make_double2(pr / hh - Kc * u0.x, pi / hh - Kc * u0.y);
+        }
+        part = 0;
         for (int t = tid; t < ni; t += EIG_THREADS) {
-            pvec[t].x -= Kc * uvec[t].x;
-            pvec[t].y -= Kc * uvec[t].y;
-        }
-        __syncthreads();
-        // A22 -= q u^H + u q^H ; store u in column i below the diagonal
-        for (int r = tid; r < ni; r += EIG_THREADS) {
-            const double2 qr = pvec[r], ur = uvec[r];
-            double2* col = A + (int64_t)(i + 1) * s + i + 1 + r;
-            for (int c = 0; c < ni; ++c) {
-                const double2 uc = uvec[c], qc = pvec[c];
-                double2 a = col[(int64_t)c * s];
-                // q_r conj(u_c) + u_r conj(q_c)
-                a.x -= qr.x * uc.x + qr.y * uc.y + ur.x * qc.x + ur.y * qc.y;
-                a.y -= qr.y * uc.x - qr.x * uc.y + ur.y * qc.x - ur.x * qc.y;
-                col[(int64_t)c * s] = a;
+            const int r = i + 1 + t;
+            double2 u = make_double2(0.0, 0.0), q = make_double2(0.0, 0.0);
+            if (refl) {
+                u = xcur[t];
+                double pr = pcol[t].x, pi = pcol[t].y;
+                for (int w = 0; w < nw; ++w) {
+                    pr += prow[w * smax + t].x;
+                    pi += prow[w * smax + t].y;
+                }
+                q = make_double2(pr / hh - Kc * u.x, pi / hh - Kc * u.y);
+                up[r] = u;
+                qp[r] = q;
+                A[pk(r, i, s)] = u;
             }
-            A[(int64_t)i * s + i + 1 + r] = ur;
+            double2 x = xraw[t];
+            // (q_r conj(u_c) + u_r conj(q_c)) at c = i + 1
+            x.x -= q.x * u0.x + q.y * u0.y + u.x * q0.x + u.y * q0.y;
+            x.y -= q.y * u0.x - q.x * u0.y + u.y * q0.x - u.x * q0.y;
+            if (t == 0) sdd[i + 1] = x.x;
+            else {
+                xnxt[t - 1] = x;
+                if (t > 1) part += cabs2(x);
+            }
         }
-        __syncthreads();
+        tail = block_sum(part, red);   // its barriers also publish xnxt, up, qp
+        double2* tmp = xcur;
+        xcur = xnxt;
+        xnxt = tmp;
+        pend = refl;
     }
-    if (tid == 0) dd[s - 1] = A[(int64_t)(s - 1) * s + s - 1].x;
     __syncthreads();
 
-    // ---- 2. real tridiagonal via a diagonal unitary --------------------------
+    // ---- 2. real tridiagonal via a diagonal unitary ------------------------------
     if (tid == 0) {
         double pr = 1.0, pi = 0.0;
-        dre[0] = 1.0;
-        dim_[0] = 0.0;
+        sdre[0] = 1.0;
+        sdim[0] = 0.0;
         for (int i = 0; i + 1 < s; ++i) {
-            const double er = ecr[i], ei = eci[i];
+            const double er = secr[i], ei = seci[i];
             const double m = sqrt(er * er + ei * ei);
-            ee[i] = m;
-            e2[i] = m * m;
+            see[i] = m;
+            se2[i] = m * m;
             if (m > 0) {
                 const double ur = er / m, ui = ei / m;
                 const double nr = pr * ur - pi * ui, ni2 = pr * ui + pi * ur;
                 pr = nr;
                 pi = ni2;
             }
-            dre[i + 1] = pr;
-            dim_[i + 1] = pi;
+            sdre[i + 1] = pr;
+            sdim[i + 1] = pi;
         }
-        // Gershgorin bounds and scale
+        see[s - 1] = 0.0;
+        se2[s - 1] = 0.0;
         double gl = DBL_MAX, gu = -DBL_MAX, emax2 = 0;
         for (int i = 0; i < s; ++i) {
-            const double off = (i > 0 ? ee[i - 1] : 0.0) + (i + 1 < s ? ee[i] : 0.0);
-            gl = fmin(gl, dd[i] - off);
-            gu = fmax(gu, dd[i] + off);
-            if (i + 1 < s) emax2 = fmax(emax2, e2[i]);
+            const double off = (i > 0 ? see[i - 1] : 0.0) + (i + 1 < s ? see[i] : 0.0);
+            gl = fmin(gl, sdd[i] - off);
+            gu = fmax(gu, sdd[i] + off);
+            if (i + 1 < s) emax2 = fmax(emax2, se2[i]);
         }
         const double tnorm = fmax(fabs(gl), fabs(gu));
         sh[0] = gl;
@@ -208,203 +337,300 @@ __global__ __launch_bounds__(EIG_THREADS) void k_heig_svt(const LRDesc* __restri
         sh[3] = DBL_MIN * fmax(1.0, emax2) * 4.0 + DBL_MIN;
     }
     __syncthreads();
-    for (int t = tid; t < s; t += EIG_THREADS) {
-        sdd[t] = dd[t];
-        se2[t] = (t + 1 < s) ? e2[t] : 0.0;
-    }
-    __syncthreads();
-    const double gl = sh[0], gu = sh[1], tnorm = sh[2], pivmin = sh[3];
-    (void)gl;
-    bool bad = !(tnorm < DBL_MAX);  // NaN or Inf in the Gram matrix
+    const double gu = sh[1], tnorm = sh[2], pivmin = sh[3];
+    const bool bad = !(tnorm < DBL_MAX);  // NaN or Inf in the Gram matrix
     const double t2 = thr * thr;
 
-    // ---- 3. eigenvalues above thr^2 ------------------------------------------
+    // ---- 3. eigenvalues above thr^2: multisection ---------------------------------
+    // A group of G lanes (a power of two <= 64) brackets one eigenvalue: each
+    // lane counts at one of G interior points, which shrinks the bracket by a
+    // factor G + 1 per round.
     int nabove = 0;
     if (!bad) nabove = s - sturm_count(sdd, se2, s, t2, pivmin);
-    const double slack = 2.0 * DBL_EPSILON * tnorm + pivmin;
-    for (int kk = tid; kk < nabove; kk += EIG_THREADS) {
-        const int idx = s - nabove + kk;   // ascending index
-        double lo = t2, hi = gu + slack + fabs(gu) * 4.0 * DBL_EPSILON;
-        for (int it = 0; it < 128; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin || mid == lo || mid == hi) break;
-            if (sturm_count(sdd, se2, s, mid, pivmin) > idx) hi = mid;
-            else lo = mid;
+    {
+        int G = 64;
+        while (G > 1 && G * nabove > EIG_THREADS) G >>= 1;
+        const int ngroups = EIG_THREADS / G;
+        const int grp = tid / G, gl_ = tid % G;
+        const double slack = 2.0 * DBL_EPSILON * tnorm + pivmin;
+        for (int k0 = 0; k0 < nabove; k0 += ngroups) {   // uniform trip count
+            const int kk = k0 + grp;
+            const bool act = kk < nabove;
+            const int idx = s - nabove + (act ? kk : 0);   // ascending index
+            double lo = t2, hi = gu + slack + fabs(gu) * 4.0 * DBL_EPSILON;
+            for (int it = 0; it < 80; ++it) {
+                const double width = hi - lo;
+                bool done = !(width > 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin);
+                // the whole wave iterates while any of its groups is active
+                const double step = width / (double)(G + 1);
+                const double x = lo + step * (double)(gl_ + 1);
+                int le = (act && !done && x > lo && x < hi) ? (sturm_count(sdd, se2, s, x, pivmin) <= idx) : 1;
+                // number of points with count <= idx in the group (counts are monotone in x)
+                int nle = le;
+                for (int off = 1; off < G; off <<= 1) nle += __shfl_xor(nle, off, 64);
+                if (!done) {
+                    const double nlo = nle > 0 ? lo + step * (double)nle : lo;
+                    const double nhi = nle < G ? lo + step * (double)(nle + 1) : hi;
+                    if (!(nlo > lo || nhi < hi)) done = true;   // no progress possible
+                    lo = nlo;
+                    hi = fmin(nhi, hi);
+                }
+                const bool any = __any(!done && act);
+                if (!any) break;
+            }
+            if (act && gl_ == 0) slam[kk] = 0.5 * (lo + hi);
         }
-        lam[kk] = 0.5 * (lo + hi);
     }
     __syncthreads();
 
-    // ---- 4. inverse iteration, clusters re-orthogonalised --------------------
+    // ---- 4. eigenvectors by twisted factorisation, in LDS ----------------------
+    // For an accurate eigenvalue lk of the tridiagonal T (diagonal sdd, off-
+    // diagonal see): T - lk I = L D+ L^T (forward) = U D- U^T (backward);
+    // gamma_i = D+_i + D-_i - (d_i - lk) is smallest at the twist r, and
+    // z_r = 1, z_i = -L_i z_{i+1} (i < r), z_{i+1} = -U_i z_i (i >= r) solves
+    // (T - lk I) z = gamma_r e_r.  Eigenvalues closer than ortol form a cluster
+    // handled by one thread: each later member is refined by two steps of
+    // inverse iteration with the L D+ L^T factors, each followed by modified
+    // Gram-Schmidt against the earlier members.  Region A of LDS holds
+    // 4 s + 1 doubles (odd stride against bank conflicts) per thread of a batch.
     const double ortol = ortol_rel * tnorm;
-    const int64_t ss = (int64_t)s * s;
-    double* du1 = LU;
-    double* du2 = LU + ss;
-    double* lmul = LU + 2 * ss;
-    double* u0 = LU + 3 * ss;
-    double* xv = LU + 4 * ss;
-    for (int kk = tid; kk < nabove; kk += EIG_THREADS) {
-        if (kk > 0 && lam[kk] - lam[kk - 1] <= ortol) continue;   // not a cluster leader
-        int kend = kk + 1;
-        while (kend < nabove && lam[kend] - lam[kend - 1] <= ortol) ++kend;
-        double prev = 0;
-        for (int k = kk; k < kend; ++k) {
-            double lk = lam[k];
-            if (k > kk) {
-                const double pertol = 10.0 * DBL_EPSILON * fmax(fabs(lk), tnorm * 1e-3);
-                if (lk - prev < pertol) lk = prev + pertol;
-            }
-            prev = lk;
-            // LU with partial pivoting of T - lk I; column k of the interleaved arrays
-            double dcur = dd[0] - lk;
-            double ucur = s > 1 ? ee[0] : 0.0;
-            const double tiny = DBL_EPSILON * tnorm + pivmin;
-            for (int i = 0; i + 1 < s; ++i) {
-                const double c = ee[i];                   // sub-diagonal below row i
-                const double a1 = dd[i + 1] - lk;
-                const double b1 = (i + 2 < s) ? ee[i + 1] : 0.0;
-                if (fabs(dcur) >= fabs(c)) {
-                    double a = dcur == 0.0 ? tiny : dcur;
-                    const double f = c / a;
-                    u0[(int64_t)i * s + k] = a;
-                    du1[(int64_t)i * s + k] = ucur;
-                    du2[(int64_t)i * s + k] = 0.0;
-                    lmul[(int64_t)i * s + k] = f;          // positive sign: no row swap
-                    dcur = a1 - f * ucur;
-                    ucur = b1;
-                } else {
-                    const double f = dcur / c;
-                    u0[(int64_t)i * s + k] = c;
-                    du1[(int64_t)i * s + k] = a1;
-                    du2[(int64_t)i * s + k] = b1;
-                    lmul[(int64_t)i * s + k] = -(f + 4.0);   // encodes a swap; f in [-1, 1]
-                    dcur = ucur - f * a1;
-                    ucur = -f * b1;
-                }
-            }
-            u0[(int64_t)(s - 1) * s + k] = dcur == 0.0 ? tiny : dcur;
-            // start vector
-            for (int i = 0; i < s; ++i) xv[(int64_t)i * s + k] = start_entry(i, k);
-            for (int it = 0; it < 3; ++it) {
-                // forward: apply the row operations
-                for (int i = 0; i + 1 < s; ++i) {
-                    const double lm = lmul[(int64_t)i * s + k];
-                    double yi = xv[(int64_t)i * s + k], yi1 = xv[(int64_t)(i + 1) * s + k];
-                    if (lm <= -3.0) {  // swapped
-                        const double f = -lm - 4.0;
-                        const double t = yi;
-                        yi = yi1;
-                        yi1 = t - f * yi;
-                    } else {
-                        yi1 -= lm * yi;
+    {
+        double* wsd = reinterpret_cast<double*>(stage);
+        const int wstride = 4 * s + 1;
+        const int cap = max(1, (EIG_STAGE * smax * 2) / wstride);
+        int nlead = 0;
+        for (int k = 0; k < nabove; ++k) nlead += (k == 0 || slam[k] - slam[k - 1] > ortol);
+        const bool leader = tid < nabove && (tid == 0 || slam[tid] - slam[tid - 1] > ortol);
+        int rank = 0;
+        if (leader)
+            for (int k = 1; k <= tid; ++k) rank += (slam[k] - slam[k - 1] > ortol);
+        for (int r0 = 0; r0 < nlead; r0 += cap) {
+            if (leader && rank >= r0 && rank < r0 + cap) {
+                double* Lf = wsd + (int64_t)(rank - r0) * wstride;
+                double* Dp = Lf + s;
+                double* Uf = Dp + s;
+                double* z = Uf + s;
+                int kend = tid + 1;
+                while (kend < nabove && slam[kend] - slam[kend - 1] <= ortol) ++kend;
+                double prev = 0;
+                for (int k = tid; k < kend; ++k) {
+                    double lk = slam[k];
+                    if (k > tid) {
+                        const double pertol = 10.0 * DBL_EPSILON * fmax(fabs(lk), tnorm * 1e-3);
+                        if (lk - prev < pertol) lk = prev + pertol;
                     }
-                    xv[(int64_t)i * s + k] = yi;
-                    xv[(int64_t)(i + 1) * s + k] = yi1;
+                    prev = lk;
+                    // forward: D+ and L
+                    double dp = sdd[0] - lk;
+                    for (int i = 0; i + 1 < s; ++i) {
+                        if (fabs(dp) < pivmin) dp = -pivmin;
+                        Dp[i] = dp;
+                        const double l = see[i] / dp;
+                        Lf[i] = l;
+                        dp = sdd[i + 1] - lk - l * see[i];
+                    }
+                    if (fabs(dp) < pivmin) dp = -pivmin;
+                    Dp[s - 1] = dp;
+                    // backward: D-, U and the twist
+                    double dm = sdd[s - 1] - lk;
+                    int twist = s - 1;
+                    double gbest = fabs(Dp[s - 1]);
+                    for (int i = s - 2; i >= 0; --i) {
+                        if (fabs(dm) < pivmin) dm = -pivmin;
+                        const double u = see[i] / dm;
+                        Uf[i] = u;
+                        dm = sdd[i] - lk - u * see[i];
+                        const double g = fabs(Dp[i] + dm - (sdd[i] - lk));
+                        if (g < gbest) {
+                            gbest = g;
+                            twist = i;
+                        }
+                    }
+                    z[twist] = 1.0;
+                    for (int i = twist - 1; i >= 0; --i) z[i] = -Lf[i] * z[i + 1];
+                    for (int i = twist; i + 1 < s; ++i) z[i + 1] = -Uf[i] * z[i];
+                    const int nref = k > tid ? 2 : 0;
+                    for (int it = 0; it <= nref; ++it) {
+                        if (it > 0) {
+                            // z <- (L D+ L^T)^{-1} z
+                            for (int i = 0; i + 1 < s; ++i) z[i + 1] -= Lf[i] * z[i];
+                            for (int i = 0; i < s; ++i) z[i] /= Dp[i];
+                            for (int i = s - 2; i >= 0; --i) z[i] -= Lf[i] * z[i + 1];
+                        }
+                        double amax = 0;
+                        for (int i = 0; i < s; ++i) amax = fmax(amax, fabs(z[i]));
+                        if (!(amax > 0) || !(amax < DBL_MAX)) {
+                            for (int i = 0; i < s; ++i) z[i] = start_entry(i, k + it + 1);
+                            amax = 1.0;
+                        }
+                        for (int i = 0; i < s; ++i) z[i] /= amax;
+                        for (int k2 = tid; k2 < k; ++k2) {
+                            double dot = 0;
+                            for (int i = 0; i < s; ++i) dot += W[(int64_t)i * s + k2] * z[i];
+                            for (int i = 0; i < s; ++i) z[i] -= dot * W[(int64_t)i * s + k2];
+                        }
+                        double nrm = 0;
+                        for (int i = 0; i < s; ++i) nrm += z[i] * z[i];
+                        nrm = nrm > 0 ? 1.0 / sqrt(nrm) : 0.0;
+                        for (int i = 0; i < s; ++i) z[i] *= nrm;
+                    }
+                    for (int i = 0; i < s; ++i) W[(int64_t)i * s + k] = z[i];
                 }
-                // back substitution
-                double x1 = 0, x2 = 0;
-                for (int i = s - 1; i >= 0; --i) {
-                    double v = xv[(int64_t)i * s + k];
-                    if (i + 1 < s) v -= du1[(int64_t)i * s + k] * x1;
-                    if (i + 2 < s) v -= du2[(int64_t)i * s + k] * x2;
-                    v /= u0[(int64_t)i * s + k];
-                    xv[(int64_t)i * s + k] = v;
-                    x2 = x1;
-                    x1 = v;
-                }
-                // re-orthogonalise against earlier members of the cluster
-                for (int k2 = kk; k2 < k; ++k2) {
-                    double dot = 0;
-                    for (int i = 0; i < s; ++i) dot += W[(int64_t)i * s + k2] * xv[(int64_t)i * s + k];
-                    for (int i = 0; i < s; ++i) xv[(int64_t)i * s + k] -= dot * W[(int64_t)i * s + k2];
-                }
-                double nrm = 0, amax = 0;
-                for (int i = 0; i < s; ++i) amax = fmax(amax, fabs(xv[(int64_t)i * s + k]));
-                if (!(amax > 0) || !(amax < DBL_MAX)) {
-                    for (int i = 0; i < s; ++i) xv[(int64_t)i * s + k] = start_entry(i, k + 7 * it + 1);
-                    continue;
-                }
-                for (int i = 0; i < s; ++i) {
-                    const double v = xv[(int64_t)i * s + k] / amax;
-                    nrm += v * v;
-                }
-                nrm = 1.0 / (amax * sqrt(nrm));
-                for (int i = 0; i < s; ++i) xv[(int64_t)i * s + k] *= nrm;
             }
-            for (int i = 0; i < s; ++i) W[(int64_t)i * s + k] = xv[(int64_t)i * s + k];
+            __syncthreads();
         }
     }
     __syncthreads();
 
     // ---- 5. back-transform: X = Q diag(phase) W sqrt(f) ----------------------
+    // X is column-major in the (now free) LU region.  Reflectors are staged in
+    // LDS in chunks shared by all waves; one wave per eigenvector, lane l owns
+    // rows l, l + 64, ... in registers.
     const int r = nabove;
+    double2* X = reinterpret_cast<double2*>(LU);
     for (int e = tid; e < s * r; e += EIG_THREADS) {
-        const int i = e / r, k = e - i * r;
-        const double sig = sqrt(fmax(lam[k], 0.0));
+        const int k = e / s, row = e - k * s;
+        const double sig = sqrt(fmax(slam[k], 0.0));
         const double f = sig > 0 ? fmax(1.0 - thr / sig, 0.0) : 0.0;
-        const double w = W[(int64_t)i * s + k] * sqrt(f);
-        X[(int64_t)i * s + k] = make_double2(dre[i] * w, dim_[i] * w);
+        const double w = W[(int64_t)row * s + k] * sqrt(f);
+        X[(int64_t)k * s + row] = make_double2(sdre[row] * w, sdim[row] * w);
+    }
+    for (int i1 = s - 2; i1 >= 0 && r > 0; i1 -= EIG_STAGE) {
+        const int i0 = max(0, i1 - EIG_STAGE + 1);   // reflectors i1, i1-1, ..., i0
+        __syncthreads();
+        for (int e = tid; e < (i1 - i0 + 1) * s; e += EIG_THREADS) {
+            const int j = e / s, row = e - j * s;
+            const int i = i1 - j;
+            stage[j * smax + row] = (row > i && shv[i] > 0) ? A[pk(row, i, s)] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        for (int k = wave; k < r; k += nw) {
+            double2 xr[SL];
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) {
+                const int row = sl * 64 + lane;
+                xr[sl] = row < s ? X[(int64_t)k * s + row] : make_double2(0.0, 0.0);
+            }
+            for (int j = 0; j <= i1 - i0; ++j) {
+                const int i = i1 - j;
+                const double hh = shv[i];
+                if (!(hh > 0)) continue;
+                double dr = 0, di = 0;
+                double2 ul[SL];
+#pragma unroll
+                for (int sl = 0; sl < SL; ++sl) {
+                    const int row = sl * 64 + lane;
+                    ul[sl] = row < s ? stage[j * smax + row] : make_double2(0.0, 0.0);
+                    dr += ul[sl].x * xr[sl].x + ul[sl].y * xr[sl].y;
+                    di += ul[sl].x * xr[sl].y - ul[sl].y * xr[sl].x;
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    dr += __shfl_xor(dr, off, 64);
+                    di += __shfl_xor(di, off, 64);
+                }
+                dr /= hh;
+                di /= hh;
+#pragma unroll
+                for (int sl = 0; sl < SL; ++sl) {
+                    xr[sl].x -= ul[sl].x * dr - ul[sl].y * di;
+                    xr[sl].y -= ul[sl].x * di + ul[sl].y * dr;
+                }
+            }
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) {
+                const int row = sl * 64 + lane;
+                if (row < s) X[(int64_t)k * s + row] = xr[sl];
+            }
+        }
     }
     __syncthreads();
-    for (int i = s - 2; i >= 0 && r > 0; --i) {
-        const double hh = hv[i];
-        if (!(hh > 0)) continue;     // uniform: hv is in global memory, same for all threads
-        const int ni = s - i - 1;
-        for (int t = tid; t < ni; t += EIG_THREADS) uvec[t] = A[(int64_t)i * s + i + 1 + t];
+    // ---- 6. S = X X^H (row-major, ld = s) ------------------------------------
+    // X is staged in LDS in column chunks; the lower triangle is accumulated in
+    // FP64 (in the now free packed Gram storage when several chunks are needed).
+    const int kc = (EIG_STAGE * smax) / max(s, 1);
+    const int64_t ntri = (int64_t)s * (s + 1) / 2;
+    for (int k0 = 0; k0 < r; k0 += kc) {
+        const int k1 = min(r, k0 + kc);
         __syncthreads();
-        for (int k = tid; k < r; k += EIG_THREADS) {
-            double dr = 0, di = 0;
-            for (int t = 0; t < ni; ++t) {
-                const double2 u = uvec[t], x = X[(int64_t)(i + 1 + t) * s + k];
-                dr += u.x * x.x + u.y * x.y;
-                di += u.x * x.y - u.y * x.x;
+        for (int e = tid; e < (k1 - k0) * s; e += EIG_THREADS) stage[e] = X[(int64_t)k0 * s + e];
+        __syncthreads();
+        for (int64_t e = tid; e < ntri; e += EIG_THREADS) {
+            // e -> (a, b), a >= b, column-major packed
+            int b = (int)((2.0 * s + 1.0 - sqrt((2.0 * s + 1.0) * (2.0 * s + 1.0) - 8.0 * (double)e)) * 0.5);
+            if (b < 0) b = 0;
+            if (b > s - 1) b = s - 1;
+            while (b > 0 && pk(b, b, s) > e) --b;
+            while (b + 1 < s && pk(b + 1, b + 1, s) <= e) ++b;
+            const int a = (int)(e - pk(b, b, s)) + b;
+            double sr = 0, si = 0;
+            for (int k = 0; k < k1 - k0; ++k) {
+                const double2 xa = stage[k * s + a], xb = stage[k * s + b];
+                sr += xa.x * xb.x + xa.y * xb.y;
+                si += xa.y * xb.x - xa.x * xb.y;
             }
-            dr /= hh;
-            di /= hh;
-            for (int t = 0; t < ni; ++t) {
-                const double2 u = uvec[t];
-                double2 x = X[(int64_t)(i + 1 + t) * s + k];
-                x.x -= u.x * dr - u.y * di;
-                x.y -= u.x * di + u.y * dr;
-                X[(int64_t)(i + 1 + t) * s + k] = x;
+            if (k0 > 0) {
+                const double2 o = A[e];
+                sr += o.x;
+                si += o.y;
+            }
+            if (k1 < r) {
+                A[e] = make_double2(sr, si);
+            } else {
+                OC o;
+                o.x = sr;
+                o.y = si;
+                S[(int64_t)a * s + b] = o;
+                o.y = -si;
+                S[(int64_t)b * s + a] = o;
             }
         }
-        __syncthreads();
     }
-    // ---- 6. S = X X^H ---------------------------------------------------------
-    for (int e = tid; e < s * s; e += EIG_THREADS) {
-        const int a = e / s, b = e - a * s;
-        double sr = 0, si = 0;
-        for (int k = 0; k < r; ++k) {
-            const double2 xa = X[(int64_t)a * s + k], xb = X[(int64_t)b * s + k];
-            sr += xa.x * xb.x + xa.y * xb.y;
-            si += xa.y * xb.x - xa.x * xb.y;
+    if (r == 0) {
+        for (int e = tid; e < s * s; e += EIG_THREADS) {
+            OC o;
+            o.x = 0;
+            o.y = 0;
+            S[e] = o;
         }
-        OC o;
-        o.x = sr;
-        o.y = si;
-        S[(int64_t)a * s + b] = o;
     }
     if (tid == 0) {
         int pos = 0;
-        for (int k = 0; k < r; ++k) pos += sqrt(fmax(lam[k], 0.0)) > thr;
+        for (int k = 0; k < r; ++k) pos += sqrt(fmax(slam[k], 0.0)) > thr;
         if (ranks) ranks[m0 + blockIdx.x] = pos;
         if (bad && flags) atomicOr(flags, 1u);
     }
 }
 
+// dynamic LDS bytes of k_heig_svt for matrices of order <= smax
+static size_t heig_lds_bytes(int smax) {
+    const int nw = EIG_THREADS / 64;
+    return (size_t)(6 + nw) * smax * sizeof(double2) + (size_t)9 * smax * sizeof(double) + (2 * nw + 8) * sizeof(double);
+}
+
 template <typename OC>
 hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
                            OC* Ss, int64_t s_stride, double* scr, int64_t scr_stride, int32_t* ranks,
-                           double ortol_rel, uint32_t* flags) {
-    hipLaunchKernelGGL((k_heig_svt<OC>), dim3(count), dim3(EIG_THREADS), 0, st, descs, m0, Gs, g_stride, Ss, s_stride,
-                       scr, scr_stride, ranks, ortol_rel, flags);
+                           double ortol_rel, uint32_t* flags, int smax) {
+    const size_t lds = heig_lds_bytes(smax);
+    const int sl = (smax + 63) / 64;
+    const void* fn = sl <= 1 ? (const void*)k_heig_svt<OC, 1>
+                   : sl == 2 ? (const void*)k_heig_svt<OC, 2>
+                   : sl == 3 ? (const void*)k_heig_svt<OC, 3>
+                   : sl == 4 ? (const void*)k_heig_svt<OC, 4>
+                             : (const void*)k_heig_svt<OC, 5>;
+    if (sl > 5) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    void* args[] = {(void*)&descs, (void*)&m0, (void*)&Gs, (void*)&g_stride, (void*)&Ss, (void*)&s_stride, (void*)&scr,
+                    (void*)&scr_stride, (void*)&ranks, (void*)&ortol_rel, (void*)&flags, (void*)&smax};
+    e = hipLaunchKernel(fn, dim3(count), dim3(EIG_THREADS), args, lds, st);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
 template hipError_t launch_heig_svt<float2>(hipStream_t, const LRDesc*, int, int, double2*, int64_t, float2*, int64_t,
-                                            double*, int64_t, int32_t*, double, uint32_t*);
+                                            double*, int64_t, int32_t*, double, uint32_t*, int);
 template hipError_t launch_heig_svt<double2>(hipStream_t, const LRDesc*, int, int, double2*, int64_t, double2*,
-                                             int64_t, double*, int64_t, int32_t*, double, uint32_t*);
+                                             int64_t, double*, int64_t, int32_t*, double, uint32_t*, int);
 
 }  // namespace shlr

@@ -280,7 +280,7 @@ static const size_t SLOT_BUDGET = (size_t)3 << 30;   // eigen-solver scratch for
 
 static void layout_slots(shlr_plan* P, int n_mat) {
     const int s = P->s_max;
-    P->g_stride = (int64_t)s * s;                       // double2
+    P->g_stride = packed_size(s);                       // double2, packed lower triangle
     P->s_stride = (int64_t)s * s;                       // working complex
     P->scr_stride = eig_scratch_doubles(s);             // doubles
     const size_t per = P->g_stride * 16 + P->s_stride * P->csize + P->scr_stride * 8 + 3 * 256;
@@ -453,9 +453,7 @@ extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
         P->groups.push_back(g);
     }
     for (auto& d : P->descs) P->s_max = std::max(P->s_max, lr_s(d));
-    int maxcount = 0;
-    for (auto& g : P->groups) maxcount = std::max(maxcount, g.count);
-    layout_slots(P, maxcount);
+    layout_slots(P, (int)P->descs.size());
     // workspace
     size_t off = 0;
     P->off_c = off;
@@ -588,25 +586,37 @@ template <typename R>
 static shlr_status run_lowrank_groups(shlr_plan* P, const std::vector<LRGroup>& groups, cplx_t<R>* hb, cplx_t<R>* db,
                                       cplx_t<R>* bb, const cplx_t<R>* wtab, LRDesc* desc_dev, double2* G,
                                       cplx_t<R>* S, double* scr, int32_t* ranks, uint32_t* flags, int n_slots,
-                                      int64_t g_stride, int64_t s_stride, int64_t scr_stride) {
+                                      int64_t g_stride, int64_t s_stride, int64_t scr_stride, int smax) {
+    // The descriptors of all groups are contiguous.  Chunks of up to n_slots
+    // matrices: the Gram products of every group segment in the chunk, then one
+    // eigen-solver launch over the whole chunk, then the reprojections.
     const double ortol = ortol_for(P);
-    for (const LRGroup& g : groups) {
-        for (int c0 = 0; c0 < g.count; c0 += n_slots) {
-            const int cnt = std::min(n_slots, g.count - c0);
-            const int m0 = g.first + c0;
-            size_t e0 = 0;
-            STCHK(phase_begin(P, &e0));
-            HIPCHK(launch_lift_gram<R>(P->stream, hb, db, wtab, desc_dev, g.proto, m0, cnt, G, g_stride, P->p.beta));
-            STCHK(phase_end(P, 1, e0));
-            STCHK(phase_begin(P, &e0));
-            HIPCHK(launch_heig_svt<cplx_t<R>>(P->stream, desc_dev, m0, cnt, G, g_stride, S, s_stride, scr, scr_stride,
-                                              ranks, ortol, flags));
-            STCHK(phase_end(P, 2, e0));
-            STCHK(phase_begin(P, &e0));
-            HIPCHK(launch_reproj<R>(P->stream, hb, db, bb, wtab, desc_dev, g.proto, m0, cnt, S, s_stride, P->p.beta,
-                                    P->p.tau));
-            STCHK(phase_end(P, 3, e0));
+    if (groups.empty()) return SHLR_OK;
+    const int first = groups.front().first;
+    const int total = groups.back().first + groups.back().count - first;
+    for (int c0 = first; c0 < first + total; c0 += n_slots) {
+        const int c1 = std::min(first + total, c0 + n_slots);
+        size_t e0 = 0;
+        STCHK(phase_begin(P, &e0));
+        for (const LRGroup& g : groups) {
+            const int s0 = std::max(c0, g.first), s1 = std::min(c1, g.first + g.count);
+            if (s0 >= s1) continue;
+            HIPCHK(launch_lift_gram<R>(P->stream, hb, db, wtab, desc_dev, g.proto, s0, s1 - s0,
+                                       G + (int64_t)(s0 - c0) * g_stride, g_stride, P->p.beta));
         }
+        STCHK(phase_end(P, 1, e0));
+        STCHK(phase_begin(P, &e0));
+        HIPCHK(launch_heig_svt<cplx_t<R>>(P->stream, desc_dev, c0, c1 - c0, G, g_stride, S, s_stride, scr, scr_stride,
+                                          ranks, ortol, flags, smax));
+        STCHK(phase_end(P, 2, e0));
+        STCHK(phase_begin(P, &e0));
+        for (const LRGroup& g : groups) {
+            const int s0 = std::max(c0, g.first), s1 = std::min(c1, g.first + g.count);
+            if (s0 >= s1) continue;
+            HIPCHK(launch_reproj<R>(P->stream, hb, db, bb, wtab, desc_dev, g.proto, s0, s1 - s0,
+                                    S + (int64_t)(s0 - c0) * s_stride, s_stride, P->p.beta, P->p.tau));
+        }
+        STCHK(phase_end(P, 3, e0));
     }
     return SHLR_OK;
 }
@@ -674,7 +684,7 @@ static shlr_status iterate_once(shlr_plan* P, bool track_change) {
     }
     STCHK(phase_end(P, 0, e0));
     STCHK(run_lowrank_groups<R>(P, P->groups, Q.c, Q.c, Q.c, Q.c, Q.desc, Q.g, Q.s, Q.scr, Q.ranks, Q.flags,
-                                P->n_slots, P->g_stride, P->s_stride, P->scr_stride));
+                                P->n_slots, P->g_stride, P->s_stride, P->scr_stride, P->s_max));
     return SHLR_OK;
 }
 
@@ -985,7 +995,7 @@ static shlr_status lr_layout(int32_t precision, int32_t n_mat, int32_t J, int32_
     if (lr_l(d) > 4096) return fail(SHLR_E_UNSUPPORTED, "max(p, q) > 4096");
     const int cs = precision == SHLR_PREC_MIXED ? 8 : 16;
     L->s = s;
-    L->gst = (int64_t)s * s;
+    L->gst = packed_size(s);
     L->sst = (int64_t)s * s;
     L->scst = eig_scratch_doubles(s);
     const size_t per = L->gst * 16 + L->sst * cs + L->scst * 8 + 3 * 256;
@@ -1049,7 +1059,7 @@ static shlr_status lowrank_impl(int32_t n_mat, int32_t J, int32_t n, int32_t k, 
     STCHK(run_lowrank_groups<R>(&tmp, std::vector<LRGroup>{g}, (C*)h_dev, (C*)d_dev, (C*)b_dev,
                                 (const C*)(ws + L.off_w), (LRDesc*)(ws + L.off_desc), (double2*)(ws + L.off_g),
                                 (C*)(ws + L.off_s), (double*)(ws + L.off_scr), ranks_dev,
-                                (uint32_t*)(ws + L.off_flags), L.slots, L.gst, L.sst, L.scst));
+                                (uint32_t*)(ws + L.off_flags), L.slots, L.gst, L.sst, L.scst, L.s));
     HIPCHK(hipStreamSynchronize(st));   // host descriptor vectors go out of scope
     return SHLR_OK;
 }

@@ -174,7 +174,7 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
         }
     }
     if (!active) return;
-    // write G (column-major, ld = s), both triangles
+    // write G: packed lower triangle
     double2* G = Gs + (int64_t)blockIdx.x * g_stride;
 #pragma unroll
     for (int t = 0; t < MAXT; ++t) {
@@ -187,9 +187,9 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
             for (int r = 0; r < 4; ++r) {
                 const int row = Ib * 16 + acc_row<R>(lk, r);
                 if (row < s && col < s) {
-                    double2 v = make_double2((double)accR[t][r], (double)accI[t][r]);
-                    G[(int64_t)col * s + row] = v;
-                    if (Ib != Jb) G[(int64_t)row * s + col] = make_double2(v.x, -v.y);
+                    // packed lower triangle; the diagonal tiles hold both halves
+                    if (row >= col) G[pk(row, col, s)] = make_double2((double)accR[t][r], (double)accI[t][r]);
+                    else if (Ib != Jb) G[pk(col, row, s)] = make_double2((double)accR[t][r], -(double)accI[t][r]);
                 }
             }
         }
