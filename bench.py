@@ -52,6 +52,24 @@ def lowrank_work(p, q, csize):
     }
 
 
+def measured_traffic(phase, prec):
+    """HBM bytes per launch of a phase's kernel from the committed rocprofv3 counter runs, or None
+    when the kernel's sources changed since the counters were taken (or another precision runs)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_8coil_256_k25.json")
+    if prec != 0 or not os.path.exists(path):   # counters were taken in mixed precision
+        return None
+    with open(path) as f:
+        rec = json.load(f)["phases"].get(phase)
+    if rec is None:
+        return None
+    for name, digest in rec["sources"].items():
+        with open(os.path.join(ROOT, "paper_2107_11650_amd", "csrc", name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return rec["bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +80,8 @@ def main():
                     help="iterations compared with the FP64 oracle (also the CPU-baseline sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-cg", type=int, default=10)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by slice / FE position "
@@ -70,6 +90,15 @@ def main():
 
     import numpy as np
     import torch
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n, "copies": 3}))
+        return
     from paper_2107_11650_amd import shlr
 
     J, M, N, kw = 8, 256, 256, 25
@@ -129,8 +158,8 @@ def main():
         bytes_launch = 6 * J * M * N * csize
         achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "unit": "GB/s"}
-    roof.update({"kernel": dom, "achieved": achieved, "peak": peak, "frac": achieved / peak, "traffic": None,
-                 "avg_launch_ms": avg_ms, "launches": n_dom})
+    roof.update({"kernel": dom, "achieved": achieved, "peak": peak, "frac": achieved / peak,
+                 "traffic": measured_traffic(dom, prec), "avg_launch_ms": avg_ms, "launches": n_dom})
 
     result = {
         "metric": METRIC,
