@@ -252,6 +252,10 @@ static shlr_status validate(const shlr_params* p) {
             return fail(SHLR_E_UNSUPPORTED, "lifted matrices with min(p, q) > 320 are not supported");
         if (std::max(pr, qr) > 4096 || std::max(pc, qc) > 4096)
             return fail(SHLR_E_UNSUPPORTED, "lifted matrices with max(p, q) > 4096 are not supported");
+        const int cs = p->precision == SHLR_PREC_MIXED ? 8 : 16;
+        if (!lowrank_lds_fits(cs, V, p->J, nr, p->k_row) || !lowrank_lds_fits(cs, Vc, p->J, nc, p->k_col))
+            return fail(SHLR_E_UNSUPPORTED, "slice %d: the line table of a lifted matrix (V*J*n = %d) exceeds the "
+                        "LDS staging of this precision", s, V * p->J * std::max(nr, nc));
     }
     return SHLR_OK;
 }
@@ -994,6 +998,8 @@ static shlr_status lr_layout(int32_t precision, int32_t n_mat, int32_t J, int32_
     if (s > 320) return fail(SHLR_E_UNSUPPORTED, "min(p, q) > 320");
     if (lr_l(d) > 4096) return fail(SHLR_E_UNSUPPORTED, "max(p, q) > 4096");
     const int cs = precision == SHLR_PREC_MIXED ? 8 : 16;
+    if (!lowrank_lds_fits(cs, use_vc ? 2 : 1, J, n, k))
+        return fail(SHLR_E_UNSUPPORTED, "the line table of a lifted matrix (V*J*n) exceeds the LDS staging");
     L->s = s;
     L->gst = packed_size(s);
     L->sst = (int64_t)s * s;

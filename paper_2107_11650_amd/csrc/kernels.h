@@ -68,6 +68,9 @@ template <typename R>
 hipError_t launch_reproj(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cplx_t<R>* bb, const cplx_t<R>* wtab,
                          const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, const cplx_t<R>* Ss,
                          int64_t s_stride, double beta, double tau);
+// True when the Gram and reprojection kernels' LDS staging for lifted matrices
+// of this shape fits a compute unit (csize = 8 for complex64, 16 for complex128).
+bool lowrank_lds_fits(int csize, int V, int J, int n, int k);
 template <typename OC>
 hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
                            OC* Ss, int64_t s_stride, double* scr, int64_t scr_stride, int32_t* ranks,

@@ -369,6 +369,18 @@ static size_t reproj_lds_bytes(int V, int J, int n, int s, int KC) {
 
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
+bool lowrank_lds_fits(int csize, int V, int J, int n, int k) {
+    LRDesc d{};
+    d.n = n;
+    d.k = k;
+    d.J = J;
+    d.V = V;
+    const int s = lr_s(d);
+    if (csize == 8)
+        return gram_lds_bytes<float>(V, J, n, s, 4) <= LDS_LIMIT && reproj_lds_bytes<float>(V, J, n, s, 16) <= LDS_LIMIT;
+    return gram_lds_bytes<double>(V, J, n, s, 4) <= LDS_LIMIT && reproj_lds_bytes<double>(V, J, n, s, 16) <= LDS_LIMIT;
+}
+
 template <typename R, int MAXT>
 static hipError_t launch_gram_t(dim3 grid, size_t lds, hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db,
                                 const cplx_t<R>* wtab, const LRDesc* descs, int m0, double2* Gs, int64_t gst,

@@ -65,6 +65,8 @@ def test_valid_plans_report_workspace():
     (dict(spirit_ksize=4), 1),
     (dict(spirit_ksize=5, hard_dc=True), 6),
     (dict(M=(1024,), N=(1024,), J=16, k_row=25, k_col=25), 6),   # min(p, q) > 320
+    # FP64 virtual-coil lifts of 12-coil 256-point lines: line table beyond the LDS staging
+    (dict(M=(256,), N=(256,), J=12, k_row=25, k_col=25, use_vc=True, precision=1), 6),
 ])
 def test_invalid_plans_are_rejected(kw, code):
     from paper_2107_11650_amd import shlr
@@ -91,3 +93,8 @@ def test_lowrank_workspace_size_and_errors():
         shlr.lowrank_workspace_size(shlr.PREC_MIXED, 16, 4, 64, 65, False)
     with pytest.raises(shlr.ShlrError):
         shlr.lowrank_workspace_size(5, 16, 4, 64, 8, False)
+    # the same 12-coil virtual-coil shape is fine in mixed precision, unsupported in FP64
+    assert shlr.lowrank_workspace_size(shlr.PREC_MIXED, 3, 12, 256, 25, True) > 0
+    with pytest.raises(shlr.ShlrError) as ei:
+        shlr.lowrank_workspace_size(shlr.PREC_FP64, 3, 12, 256, 25, True)
+    assert ei.value.code == 6

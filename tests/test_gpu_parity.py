@@ -81,7 +81,9 @@ def test_lowrank_step(case, prec):
     shlr = _lib()
     B, J, n, k, vc, use_w = case
     if prec == "fp64" and vc and n == 256:
-        pytest.skip("FP64 reprojection of 232 x 600 lifts does not fit the 160 KB LDS yet")
+        with pytest.raises(shlr.ShlrError):
+            shlr.lowrank_workspace_size(shlr.PREC_FP64, B, J, n, k, vc)
+        pytest.skip("FP64 line tables of 12-coil virtual-coil lifts exceed the LDS staging (rejected as unsupported)")
     lift = O.LineLift(n, k, use_w, vc)
     h = inputs.random_complex((B, J, n), seed=100 + n + k)
     D = inputs.random_complex((B, lift.p, lift.q(J)), seed=200 + n + k, scale=0.5)
