@@ -170,6 +170,48 @@ shlr_status shlr_timing_enable(shlr_plan* plan, int32_t enable);
 shlr_status shlr_timing_read(shlr_plan* plan, double* ms_out, int32_t* launches_out);
 
 /* ---------------------------------------------------------------------------
+ * Reverse mode through unrolled iterations.
+ *
+ * The paper states no derivative; these calls differentiate the fixed map of
+ * n_iter iterations of Algorithm S1 (X-update of Eq. 15, SVT of Eq. 16,
+ * multiplier update of Eq. 13, for rows and columns) from the acquired
+ * k-space Y and the data-consistency weight lambda (Eq. 2) to the k-space
+ * K after the n_iter-th X-update.  Scope: SHLR_MODEL_PI with finite lambda
+ * (hard_dc = 0), no SPIRiT term (spirit_ksize = 0) and normalize = 0 (the
+ * caller scales Y); virtual coils and any number of slices are covered.
+ * Gradients follow the real inner product: for the loss L = Re <gK, K>
+ * (sum over entries of conj(gK) K) the call returns gY with dL = Re <gY, dY>
+ * and dL/dlambda.  The SVT derivative is the spectral-function derivative
+ * of the Gram form (Daleckii-Krein divided differences, exact at repeated
+ * singular values); it is undefined where a singular value equals the
+ * threshold.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of the checkpoint buffer (K after every X-update, the multipliers
+ * before every low-rank step) and of the backward work buffer for n_iter
+ * iterations.  SHLR_E_UNSUPPORTED outside the scope above. */
+shlr_status shlr_unrolled_sizes(const shlr_plan* plan, int32_t n_iter, size_t* ckpt_bytes,
+                                size_t* work_bytes);
+
+/* shlr_init(y_dev, mask_dev), then n_iter iterations that fill ckpt_dev
+ * (device, >= ckpt_bytes of shlr_unrolled_sizes, 256-byte aligned), then
+ * K_n to k_out_dev (layout of Y).  The low-rank step of the last iteration
+ * does not reach K_n and is skipped. */
+shlr_status shlr_unrolled_forward(shlr_plan* plan, int32_t n_iter, const void* y_dev,
+                                  const uint8_t* mask_dev, void* k_out_dev, void* ckpt_dev,
+                                  size_t ckpt_bytes);
+
+/* Reverse pass of the last shlr_unrolled_forward on this plan (same n_iter
+ * and checkpoint buffer, else SHLR_E_STATE).  gk_dev: cotangent of K_n
+ * (layout of Y); gy_dev: output gradient with respect to Y (layout of Y,
+ * overwritten); g_lambda_host (may be NULL): dL/dlambda.  work_dev: device,
+ * >= work_bytes of shlr_unrolled_sizes, 256-byte aligned.  The plan's
+ * iterate state is consumed: call shlr_init before iterating again. */
+shlr_status shlr_unrolled_backward(shlr_plan* plan, int32_t n_iter, const void* gk_dev,
+                                   const void* ckpt_dev, size_t ckpt_bytes, void* work_dev,
+                                   size_t work_bytes, void* gy_dev, double* g_lambda_host);
+
+/* ---------------------------------------------------------------------------
  * Stage entry points (the steps of one iteration, callable on their own).
  * ------------------------------------------------------------------------- */
 

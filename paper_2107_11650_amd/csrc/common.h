@@ -132,4 +132,17 @@ __host__ __device__ inline int64_t packed_size(int s) { return (int64_t)s * (s +
 // Per-slot scratch of the eigen-solver, in doubles, for matrices of order s.
 __host__ __device__ inline int64_t eig_scratch_doubles(int s) { return 3LL * s * s + 16LL * s + 64; }
 
+// Reverse-mode arguments of the eigen-SVT kernel (all null in the forward).
+template <typename OC>
+struct VjpArgs {
+    const double2* C = nullptr;   // per matrix s x s, row-major: A^H Zbar_A
+    int64_t c_stride = 0;
+    OC* P2 = nullptr;             // per matrix s x s output: 2 x (cotangent of G, Hermitian part)
+    int64_t p2_stride = 0;
+    double* scr = nullptr;        // per matrix scratch of eig_vjp_scratch_doubles(s)
+    int64_t scr_stride = 0;
+    double* tbar = nullptr;       // per descriptor: Re <Zbar, dZ/dthr> (may be null)
+};
+__host__ __device__ inline int64_t eig_vjp_scratch_doubles(int s) { return 14LL * s * s + 64; }
+
 }  // namespace shlr

@@ -74,13 +74,77 @@ __device__ inline double start_entry(int i, int k) {
     return ((double)(x & 0xffffff) / (double)0xffffff) * 2.0 - 1.0;
 }
 
+// x <- P_i x for every column of Xv (s x nvec, column-major, global), with the
+// Hermitian reflectors P_i = I - u_i u_i^H / h_i of the tridiagonalisation
+// (u_i below the diagonal of column i of the packed matrix A, h_i = shv[i]):
+// i = s-2 .. 0 gives Q x (back-transform), i = 0 .. s-2 gives Q^H x.
+// Reflectors are staged in LDS in chunks shared by all waves; one wave per
+// column, lane l owning rows l, l + 64, ... in registers.  All threads call.
+template <int SL>
+__device__ void apply_reflectors(double2* __restrict__ Xv, int nvec, int s, int smax,
+                                 const double2* __restrict__ A, const double* shv, double2* stage,
+                                 bool adjoint) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nw = EIG_THREADS / 64;
+    for (int c0 = 0; c0 + 1 < s && nvec > 0; c0 += EIG_STAGE) {
+        const int cnt = min(EIG_STAGE, s - 1 - c0);
+        __syncthreads();
+        for (int e = tid; e < cnt * s; e += EIG_THREADS) {
+            const int j = e / s, row = e - j * s;
+            const int i = adjoint ? c0 + j : s - 2 - c0 - j;
+            stage[j * smax + row] = (row > i && shv[i] > 0) ? A[pk(row, i, s)] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        for (int k = wave; k < nvec; k += nw) {
+            double2 xr[SL];
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) {
+                const int row = sl * 64 + lane;
+                xr[sl] = row < s ? Xv[(int64_t)k * s + row] : make_double2(0.0, 0.0);
+            }
+            for (int j = 0; j < cnt; ++j) {
+                const int i = adjoint ? c0 + j : s - 2 - c0 - j;
+                const double hh = shv[i];
+                if (!(hh > 0)) continue;
+                double dr = 0, di = 0;
+                double2 ul[SL];
+#pragma unroll
+                for (int sl = 0; sl < SL; ++sl) {
+                    const int row = sl * 64 + lane;
+                    ul[sl] = row < s ? stage[j * smax + row] : make_double2(0.0, 0.0);
+                    dr += ul[sl].x * xr[sl].x + ul[sl].y * xr[sl].y;
+                    di += ul[sl].x * xr[sl].y - ul[sl].y * xr[sl].x;
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    dr += __shfl_xor(dr, off, 64);
+                    di += __shfl_xor(di, off, 64);
+                }
+                dr /= hh;
+                di /= hh;
+#pragma unroll
+                for (int sl = 0; sl < SL; ++sl) {
+                    xr[sl].x -= ul[sl].x * dr - ul[sl].y * di;
+                    xr[sl].y -= ul[sl].x * di + ul[sl].y * dr;
+                }
+            }
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) {
+                const int row = sl * 64 + lane;
+                if (row < s) Xv[(int64_t)k * s + row] = xr[sl];
+            }
+        }
+    }
+    __syncthreads();
+}
+
 template <typename OC, int SL>
 __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __restrict__ descs, int m0,
                                                              double2* __restrict__ Gs, int64_t g_stride,
                                                              OC* __restrict__ Ss, int64_t s_stride,
                                                              double* __restrict__ scr, int64_t scr_stride,
                                                              int32_t* __restrict__ ranks, double ortol_rel,
-                                                             uint32_t* __restrict__ flags, int smax) {
+                                                             uint32_t* __restrict__ flags, int smax,
+                                                             VjpArgs<OC> vj) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int UNR = SL <= 3 ? 4 : (SL == 4 ? 3 : 2);   // columns per wave with loads in flight
     const LRDesc dsc = descs[m0 + blockIdx.x];
@@ -483,67 +547,237 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
     __syncthreads();
 
     // ---- 5. back-transform: X = Q diag(phase) W sqrt(f) ----------------------
-    // X is column-major in the (now free) LU region.  Reflectors are staged in
-    // LDS in chunks shared by all waves; one wave per eigenvector, lane l owns
-    // rows l, l + 64, ... in registers.
+    // X is column-major in the LU region.  For the derivative the unscaled
+    // eigenvectors V = Q diag(phase) W are kept and sqrt(f) enters the S step.
     const int r = nabove;
     double2* X = reinterpret_cast<double2*>(LU);
+    const bool vjp = vj.C != nullptr;
     for (int e = tid; e < s * r; e += EIG_THREADS) {
         const int k = e / s, row = e - k * s;
         const double sig = sqrt(fmax(slam[k], 0.0));
         const double f = sig > 0 ? fmax(1.0 - thr / sig, 0.0) : 0.0;
-        const double w = W[(int64_t)row * s + k] * sqrt(f);
+        const double w = W[(int64_t)row * s + k] * (vjp ? 1.0 : sqrt(f));
         X[(int64_t)k * s + row] = make_double2(sdre[row] * w, sdim[row] * w);
     }
-    for (int i1 = s - 2; i1 >= 0 && r > 0; i1 -= EIG_STAGE) {
-        const int i0 = max(0, i1 - EIG_STAGE + 1);   // reflectors i1, i1-1, ..., i0
-        __syncthreads();
-        for (int e = tid; e < (i1 - i0 + 1) * s; e += EIG_THREADS) {
-            const int j = e / s, row = e - j * s;
-            const int i = i1 - j;
-            stage[j * smax + row] = (row > i && shv[i] > 0) ? A[pk(row, i, s)] : make_double2(0.0, 0.0);
+    apply_reflectors<SL>(X, r, s, smax, A, shv, stage, false);
+
+    if (vjp) {
+        // ---- 5b. reverse-mode derivative of the threshold map ----------------
+        // Z_A = A h(G), G = A^H A, h(l) = max(1 - thr / sqrt(l), 0).  Given
+        // C = A^H Zbar_A, the cotangent of A is Zbar_A S + A P2 with
+        //   P2 = 2 V_all (Hd o sym(V_all^H C V_all)) V_all^H,
+        //   Hd_ij = (h_i - h_j) / (l_i - l_j)  (Daleckii-Krein; h'(l_i) on ties).
+        // Pairs of eigenvalues both at or below thr^2 contribute nothing.  For
+        // a, a2 above: Hd = thr / (s_a s_a2 (s_a + s_a2)), s = sqrt(l), exact
+        // also at ties.  A pair (a above, b below) gives h_a / (l_a - l_b), so
+        // the sum over all b is h_a (l_a I - G)^+ restricted to the complement
+        // of range(V): y_a solves (l_a I - T) y'' = c'' in the real tridiagonal
+        // basis (LU with partial pivoting), c_a = (I - V V^H) Msym v_a.
+        //   P2 = 2 [V K V^H + sum_a h_a (v_a y_a^H + y_a v_a^H)],
+        //   K = Hd o sym(V^H Msym V),  Msym = (C + C^H) / 2.
+        // Also d Z_A / d thr contracted with Zbar: -sum_a Re(v_a^H C v_a) / s_a.
+        const double2* C = vj.C + (int64_t)blockIdx.x * vj.c_stride;
+        double2* Mv = reinterpret_cast<double2*>(vj.scr + (int64_t)blockIdx.x * vj.scr_stride);
+        double2* Yv = Mv + (int64_t)s * r;
+        double2* Mp = Yv + (int64_t)s * r;     // r x r, [a * r + a2] = v_a^H m_a2
+        double2* Kc = Mp + (int64_t)r * r;     // r x r
+        double2* Ev = Kc + (int64_t)r * r;     // s x r
+        double* lu = reinterpret_cast<double*>(Ev + (int64_t)s * r);   // 4 s r, [i * r + a]
+        double* u0 = lu;
+        double* du1 = lu + (int64_t)s * r;
+        double* du2 = du1 + (int64_t)s * r;
+        double* lmul = du2 + (int64_t)s * r;
+        // (i) m_a = Msym v_a
+        for (int e = tid; e < s * r; e += EIG_THREADS) {
+            const int a = e / s, i = e - a * s;
+            double mr = 0, mi = 0;
+            for (int j = 0; j < s; ++j) {
+                const double2 v = X[(int64_t)a * s + j];
+                const double2 c1 = C[(int64_t)i * s + j];
+                const double2 c2 = C[(int64_t)j * s + i];
+                mr += (c1.x + c2.x) * v.x - (c1.y - c2.y) * v.y;
+                mi += (c1.x + c2.x) * v.y + (c1.y - c2.y) * v.x;
+            }
+            Mv[(int64_t)a * s + i] = make_double2(0.5 * mr, 0.5 * mi);
         }
         __syncthreads();
-        for (int k = wave; k < r; k += nw) {
-            double2 xr[SL];
-#pragma unroll
-            for (int sl = 0; sl < SL; ++sl) {
-                const int row = sl * 64 + lane;
-                xr[sl] = row < s ? X[(int64_t)k * s + row] : make_double2(0.0, 0.0);
+        // (ii) M' = V^H Msym V
+        for (int e = tid; e < r * r; e += EIG_THREADS) {
+            const int a = e / r, a2 = e - a * r;
+            double pr = 0, pi = 0;
+            for (int i = 0; i < s; ++i) {
+                const double2 v = X[(int64_t)a * s + i], m = Mv[(int64_t)a2 * s + i];
+                pr += v.x * m.x + v.y * m.y;
+                pi += v.x * m.y - v.y * m.x;
             }
-            for (int j = 0; j <= i1 - i0; ++j) {
-                const int i = i1 - j;
-                const double hh = shv[i];
-                if (!(hh > 0)) continue;
-                double dr = 0, di = 0;
-                double2 ul[SL];
-#pragma unroll
-                for (int sl = 0; sl < SL; ++sl) {
-                    const int row = sl * 64 + lane;
-                    ul[sl] = row < s ? stage[j * smax + row] : make_double2(0.0, 0.0);
-                    dr += ul[sl].x * xr[sl].x + ul[sl].y * xr[sl].y;
-                    di += ul[sl].x * xr[sl].y - ul[sl].y * xr[sl].x;
-                }
-                for (int off = 32; off > 0; off >>= 1) {
-                    dr += __shfl_xor(dr, off, 64);
-                    di += __shfl_xor(di, off, 64);
-                }
-                dr /= hh;
-                di /= hh;
-#pragma unroll
-                for (int sl = 0; sl < SL; ++sl) {
-                    xr[sl].x -= ul[sl].x * dr - ul[sl].y * di;
-                    xr[sl].y -= ul[sl].x * di + ul[sl].y * dr;
+            Mp[e] = make_double2(pr, pi);
+        }
+        __syncthreads();
+        // (iii) c_a = m_a - V M'[:, a], then conj(phase) Q^H c_a
+        for (int e = tid; e < s * r; e += EIG_THREADS) {
+            const int a = e / s, i = e - a * s;
+            double2 c = Mv[(int64_t)a * s + i];
+            for (int a2 = 0; a2 < r; ++a2) {
+                const double2 v = X[(int64_t)a2 * s + i], pm = Mp[a2 * r + a];
+                c.x -= v.x * pm.x - v.y * pm.y;
+                c.y -= v.x * pm.y + v.y * pm.x;
+            }
+            Yv[(int64_t)a * s + i] = c;
+        }
+        apply_reflectors<SL>(Yv, r, s, smax, A, shv, stage, true);
+        for (int e = tid; e < s * r; e += EIG_THREADS) {
+            const int i = e % s;
+            const double2 c = Yv[e];
+            Yv[e] = make_double2(sdre[i] * c.x + sdim[i] * c.y, sdre[i] * c.y - sdim[i] * c.x);
+        }
+        __syncthreads();
+        // (iv) (T - l_a I) y'' = -c'', one thread per eigenvalue
+        const double tiny = DBL_EPSILON * tnorm + pivmin;
+        for (int a = tid; a < r; a += EIG_THREADS) {
+            const double lk = slam[a];
+            double dcur = sdd[0] - lk;
+            double ucur = s > 1 ? see[0] : 0.0;
+            for (int i = 0; i + 1 < s; ++i) {
+                const double c = see[i];
+                const double a1 = sdd[i + 1] - lk;
+                const double b1 = (i + 2 < s) ? see[i + 1] : 0.0;
+                const int64_t o = (int64_t)i * r + a;
+                if (fabs(dcur) >= fabs(c)) {
+                    const double piv = dcur == 0.0 ? tiny : dcur;
+                    const double f = c / piv;
+                    u0[o] = piv;
+                    du1[o] = ucur;
+                    du2[o] = 0.0;
+                    lmul[o] = f;                 // no row swap, |f| <= 1
+                    dcur = a1 - f * ucur;
+                    ucur = b1;
+                } else {
+                    const double f = dcur / c;
+                    u0[o] = c;
+                    du1[o] = a1;
+                    du2[o] = b1;
+                    lmul[o] = -(f + 4.0);        // a swap, encoded below -3
+                    dcur = ucur - f * a1;
+                    ucur = -f * b1;
                 }
             }
-#pragma unroll
-            for (int sl = 0; sl < SL; ++sl) {
-                const int row = sl * 64 + lane;
-                if (row < s) X[(int64_t)k * s + row] = xr[sl];
+            u0[(int64_t)(s - 1) * r + a] = dcur == 0.0 ? tiny : dcur;
+            double2* y = Yv + (int64_t)a * s;
+            for (int i = 0; i < s; ++i) y[i] = make_double2(-y[i].x, -y[i].y);
+            for (int i = 0; i + 1 < s; ++i) {
+                const double lm = lmul[(int64_t)i * r + a];
+                double2 yi = y[i], yi1 = y[i + 1];
+                if (lm <= -3.0) {
+                    const double f = -lm - 4.0;
+                    const double2 t = yi;
+                    yi = yi1;
+                    yi1 = make_double2(t.x - f * yi.x, t.y - f * yi.y);
+                } else {
+                    yi1 = make_double2(yi1.x - lm * yi.x, yi1.y - lm * yi.y);
+                }
+                y[i] = yi;
+                y[i + 1] = yi1;
+            }
+            double2 x1 = make_double2(0.0, 0.0), x2 = x1;
+            for (int i = s - 1; i >= 0; --i) {
+                const int64_t o = (int64_t)i * r + a;
+                double2 v = y[i];
+                if (i + 1 < s) {
+                    v.x -= du1[o] * x1.x;
+                    v.y -= du1[o] * x1.y;
+                }
+                if (i + 2 < s) {
+                    v.x -= du2[o] * x2.x;
+                    v.y -= du2[o] * x2.y;
+                }
+                v.x /= u0[o];
+                v.y /= u0[o];
+                y[i] = v;
+                x2 = x1;
+                x1 = v;
             }
         }
+        __syncthreads();
+        // (v) back to the Gram basis: y = Q diag(phase) y''
+        for (int e = tid; e < s * r; e += EIG_THREADS) {
+            const int i = e % s;
+            const double2 c = Yv[e];
+            Yv[e] = make_double2(sdre[i] * c.x - sdim[i] * c.y, sdre[i] * c.y + sdim[i] * c.x);
+        }
+        apply_reflectors<SL>(Yv, r, s, smax, A, shv, stage, false);
+        // (vi) y_a -= V (V^H y_a): coefficients into Kc, then the update
+        for (int e = tid; e < r * r; e += EIG_THREADS) {
+            const int a2 = e / r, a = e - a2 * r;
+            double pr = 0, pi = 0;
+            for (int i = 0; i < s; ++i) {
+                const double2 v = X[(int64_t)a2 * s + i], y = Yv[(int64_t)a * s + i];
+                pr += v.x * y.x + v.y * y.y;
+                pi += v.x * y.y - v.y * y.x;
+            }
+            Kc[e] = make_double2(pr, pi);   // [a2 * r + a] = v_a2^H y_a
+        }
+        __syncthreads();
+        for (int e = tid; e < s * r; e += EIG_THREADS) {
+            const int a = e / s, i = e - a * s;
+            double2 y = Yv[e];
+            for (int a2 = 0; a2 < r; ++a2) {
+                const double2 v = X[(int64_t)a2 * s + i], cf = Kc[a2 * r + a];
+                y.x -= v.x * cf.x - v.y * cf.y;
+                y.y -= v.x * cf.y + v.y * cf.x;
+            }
+            Yv[e] = y;
+        }
+        __syncthreads();
+        // (vii) K = Hd o sym(M'), the threshold contraction
+        for (int e = tid; e < r * r; e += EIG_THREADS) {
+            const int a = e / r, a2 = e - a * r;
+            const double sa = sqrt(slam[a]), sb = sqrt(slam[a2]);
+            const double hd = thr / (sa * sb * (sa + sb));
+            const double2 m1 = Mp[a * r + a2], m2 = Mp[a2 * r + a];
+            Kc[e] = make_double2(0.5 * hd * (m1.x + m2.x), 0.5 * hd * (m1.y - m2.y));
+        }
+        if (tid == 0 && vj.tbar) {
+            double tb = 0;
+            for (int a = 0; a < r; ++a) tb -= Mp[a * r + a].x / sqrt(slam[a]);
+            vj.tbar[m0 + blockIdx.x] = tb;
+        }
+        __syncthreads();
+        // (viii) E = V K
+        for (int e = tid; e < s * r; e += EIG_THREADS) {
+            const int a2 = e / s, i = e - a2 * s;
+            double er = 0, ei = 0;
+            for (int a = 0; a < r; ++a) {
+                const double2 v = X[(int64_t)a * s + i], kk = Kc[a * r + a2];
+                er += v.x * kk.x - v.y * kk.y;
+                ei += v.x * kk.y + v.y * kk.x;
+            }
+            Ev[e] = make_double2(er, ei);
+        }
+        __syncthreads();
+        // (ix) P2[i][j] = 2 sum_a (E_ia conj(V_ja) + h_a (V_ia conj(Y_ja) + Y_ia conj(V_ja)))
+        OC* P2 = vj.P2 + (int64_t)blockIdx.x * vj.p2_stride;
+        for (int e = tid; e < s * s; e += EIG_THREADS) {
+            const int i = e / s, j = e - i * s;
+            double pr = 0, pi = 0;
+            for (int a = 0; a < r; ++a) {
+                const double ha = 1.0 - thr / sqrt(slam[a]);
+                const double2 ei_ = Ev[(int64_t)a * s + i], vj_ = X[(int64_t)a * s + j];
+                const double2 vi_ = X[(int64_t)a * s + i], yj_ = Yv[(int64_t)a * s + j];
+                const double2 yi_ = Yv[(int64_t)a * s + i];
+                // E_ia conj(V_ja)
+                pr += ei_.x * vj_.x + ei_.y * vj_.y;
+                pi += ei_.y * vj_.x - ei_.x * vj_.y;
+                // h_a (V_ia conj(Y_ja) + Y_ia conj(V_ja))
+                pr += ha * (vi_.x * yj_.x + vi_.y * yj_.y + yi_.x * vj_.x + yi_.y * vj_.y);
+                pi += ha * (vi_.y * yj_.x - vi_.x * yj_.y + yi_.y * vj_.x - yi_.x * vj_.y);
+            }
+            OC o;
+            o.x = 2.0 * pr;
+            o.y = 2.0 * pi;
+            P2[e] = o;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     // ---- 6. S = X X^H (row-major, ld = s) ------------------------------------
     // X is staged in LDS in column chunks; the lower triangle is accumulated in
     // FP64 (in the now free packed Gram storage when several chunks are needed).
@@ -552,7 +786,16 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
     for (int k0 = 0; k0 < r; k0 += kc) {
         const int k1 = min(r, k0 + kc);
         __syncthreads();
-        for (int e = tid; e < (k1 - k0) * s; e += EIG_THREADS) stage[e] = X[(int64_t)k0 * s + e];
+        for (int e = tid; e < (k1 - k0) * s; e += EIG_THREADS) {
+            double2 x = X[(int64_t)k0 * s + e];
+            if (vjp) {
+                const double sig = sqrt(fmax(slam[k0 + e / s], 0.0));
+                const double g = sqrt(sig > 0 ? fmax(1.0 - thr / sig, 0.0) : 0.0);
+                x.x *= g;
+                x.y *= g;
+            }
+            stage[e] = x;
+        }
         __syncthreads();
         for (int64_t e = tid; e < ntri; e += EIG_THREADS) {
             // e -> (a, b), a >= b, column-major packed
@@ -610,7 +853,7 @@ static size_t heig_lds_bytes(int smax) {
 template <typename OC>
 hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
                            OC* Ss, int64_t s_stride, double* scr, int64_t scr_stride, int32_t* ranks,
-                           double ortol_rel, uint32_t* flags, int smax) {
+                           double ortol_rel, uint32_t* flags, int smax, const VjpArgs<OC>& vj) {
     const size_t lds = heig_lds_bytes(smax);
     const int sl = (smax + 63) / 64;
     const void* fn = sl <= 1 ? (const void*)k_heig_svt<OC, 1>
@@ -622,15 +865,18 @@ hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int coun
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     void* args[] = {(void*)&descs, (void*)&m0, (void*)&Gs, (void*)&g_stride, (void*)&Ss, (void*)&s_stride, (void*)&scr,
-                    (void*)&scr_stride, (void*)&ranks, (void*)&ortol_rel, (void*)&flags, (void*)&smax};
+                    (void*)&scr_stride, (void*)&ranks, (void*)&ortol_rel, (void*)&flags, (void*)&smax,
+                    (void*)&vj};
     e = hipLaunchKernel(fn, dim3(count), dim3(EIG_THREADS), args, lds, st);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
 template hipError_t launch_heig_svt<float2>(hipStream_t, const LRDesc*, int, int, double2*, int64_t, float2*, int64_t,
-                                            double*, int64_t, int32_t*, double, uint32_t*, int);
+                                            double*, int64_t, int32_t*, double, uint32_t*, int,
+                                            const VjpArgs<float2>&);
 template hipError_t launch_heig_svt<double2>(hipStream_t, const LRDesc*, int, int, double2*, int64_t, double2*,
-                                             int64_t, double*, int64_t, int32_t*, double, uint32_t*, int);
+                                             int64_t, double*, int64_t, int32_t*, double, uint32_t*, int,
+                                             const VjpArgs<double2>&);
 
 }  // namespace shlr

@@ -153,6 +153,10 @@ struct shlr_plan {
     bool bound = false, initialised = false;
     std::vector<double> scales;
     int64_t total_elems = 0;  // complex elements of Y
+    int64_t d_block_off = 0, d_block_elems = 0;   // PI: the multipliers of all slices (complex elements)
+    // reverse mode: the forward with checkpoints that the backward may follow
+    int unrolled_n = 0;
+    const void* unrolled_ckpt = nullptr;
     // spirit
     bool spirit_ready = false;
     // graph
@@ -341,10 +345,6 @@ extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
             L.hct = cal(e);
             L.br = cal(e);
             L.bct = cal(e);
-            const int pr = N - p->k_row + 1, qr = p->k_row * J * V;
-            const int pc = M - p->k_col + 1, qc = p->k_col * J * V;
-            L.dr = cal((int64_t)M * pr * qr);
-            L.dc = cal((int64_t)N * pc * qc);
             L.mask_b = mal((int64_t)M * N);
             L.rr = ral(N);
             L.rc = ral(M);
@@ -353,6 +353,17 @@ extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
             P->total_elems += e;
             P->sl.push_back(L);
         }
+        // the multipliers of all slices form one contiguous block (checkpoints copy it whole)
+        P->d_block_off = c;
+        for (int s = 0; s < p->n_slices; ++s) {
+            SliceLayout& L = P->sl[s];
+            const int M = L.M, N = L.N;
+            const int pr = N - p->k_row + 1, qr = p->k_row * J * V;
+            const int pc = M - p->k_col + 1, qc = p->k_col * J * V;
+            L.dr = cal((int64_t)M * pr * qr);
+            L.dc = cal((int64_t)N * pc * qc);
+        }
+        P->d_block_elems = c - P->d_block_off;
         // complex tables after the per-slice arrays
         for (int s = 0; s < p->n_slices; ++s) {
             SliceLayout& L = P->sl[s];
@@ -626,7 +637,7 @@ static shlr_status run_lowrank_groups(shlr_plan* P, const std::vector<LRGroup>& 
 }
 
 template <typename R>
-static shlr_status iterate_once(shlr_plan* P, bool track_change) {
+static shlr_status x_update_phase(shlr_plan* P, bool track_change) {
     Ptrs<R> Q(P);
     const shlr_params& p = P->p;
     const int J = p.J;
@@ -687,9 +698,21 @@ static shlr_status iterate_once(shlr_plan* P, bool track_change) {
                                    track_change ? Q.change : nullptr));
     }
     STCHK(phase_end(P, 0, e0));
-    STCHK(run_lowrank_groups<R>(P, P->groups, Q.c, Q.c, Q.c, Q.c, Q.desc, Q.g, Q.s, Q.scr, Q.ranks, Q.flags,
-                                P->n_slots, P->g_stride, P->s_stride, P->scr_stride, P->s_max));
     return SHLR_OK;
+}
+
+template <typename R>
+static shlr_status lowrank_phase(shlr_plan* P) {
+    Ptrs<R> Q(P);
+    return run_lowrank_groups<R>(P, P->groups, Q.c, Q.c, Q.c, Q.c, Q.desc, Q.g, Q.s, Q.scr, Q.ranks, Q.flags,
+                                 P->n_slots, P->g_stride, P->s_stride, P->scr_stride, P->s_max);
+}
+
+// One iteration of Algorithm S1 / S2: X-update, then the Z and multiplier updates.
+template <typename R>
+static shlr_status iterate_once(shlr_plan* P, bool track_change) {
+    STCHK(x_update_phase<R>(P, track_change));
+    return lowrank_phase<R>(P);
 }
 
 template <typename R>
@@ -1092,3 +1115,4 @@ extern "C" shlr_status shlr_lowrank_lines(int32_t precision, int32_t n_mat, int3
 // SPIRiT (Eq. 3): set / calibrate the kernel; X-update by PCG
 // ---------------------------------------------------------------------------
 #include "spirit_host.inc"
+#include "unrolled.inc"

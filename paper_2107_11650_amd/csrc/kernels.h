@@ -68,12 +68,31 @@ template <typename R>
 hipError_t launch_reproj(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cplx_t<R>* bb, const cplx_t<R>* wtab,
                          const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, const cplx_t<R>* Ss,
                          int64_t s_stride, double beta, double tau);
+template <typename R>
+hipError_t launch_cross_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* gb,
+                             const cplx_t<R>* gdb, const cplx_t<R>* wtab, const LRDesc* descs_dev,
+                             const LRDesc& proto, int m0, int count, double2* Cs, int64_t c_stride, double beta,
+                             double tau);
+template <typename R>
+hipError_t launch_reproj_vjp(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* gb,
+                             cplx_t<R>* gdb, cplx_t<R>* ghb, const cplx_t<R>* wtab, const LRDesc* descs_dev,
+                             const LRDesc& proto, int m0, int count, const cplx_t<R>* Ss, const cplx_t<R>* P2s,
+                             int64_t s_stride, double beta, double tau);
+constexpr int DC_VJP_BLOCKS = 512;   // partial sums per slice of the data-consistency backward
+template <typename R>
+hipError_t launch_dc_vjp(hipStream_t st, const cplx_t<R>* gk, const cplx_t<R>* K, const cplx_t<R>* Y,
+                         const uint8_t* mask, const R* rr, const R* rc, int J, int M, int N, double lam, double beta,
+                         cplx_t<R>* rbar, cplx_t<R>* gy, double* partials);
+template <typename R>
+hipError_t launch_add(hipStream_t st, cplx_t<R>* a, const cplx_t<R>* b, int64_t n);
+// True when the reverse-mode kernels' LDS staging fits for this shape.
+bool lowrank_vjp_lds_fits(int csize, int V, int J, int n, int k);
 // True when the Gram and reprojection kernels' LDS staging for lifted matrices
 // of this shape fits a compute unit (csize = 8 for complex64, 16 for complex128).
 bool lowrank_lds_fits(int csize, int V, int J, int n, int k);
 template <typename OC>
 hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
                            OC* Ss, int64_t s_stride, double* scr, int64_t scr_stride, int32_t* ranks,
-                           double ortol_rel, uint32_t* flags, int smax);
+                           double ortol_rel, uint32_t* flags, int smax, const VjpArgs<OC>& vj = VjpArgs<OC>());
 
 }  // namespace shlr

@@ -23,9 +23,10 @@ constexpr int LR_THREADS = 512;     // 8 waves
 constexpr int LR_WAVES = LR_THREADS / 64;
 
 // Build the lifted line table u[v][j][i] = w[i] * (v == 0 ? h_j[i] : conj(h_j[flip(i)]))
+// from lines at hb + off + j * cs + i * es.
 template <typename R>
-__device__ inline void load_line_table(cplx_t<R>* U, const cplx_t<R>* hb, const cplx_t<R>* wtab,
-                                       const LRDesc& d, int tid, int nth) {
+__device__ inline void load_line_table_at(cplx_t<R>* U, const cplx_t<R>* hb, int64_t off, int cs, int es,
+                                          const cplx_t<R>* wtab, const LRDesc& d, int tid, int nth) {
     using C = cplx_t<R>;
     const int n = d.n, J = d.J, V = d.V;
     const int c = n / 2;
@@ -35,15 +36,21 @@ __device__ inline void load_line_table(cplx_t<R>* U, const cplx_t<R>* hb, const 
         int v = blk / J, j = blk % J;
         C h;
         if (v == 0) {
-            h = hb[d.h_off + (int64_t)j * d.h_cs + (int64_t)i * d.h_es];
+            h = hb[off + (int64_t)j * cs + (int64_t)i * es];
         } else {
             int fi = (2 * c - i) % n;
             if (fi < 0) fi += n;
-            h = cconj(hb[d.h_off + (int64_t)j * d.h_cs + (int64_t)fi * d.h_es]);
+            h = cconj(hb[off + (int64_t)j * cs + (int64_t)fi * es]);
         }
         if (d.use_w) h = cmul(wtab[d.w_off + i], h);
         U[e] = h;
     }
+}
+
+template <typename R>
+__device__ inline void load_line_table(cplx_t<R>* U, const cplx_t<R>* hb, const cplx_t<R>* wtab,
+                                       const LRDesc& d, int tid, int nth) {
+    load_line_table_at<R>(U, hb, d.h_off, d.h_cs, d.h_es, wtab, d, tid, nth);
 }
 
 // Value of T (without the D term) at (a, col).
@@ -58,6 +65,47 @@ __device__ inline C lift_val(const C* U, int n, int k, int a, int col) {
 // Stage a chunk of A rows [r0, r0 + KC) into LDS as split real/imag planes,
 // zero padded to s_pad columns and KC rows.
 // ---------------------------------------------------------------------------
+// General form: rows of (cu * lift(U) + cd * Dm) (side 0) or of its conjugate
+// transpose (side 1).
+template <typename R>
+__device__ inline void stage_chunk(R* Ar, R* Ai, int ldA, const cplx_t<R>* U, R cu, const cplx_t<R>* Dm, R cd,
+                                   const LRDesc& d, int r0, int KC, int s_pad, int tid, int nth) {
+    using C = cplx_t<R>;
+    const int p = lr_p(d), q = lr_q(d), side = lr_side(d);
+    const int s = side == 0 ? q : p;
+    const int l = side == 0 ? p : q;
+    const int total = KC * s_pad;
+    if (side == 0) {
+        for (int e = tid; e < total; e += nth) {
+            int r = e / s_pad, cidx = e - r * s_pad;
+            int a = r0 + r;
+            R re = 0, im = 0;
+            if (a < l && cidx < s) {
+                C dv = Dm[(int64_t)a * q + cidx];
+                C lv = lift_val(U, d.n, d.k, a, cidx);
+                re = cu * lv.x + cd * dv.x;
+                im = cu * lv.y + cd * dv.y;
+            }
+            Ar[r * ldA + cidx] = re;
+            Ai[r * ldA + cidx] = im;
+        }
+    } else {
+        for (int e = tid; e < total; e += nth) {
+            int cidx = e / KC, r = e - cidx * KC;
+            int col = r0 + r;
+            R re = 0, im = 0;
+            if (col < l && cidx < s) {
+                C dv = Dm[(int64_t)cidx * q + col];
+                C lv = lift_val(U, d.n, d.k, cidx, col);
+                re = cu * lv.x + cd * dv.x;
+                im = -(cu * lv.y + cd * dv.y);
+            }
+            Ar[r * ldA + cidx] = re;
+            Ai[r * ldA + cidx] = im;
+        }
+    }
+}
+
 template <typename R>
 __device__ inline void stage_A_chunk(R* Ar, R* Ai, int ldA, const cplx_t<R>* U, const cplx_t<R>* Dm,
                                      const LRDesc& d, R inv_beta, int r0, int KC, int s_pad, int tid, int nth) {
@@ -353,6 +401,256 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Reverse mode of one low-rank step (lift, SVT, multiplier update, adjoint
+// lift).  Per matrix, with A the side-s form of T = lift(h) + D / beta and
+//   Zbar = (1 + tau/beta) lift(gb) - tau Dbar
+// (gb: cotangent of the adjoint-lift output line, Dbar: cotangent of the
+// updated multiplier):
+//   k_cross_gram : C = A^H Zbar_A (full s x s, FP64) for the eigen kernel;
+//   k_reproj_vjp : Tbar_A = Zbar_A S + A P2, then
+//                  Dbar' = Dbar - lift(gb) / beta,
+//                  Dbar <- Dbar' + Tbar / beta        (cotangent of D),
+//                  ghb  = lift^*(tau Dbar' + Tbar)     (cotangent of the line).
+// ---------------------------------------------------------------------------
+template <typename R, int MAXT>
+__global__ __launch_bounds__(LR_THREADS) void k_cross_gram(const cplx_t<R>* __restrict__ hb,
+                                                           const cplx_t<R>* __restrict__ db,
+                                                           const cplx_t<R>* __restrict__ gb,
+                                                           const cplx_t<R>* __restrict__ gdb,
+                                                           const cplx_t<R>* __restrict__ wtab,
+                                                           const LRDesc* __restrict__ descs, int m0,
+                                                           double2* __restrict__ Cs, int64_t c_stride,
+                                                           R inv_beta, R cz, R cdz, int KC) {
+    using C = cplx_t<R>;
+    using A4 = acc4_t<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const LRDesc d = descs[m0 + blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int s = lr_s(d), l = lr_l(d);
+    const int nt = (s + 15) / 16;
+    const int s_pad = nt * 16;
+    const int ldA = s_pad + 4;
+    const int utab = d.V * d.J * d.n;
+    C* Uh = reinterpret_cast<C*>(smem_raw);
+    C* Ub = Uh + utab;
+    R* Ar = reinterpret_cast<R*>(Ub + utab);
+    R* Ai = Ar + KC * ldA;
+    R* Zr = Ai + KC * ldA;
+    R* Zi = Zr + KC * ldA;
+
+    const int nseg = (nt + MAXT - 1) / MAXT;
+    const int unit = blockIdx.y * LR_WAVES + wave;
+    const bool active = unit < nt * nseg;
+    const int I = active ? unit / nseg : 0;
+    const int J0 = active ? (unit % nseg) * MAXT : 0;
+    const int cnt = active ? min(MAXT, nt - J0) : 0;
+
+    A4 accR[MAXT], accI[MAXT];
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+        accR[t] = A4{0, 0, 0, 0};
+        accI[t] = A4{0, 0, 0, 0};
+    }
+    load_line_table<R>(Uh, hb, wtab, d, tid, LR_THREADS);
+    load_line_table_at<R>(Ub, gb, d.b_off, d.b_cs, d.b_es, wtab, d, tid, LR_THREADS);
+    const C* Dm = db + d.d_off;
+    const C* Gm = gdb + d.d_off;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int r0 = 0; r0 < l; r0 += KC) {
+        __syncthreads();
+        stage_chunk<R>(Ar, Ai, ldA, Uh, (R)1, Dm, inv_beta, d, r0, KC, s_pad, tid, LR_THREADS);
+        stage_chunk<R>(Zr, Zi, ldA, Ub, cz, Gm, cdz, d, r0, KC, s_pad, tid, LR_THREADS);
+        __syncthreads();
+        if (!active) continue;
+        for (int kk = 0; kk < KC; kk += 4) {
+            const int row = (kk + lk) * ldA + li;
+            const R ar = Ar[row + I * 16], ai = Ai[row + I * 16];
+#pragma unroll
+            for (int t = 0; t < MAXT; ++t) {
+                if (t < cnt) {
+                    const int Jb = J0 + t;
+                    const R zr = Zr[row + Jb * 16], zi = Zi[row + Jb * 16];
+                    accR[t] = mfma16(ar, zr, accR[t]);
+                    accR[t] = mfma16(ai, zi, accR[t]);
+                    accI[t] = mfma16(ar, zi, accI[t]);
+                    accI[t] = mfma16(-ai, zr, accI[t]);
+                }
+            }
+        }
+    }
+    if (!active) return;
+    double2* Cm = Cs + (int64_t)blockIdx.x * c_stride;
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+        if (t < cnt) {
+            const int col = (J0 + t) * 16 + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = I * 16 + acc_row<R>(lk, r);
+                if (row < s && col < s) Cm[(int64_t)row * s + col] = make_double2((double)accR[t][r], (double)accI[t][r]);
+            }
+        }
+    }
+}
+
+template <typename R, int MAXT>
+__global__ __launch_bounds__(LR_THREADS) void k_reproj_vjp(const cplx_t<R>* __restrict__ hb,
+                                                           const cplx_t<R>* __restrict__ db,
+                                                           const cplx_t<R>* __restrict__ gb,
+                                                           cplx_t<R>* __restrict__ gdb,
+                                                           cplx_t<R>* __restrict__ ghb,
+                                                           const cplx_t<R>* __restrict__ wtab,
+                                                           const LRDesc* __restrict__ descs, int m0,
+                                                           const cplx_t<R>* __restrict__ Ss,
+                                                           const cplx_t<R>* __restrict__ P2s, int64_t s_stride,
+                                                           R inv_beta, R tau, R cz, R cdz, int KC) {
+    using C = cplx_t<R>;
+    using A4 = acc4_t<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const LRDesc d = descs[m0 + blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int p = lr_p(d), q = lr_q(d), side = lr_side(d);
+    const int s = side == 0 ? q : p;
+    const int l = side == 0 ? p : q;
+    const int n = d.n, k = d.k, J = d.J, V = d.V;
+    const int nt = (s + 15) / 16;
+    const int s_pad = nt * 16;
+    const int ldA = s_pad + 4;
+    const int utab = V * J * n;
+    C* Uh = reinterpret_cast<C*>(smem_raw);
+    C* Ub = Uh + utab;
+    C* Bacc = Ub + utab;
+    R* Ar = reinterpret_cast<R*>(Bacc + utab);   // one pair of planes: the Zbar chunk, then the A chunk
+    R* Ai = Ar + KC * ldA;
+    C* Rst = reinterpret_cast<C*>(Ar);   // KC x s_pad complex fits in the two planes
+
+    load_line_table<R>(Uh, hb, wtab, d, tid, LR_THREADS);
+    load_line_table_at<R>(Ub, gb, d.b_off, d.b_cs, d.b_es, wtab, d, tid, LR_THREADS);
+    for (int e = tid; e < utab; e += LR_THREADS) Bacc[e] = cmk<C>(0, 0);
+
+    const C* Dm = db + d.d_off;
+    C* Gm = gdb + d.d_off;
+    const C* S = Ss + (int64_t)blockIdx.x * s_stride;
+    const C* P2 = P2s + (int64_t)blockIdx.x * s_stride;
+    const int li = lane & 15, lk = lane >> 4;
+    const int rt = KC / 16;
+    const int ntile = rt * nt;
+
+    for (int r0 = 0; r0 < l; r0 += KC) {
+        A4 accR[MAXT], accI[MAXT];
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+            accR[t] = A4{0, 0, 0, 0};
+            accI[t] = A4{0, 0, 0, 0};
+        }
+        // pass 0: Zbar_A chunk x S; pass 1: A chunk x P2
+        for (int pass = 0; pass < 2; ++pass) {
+            __syncthreads();
+            if (pass == 0) stage_chunk<R>(Ar, Ai, ldA, Ub, cz, Gm, cdz, d, r0, KC, s_pad, tid, LR_THREADS);
+            else stage_chunk<R>(Ar, Ai, ldA, Uh, (R)1, Dm, inv_beta, d, r0, KC, s_pad, tid, LR_THREADS);
+            __syncthreads();
+            const C* B = pass == 0 ? S : P2;
+            for (int kk = 0; kk < s_pad; kk += 4) {
+                const int kidx = kk + lk;
+#pragma unroll
+                for (int t = 0; t < MAXT; ++t) {
+                    const int tile = wave + t * LR_WAVES;
+                    if (tile < ntile) {
+                        const int It = tile / nt, Jt = tile - It * nt;
+                        const int arow = (It * 16 + li) * ldA + kidx;
+                        const int col = Jt * 16 + li;
+                        R br = 0, bi = 0;
+                        if (kidx < s && col < s) {
+                            const C bv = B[(int64_t)kidx * s + col];
+                            br = bv.x;
+                            bi = bv.y;
+                        }
+                        const R ar = Ar[arow], ai = Ai[arow];
+                        accR[t] = mfma16(ar, br, accR[t]);
+                        accR[t] = mfma16(-ai, bi, accR[t]);
+                        accI[t] = mfma16(ar, bi, accI[t]);
+                        accI[t] = mfma16(ai, br, accI[t]);
+                    }
+                }
+            }
+        }
+        __syncthreads();   // the A planes are dead from here on; reuse them for the line cotangent terms
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+            const int tile = wave + t * LR_WAVES;
+            if (tile < ntile) {
+                const int It = tile / nt, Jt = tile - It * nt;
+                const int col = Jt * 16 + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rloc = It * 16 + acc_row<R>(lk, r);
+                    const int row = r0 + rloc;
+                    C lb = cmk<C>(0, 0);
+                    if (row < l && col < s) {
+                        int a, c;
+                        C tb;
+                        if (side == 0) { a = row; c = col; tb = cmk<C>(accR[t][r], accI[t][r]); }
+                        else { a = col; c = row; tb = cmk<C>(accR[t][r], -accI[t][r]); }
+                        const C rb = lift_val(Ub, n, k, a, c);
+                        const int64_t di = (int64_t)a * q + c;
+                        const C go = Gm[di];
+                        C gp, gn;
+                        gp.x = go.x - rb.x * inv_beta;
+                        gp.y = go.y - rb.y * inv_beta;
+                        gn.x = gp.x + tb.x * inv_beta;
+                        gn.y = gp.y + tb.y * inv_beta;
+                        Gm[di] = gn;
+                        lb.x = tau * gp.x + tb.x;
+                        lb.y = tau * gp.y + tb.y;
+                    }
+                    Rst[rloc * s_pad + col] = lb;
+                }
+            }
+        }
+        __syncthreads();
+        const int rows_here = min(KC, l - r0);
+        for (int e = tid; e < utab; e += LR_THREADS) {
+            const int i = e % n, blk = e / n;
+            C acc = Bacc[e];
+            if (side == 0) {
+                int a_lo = max(r0, i - k + 1), a_hi = min(r0 + rows_here - 1, min(i, p - 1));
+                for (int a = a_lo; a <= a_hi; ++a) {
+                    const C v = Rst[(a - r0) * s_pad + blk * k + (i - a)];
+                    acc.x += v.x;
+                    acc.y += v.y;
+                }
+            } else {
+                int c_lo = max(r0, blk * k + max(0, i - p + 1));
+                int c_hi = min(r0 + rows_here - 1, blk * k + min(k - 1, i));
+                for (int c = c_lo; c <= c_hi; ++c) {
+                    const int b = c - blk * k;
+                    const C v = Rst[(c - r0) * s_pad + (i - b)];
+                    acc.x += v.x;
+                    acc.y += v.y;
+                }
+            }
+            Bacc[e] = acc;
+        }
+    }
+    __syncthreads();
+    const int cc = n / 2;
+    for (int e = tid; e < J * n; e += LR_THREADS) {
+        const int i = e % n, j = e / n;
+        C w = d.use_w ? wtab[d.w_off + i] : cmk<C>(1, 0);
+        C out = cmulc(w, Bacc[j * n + i]);
+        if (V == 2) {
+            int fi = (2 * cc - i) % n;
+            if (fi < 0) fi += n;
+            C wf = d.use_w ? wtab[d.w_off + fi] : cmk<C>(1, 0);
+            C g = cmulc(wf, Bacc[(J + j) * n + fi]);
+            out.x += g.x;
+            out.y -= g.y;
+        }
+        ghb[d.h_off + (int64_t)j * d.h_cs + (int64_t)i * d.h_es] = out;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 
@@ -460,5 +758,114 @@ template hipError_t launch_reproj<float>(hipStream_t, const float2*, float2*, fl
 template hipError_t launch_reproj<double>(hipStream_t, const double2*, double2*, double2*, const double2*,
                                           const LRDesc*, const LRDesc&, int, int, const double2*, int64_t, double,
                                           double);
+
+template <typename R>
+static size_t cross_lds_bytes(int V, int J, int n, int s, int KC) {
+    int s_pad = ((s + 15) / 16) * 16;
+    return 2 * (size_t)V * J * n * sizeof(cplx_t<R>) + 4 * (size_t)KC * (s_pad + 4) * sizeof(R);
+}
+template <typename R>
+static size_t reproj_vjp_lds_bytes(int V, int J, int n, int s, int KC) {
+    int s_pad = ((s + 15) / 16) * 16;
+    return 3 * (size_t)V * J * n * sizeof(cplx_t<R>) + 2 * (size_t)KC * (s_pad + 4) * sizeof(R);
+}
+
+bool lowrank_vjp_lds_fits(int csize, int V, int J, int n, int k) {
+    LRDesc d{};
+    d.n = n;
+    d.k = k;
+    d.J = J;
+    d.V = V;
+    const int s = lr_s(d);
+    if (csize == 8)
+        return cross_lds_bytes<float>(V, J, n, s, 4) <= LDS_LIMIT && reproj_vjp_lds_bytes<float>(V, J, n, s, 16) <= LDS_LIMIT;
+    return cross_lds_bytes<double>(V, J, n, s, 4) <= LDS_LIMIT && reproj_vjp_lds_bytes<double>(V, J, n, s, 16) <= LDS_LIMIT;
+}
+
+template <typename R, int MAXT>
+static hipError_t launch_cross_t(dim3 grid, size_t lds, hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db,
+                                 const cplx_t<R>* gb, const cplx_t<R>* gdb, const cplx_t<R>* wtab,
+                                 const LRDesc* descs, int m0, double2* Cs, int64_t c_stride, R ib, R cz, R cdz,
+                                 int KC) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_cross_gram<R, MAXT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_cross_gram<R, MAXT>), grid, dim3(LR_THREADS), lds, st, hb, db, gb, gdb, wtab, descs, m0,
+                       Cs, c_stride, ib, cz, cdz, KC);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_cross_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* gb,
+                             const cplx_t<R>* gdb, const cplx_t<R>* wtab, const LRDesc* descs_dev,
+                             const LRDesc& proto, int m0, int count, double2* Cs, int64_t c_stride, double beta,
+                             double tau) {
+    const int s = lr_s(proto);
+    const int nt = (s + 15) / 16;
+    constexpr int MAXT = sizeof(R) == 4 ? 8 : 4;
+    const int nseg = (nt + MAXT - 1) / MAXT;
+    const int groups = (nt * nseg + LR_WAVES - 1) / LR_WAVES;
+    int KC = 16;
+    while (KC > 4 && cross_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT) KC /= 2;
+    const size_t lds = cross_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC);
+    if (lds > LDS_LIMIT) return hipErrorInvalidValue;
+    return launch_cross_t<R, MAXT>(dim3(count, groups), lds, st, hb, db, gb, gdb, wtab, descs_dev, m0, Cs, c_stride,
+                                   (R)(1.0 / beta), (R)(1.0 + tau / beta), (R)(-tau), KC);
+}
+
+template <typename R, int MAXT>
+static hipError_t launch_reproj_vjp_t(dim3 grid, size_t lds, hipStream_t st, const cplx_t<R>* hb,
+                                      const cplx_t<R>* db, const cplx_t<R>* gb, cplx_t<R>* gdb, cplx_t<R>* ghb,
+                                      const cplx_t<R>* wtab, const LRDesc* descs, int m0, const cplx_t<R>* Ss,
+                                      const cplx_t<R>* P2s, int64_t sst, R ib, R tau, R cz, R cdz, int KC) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_reproj_vjp<R, MAXT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_reproj_vjp<R, MAXT>), grid, dim3(LR_THREADS), lds, st, hb, db, gb, gdb, ghb, wtab, descs,
+                       m0, Ss, P2s, sst, ib, tau, cz, cdz, KC);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_reproj_vjp(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* gb,
+                             cplx_t<R>* gdb, cplx_t<R>* ghb, const cplx_t<R>* wtab, const LRDesc* descs_dev,
+                             const LRDesc& proto, int m0, int count, const cplx_t<R>* Ss, const cplx_t<R>* P2s,
+                             int64_t s_stride, double beta, double tau) {
+    const int s = lr_s(proto), l = lr_l(proto);
+    const int nt = (s + 15) / 16;
+    int KC = sizeof(R) == 4 ? 32 : 16;
+    while (KC > 16 && (reproj_vjp_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT ||
+                       KC > ((l + 15) / 16) * 16))
+        KC -= 16;
+    const size_t lds = reproj_vjp_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC);
+    if (lds > LDS_LIMIT) return hipErrorInvalidValue;
+    const int tiles = (KC / 16) * nt;
+    const int need = (tiles + LR_WAVES - 1) / LR_WAVES;
+    const R ib = (R)(1.0 / beta), tt = (R)tau, cz = (R)(1.0 + tau / beta), cdz = (R)(-tau);
+    dim3 grid(count);
+    if (need <= 2)
+        return launch_reproj_vjp_t<R, 2>(grid, lds, st, hb, db, gb, gdb, ghb, wtab, descs_dev, m0, Ss, P2s, s_stride,
+                                         ib, tt, cz, cdz, KC);
+    if (need <= 4)
+        return launch_reproj_vjp_t<R, 4>(grid, lds, st, hb, db, gb, gdb, ghb, wtab, descs_dev, m0, Ss, P2s, s_stride,
+                                         ib, tt, cz, cdz, KC);
+    if (need <= 6)
+        return launch_reproj_vjp_t<R, 6>(grid, lds, st, hb, db, gb, gdb, ghb, wtab, descs_dev, m0, Ss, P2s, s_stride,
+                                         ib, tt, cz, cdz, KC);
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_cross_gram<float>(hipStream_t, const float2*, const float2*, const float2*, const float2*,
+                                             const float2*, const LRDesc*, const LRDesc&, int, int, double2*, int64_t,
+                                             double, double);
+template hipError_t launch_cross_gram<double>(hipStream_t, const double2*, const double2*, const double2*,
+                                              const double2*, const double2*, const LRDesc*, const LRDesc&, int, int,
+                                              double2*, int64_t, double, double);
+template hipError_t launch_reproj_vjp<float>(hipStream_t, const float2*, const float2*, const float2*, float2*, float2*,
+                                             const float2*, const LRDesc*, const LRDesc&, int, int, const float2*,
+                                             const float2*, int64_t, double, double);
+template hipError_t launch_reproj_vjp<double>(hipStream_t, const double2*, const double2*, const double2*, double2*,
+                                              double2*, const double2*, const LRDesc*, const LRDesc&, int, int,
+                                              const double2*, const double2*, int64_t, double, double);
 
 }  // namespace shlr

@@ -36,6 +36,7 @@ EXPORTED = [
     "shlr_calibrate_spirit", "shlr_init", "shlr_iterate", "shlr_iterate_graph", "shlr_get_kspace",
     "shlr_reconstruct", "shlr_fft_lines", "shlr_lowrank_workspace_size", "shlr_lowrank_lines",
     "shlr_last_error", "shlr_version", "shlr_timing_enable", "shlr_timing_read",
+    "shlr_unrolled_sizes", "shlr_unrolled_forward", "shlr_unrolled_backward",
 ]
 TIMING_PHASES = ("xupdate", "gram", "eig", "reproj", "spirit")
 
@@ -82,6 +83,10 @@ _lib.shlr_fft_lines.argtypes = [_i32, _i32, _i32, _i32, _vp, _vp, _vp]
 _lib.shlr_lowrank_workspace_size.argtypes = [_i32, _i32, _i32, _i32, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)]
 _lib.shlr_lowrank_lines.argtypes = [_i32, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.shlr_unrolled_sizes.argtypes = [_vp, _i32, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+_lib.shlr_unrolled_forward.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, ctypes.c_size_t]
+_lib.shlr_unrolled_backward.argtypes = [_vp, _i32, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp,
+                                        ctypes.POINTER(ctypes.c_double)]
 _lib.shlr_timing_enable.argtypes = [_vp, _i32]
 _lib.shlr_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
 _lib.shlr_last_error.restype = ctypes.c_char_p
@@ -230,6 +235,43 @@ class Plan:
         _check(_lib.shlr_reconstruct(self._h, _ptr(y), _ptr(mask), _ptr(out), ctypes.byref(info)))
         return out, info
 
+    # -- reverse mode through unrolled iterations (see shlr_unrolled_* in include/shlr.h) --
+
+    def unrolled_sizes(self, n_iter):
+        ck, wk = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_lib.shlr_unrolled_sizes(self._h, int(n_iter), ctypes.byref(ck), ctypes.byref(wk)))
+        return ck.value, wk.value
+
+    def unrolled_forward(self, y, mask, n_iter):
+        """K after n_iter iterations; keeps the checkpoints for unrolled_backward."""
+        import torch
+        y, mask = self._prep(y, mask)
+        self._y, self._mask = y, mask
+        ck, _ = self.unrolled_sizes(n_iter)
+        self._ckpt = torch.empty(ck + 256, dtype=torch.uint8, device=y.device)
+        off = (-self._ckpt.data_ptr()) % 256
+        self._ckpt_ptr = ctypes.c_void_p(self._ckpt.data_ptr() + off)
+        self._ckpt_bytes = ck
+        out = torch.empty_like(y)
+        _check(_lib.shlr_unrolled_forward(self._h, int(n_iter), _ptr(y), _ptr(mask), _ptr(out), self._ckpt_ptr,
+                                          ctypes.c_size_t(ck)))
+        return out
+
+    def unrolled_backward(self, gk, n_iter):
+        """(gY, dL/dlambda) for L = Re <gk, K_n> after unrolled_forward(n_iter)."""
+        import torch
+        gk = gk.to(self.cdtype).contiguous()
+        _, wk = self.unrolled_sizes(n_iter)
+        work = torch.empty(wk + 256, dtype=torch.uint8, device=gk.device)
+        off = (-work.data_ptr()) % 256
+        gy = torch.empty_like(gk)
+        gl = ctypes.c_double()
+        _check(_lib.shlr_unrolled_backward(self._h, int(n_iter), _ptr(gk), self._ckpt_ptr,
+                                           ctypes.c_size_t(self._ckpt_bytes), ctypes.c_void_p(work.data_ptr() + off),
+                                           ctypes.c_size_t(wk), _ptr(gy), ctypes.byref(gl)))
+        self._ckpt = None
+        return gy, gl.value
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.shlr_plan_destroy(self._h)
@@ -290,3 +332,43 @@ def lowrank_lines(h, D, k, beta, tau, thr, use_vc=False, use_w=True, ranks=False
                                    _ptr(h), _ptr(D), _ptr(b), _ptr(rk) if ranks else None,
                                    ctypes.c_void_p(ws.data_ptr() + off), ctypes.c_size_t(nb), _stream()))
     return (b, rk) if ranks else b
+
+
+def _unrolled_function():
+    import torch
+
+    class UnrolledSHLR(torch.autograd.Function):
+        """K_n = n_iter SHLR iterations of (Y, lambda); backward through the library's reverse mode."""
+
+        @staticmethod
+        def forward(ctx, y, lam, mask, n_iter, params):
+            import dataclasses
+            prm = dataclasses.replace(params, lam=float(lam), normalize=False)
+            plan = Plan(prm, device=y.device)
+            k = plan.unrolled_forward(y.detach(), mask, n_iter)
+            ctx.plan, ctx.n_iter = plan, n_iter
+            return k
+
+        @staticmethod
+        def backward(ctx, gk):
+            gy, gl = ctx.plan.unrolled_backward(gk, ctx.n_iter)
+            ctx.plan.close()
+            ctx.plan = None
+            return gy, torch.tensor(gl, dtype=torch.float64), None, None, None
+
+    return UnrolledSHLR
+
+
+_UNROLLED = None
+
+
+def unrolled(y, lam, mask, n_iter, params: Params):
+    """Differentiable K_n of n_iter iterations (model PI, soft data consistency, no SPIRiT).
+
+    y: complex tensor in the layout of Y (slices packed); lam: real 0-dim tensor (data-consistency
+    weight); the other fields of ``params`` are fixed.  Y is used as given (no normalisation).
+    """
+    global _UNROLLED
+    if _UNROLLED is None:
+        _UNROLLED = _unrolled_function()
+    return _UNROLLED.apply(y, lam, mask, int(n_iter), params)

@@ -98,3 +98,38 @@ def test_lowrank_workspace_size_and_errors():
     with pytest.raises(shlr.ShlrError) as ei:
         shlr.lowrank_workspace_size(shlr.PREC_FP64, 3, 12, 256, 25, True)
     assert ei.value.code == 6
+
+
+def _raw_plan(shlr, **kw):
+    import ctypes
+    c, keep = _p(**kw).to_c()
+    h = ctypes.c_void_p()
+    shlr._check(shlr.library().shlr_plan_create(ctypes.byref(c), ctypes.byref(h)))
+    return h, keep
+
+
+@pytest.mark.parametrize("kw,ok", [
+    (dict(normalize=False), True),
+    (dict(normalize=False, use_vc=True, M=(40, 64), N=(48, 32), J=2, k_row=5, k_col=5), True),
+    (dict(normalize=True), False),                         # the caller scales Y
+    (dict(normalize=False, hard_dc=True), False),          # lambda = inf has no lambda derivative
+    (dict(normalize=False, spirit_ksize=5, lambda1=1.0), False),
+    (dict(normalize=False, model=1, M=(8,), N=(64,), L=8, k_col=4), False),
+])
+def test_unrolled_scope_and_sizes(kw, ok):
+    import ctypes
+    from paper_2107_11650_amd import shlr
+    h, keep = _raw_plan(shlr, **kw)
+    try:
+        ck, wk = ctypes.c_size_t(), ctypes.c_size_t()
+        st = shlr.library().shlr_unrolled_sizes(h, 4, ctypes.byref(ck), ctypes.byref(wk))
+        if ok:
+            assert st == 0 and ck.value > 0 and wk.value > 0
+            # checkpoints: K after each of 4 X-updates + D before each of 3 low-rank steps
+            st1 = shlr.library().shlr_unrolled_sizes(h, 1, ctypes.byref(ck), ctypes.byref(wk))
+            assert st1 == 0
+        else:
+            assert st == 6, shlr.library().shlr_last_error()
+        assert shlr.library().shlr_unrolled_sizes(h, 0, ctypes.byref(ck), ctypes.byref(wk)) != 0
+    finally:
+        shlr.library().shlr_plan_destroy(h)
