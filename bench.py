@@ -70,6 +70,51 @@ def measured_traffic(phase, prec):
     return rec["bytes_per_launch"]
 
 
+def diff_leg(batch, steps, kw, lam, beta, reps=2):
+    """Reverse mode through `steps` unrolled iterations of a batch of 8-coil 256 x 256 slices."""
+    import numpy as np
+    import torch
+    from paper_2107_11650_amd import inputs, shlr
+    J, M, N = 8, 256, 256
+    mask = inputs.mask_poisson_disc(M, N, R=4.0, acs=24, seed=2000).astype(np.uint8)
+    ys = []
+    for b in range(batch):
+        k = inputs.phantom_kspace(J, M, N, seed=1000 + b)
+        y = inputs.undersample(k, mask.astype(bool))
+        ys.append(y / np.abs(y).max())
+    p = shlr.Params(M=(M,) * batch, N=(N,) * batch, J=J, k_row=kw, k_col=kw, lam=lam, beta=beta, tau=beta,
+                    normalize=False, precision=shlr.PREC_MIXED)
+    plan = shlr.Plan(p)
+    y = torch.from_numpy(np.concatenate([v.ravel() for v in ys])).to(torch.complex64).cuda()
+    m = torch.from_numpy(np.tile(mask.ravel(), batch)).cuda()
+    gk = torch.from_numpy(inputs.random_complex(y.shape, seed=77)).to(torch.complex64).cuda()
+    tf, tb = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.unrolled_forward(y, m, steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan.unrolled_backward(gk, steps)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tf.append(t1 - t0)
+        tb.append(t2 - t1)
+    ck, wk = plan.unrolled_sizes(steps)
+    plan.close()
+    fwd, bwd = min(tf), min(tb)
+    return {
+        "workload": f"reverse mode through {steps} unrolled SHLR iterations, batch {batch} x 8 coils x 256x256 "
+                    "complex64 (seeds 1000+b, shared 2D Poisson-disc R=4 mask), window 25, lambda=1e4, beta=tau=30; "
+                    "gradient w.r.t. Y and lambda; checkpoints K and D of every iteration",
+        "forward_ms": 1e3 * fwd, "backward_ms": 1e3 * bwd,
+        "forward_ms_per_step": 1e3 * fwd / steps, "backward_ms_per_step": 1e3 * bwd / steps,
+        "backward_over_forward": bwd / fwd,
+        "unrolled_steps_per_s": steps / (fwd + bwd),
+        "checkpoint_gb": ck / 1e9, "work_gb": wk / 1e9, "reps": reps, "timing": "best of reps, wall clock with syncs",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +125,9 @@ def main():
                     help="iterations compared with the FP64 oracle (also the CPU-baseline sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-cg", type=int, default=10)
+    ap.add_argument("--no-diff", action="store_true", help="skip the reverse-mode (differentiation) leg")
+    ap.add_argument("--diff-batch", type=int, default=8)
+    ap.add_argument("--diff-steps", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -184,6 +232,9 @@ def main():
         "phases_ms_per_step": {k: v[0] / args.steps for k, v in phases.items()},
         "roofline": roof,
     }
+
+    if not args.no_diff:
+        result["differentiation"] = diff_leg(args.diff_batch, args.diff_steps, kw, lam, beta)
 
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_info
