@@ -418,12 +418,16 @@ def param_den(mask, prm: ParamParams):
     return prm.lam * mask + prm.beta * r
 
 
-def shlr_param(Yk, mask, prm: ParamParams, return_state=False):
+def shlr_param(Yk, mask, prm: ParamParams, return_state=False, fe_positions=None):
     """SHLR-P / SHLR-VP (Algorithm S2).
 
     Yk: (L, J, M, N) zero-filled centred k-space (M: frequency encode, fully
     sampled; N: phase encode).  mask: (L, N) PE lines acquired per echo.
     Returns the reconstructed k-space, (L, J, M, N).
+
+    fe_positions: run only these frequency-encode positions (the iteration of
+    each position is independent once the FE transform is applied) and return
+    their hybrid-space result, (len(fe_positions), L, J, N), scaled back.
     """
     Yk = np.asarray(Yk, dtype=np.complex128)
     mask = np.asarray(mask, dtype=bool)
@@ -433,6 +437,9 @@ def shlr_param(Yk, mask, prm: ParamParams, return_state=False):
         scale = 1.0
     Yh = ifftc(Yk / scale, axis=2)                          # 1D inverse DFT along FE
     Ym = np.transpose(Yh, (2, 0, 1, 3))                     # (M, L, J, N)
+    if fe_positions is not None:
+        Ym = Ym[np.asarray(fe_positions)]
+        M = Ym.shape[0]
     Lp, Le = param_lifts(L, N, prm)
     den = param_den(mask, prm)                              # (L, N)
     Zp = np.zeros((M, L, Lp.p, Lp.q(J)), dtype=np.complex128)
@@ -470,7 +477,10 @@ def shlr_param(Yk, mask, prm: ParamParams, return_state=False):
             dd = np.sum(np.abs(K_prev) ** 2, axis=(1, 2, 3))
             idx = np.nonzero(act)[0]
             st.active[idx[num < prm.tol * dd]] = False
-    out = fftc(np.transpose(st.K, (1, 2, 0, 3)), axis=2) * scale
+    if fe_positions is not None:
+        out = st.K * scale
+    else:
+        out = fftc(np.transpose(st.K, (1, 2, 0, 3)), axis=2) * scale
     return (out, st) if return_state else out
 
 

@@ -114,6 +114,15 @@ struct LRGroup {
     LRDesc proto;
 };
 
+// Consecutive groups whose matrix orders are within a factor 2 share the
+// eigen-solver slots: chunks of up to `slots` matrices, strides for order smax.
+struct LRRun {
+    int first, count;      // descriptors [first, first + count)
+    int g0, g1;            // groups [g0, g1)
+    int smax, slots;
+    int64_t g_stride, s_stride, scr_stride;
+};
+
 struct SliceLayout {
     int M, N;
     // complex offsets (elements of the working complex type)
@@ -135,7 +144,8 @@ struct shlr_plan {
     std::vector<LRDesc> descs;
     std::vector<LRGroup> groups;
     int s_max = 0;
-    int n_slots = 0;
+    std::vector<LRRun> runs;
+    size_t bytes_g = 0, bytes_s = 0, bytes_scr = 0;   // slot regions (max over runs)
     // byte offsets in the workspace
     size_t off_c = 0, bytes_c = 0;      // complex arena
     size_t off_r = 0, bytes_r = 0;      // real arena
@@ -143,7 +153,6 @@ struct shlr_plan {
     size_t off_desc = 0, off_g = 0, off_s = 0, off_scr = 0, off_ranks = 0, off_scal = 0;
     size_t off_spirit = 0, bytes_spirit = 0;
     size_t total = 0;
-    int64_t g_stride = 0, s_stride = 0, scr_stride = 0;
     // host tables uploaded at bind
     std::vector<double> rtab;                      // real table (FP64, converted at upload)
     std::vector<double> ctab;                      // complex table interleaved (FP64)
@@ -286,14 +295,44 @@ static LRDesc make_desc(int64_t h_off, int h_cs, int h_es, int64_t b_off, int b_
 
 static const size_t SLOT_BUDGET = (size_t)3 << 30;   // eigen-solver scratch for one chunk
 
-static void layout_slots(shlr_plan* P, int n_mat) {
-    const int s = P->s_max;
-    P->g_stride = packed_size(s);                       // double2, packed lower triangle
-    P->s_stride = (int64_t)s * s;                       // working complex
-    P->scr_stride = eig_scratch_doubles(s);             // doubles
-    const size_t per = P->g_stride * 16 + P->s_stride * P->csize + P->scr_stride * 8 + 3 * 256;
-    int slots = (int)std::max<size_t>(1, SLOT_BUDGET / per);
-    P->n_slots = std::min(n_mat, slots);
+static void layout_slots(shlr_plan* P) {
+    P->runs.clear();
+    P->bytes_g = P->bytes_s = P->bytes_scr = 0;
+    for (int gi = 0; gi < (int)P->groups.size(); ++gi) {
+        const LRGroup& g = P->groups[gi];
+        const int sg = lr_s(g.proto);
+        if (!P->runs.empty()) {
+            LRRun& r = P->runs.back();
+            int lo = sg, hi = sg;
+            for (int gj = r.g0; gj < r.g1; ++gj) {
+                lo = std::min(lo, lr_s(P->groups[gj].proto));
+                hi = std::max(hi, lr_s(P->groups[gj].proto));
+            }
+            if (hi <= 2 * lo) {
+                r.g1 = gi + 1;
+                r.count += g.count;
+                r.smax = hi;
+                continue;
+            }
+        }
+        LRRun r{};
+        r.first = g.first;
+        r.count = g.count;
+        r.g0 = gi;
+        r.g1 = gi + 1;
+        r.smax = sg;
+        P->runs.push_back(r);
+    }
+    for (LRRun& r : P->runs) {
+        r.g_stride = packed_size(r.smax);                    // double2, packed lower triangle
+        r.s_stride = (int64_t)r.smax * r.smax;                // working complex
+        r.scr_stride = eig_scratch_doubles(r.smax);           // doubles
+        const size_t per = r.g_stride * 16 + r.s_stride * P->csize + r.scr_stride * 8 + 3 * 256;
+        r.slots = (int)std::min<size_t>((size_t)r.count, std::max<size_t>(1, SLOT_BUDGET / per));
+        P->bytes_g = std::max(P->bytes_g, (size_t)r.slots * r.g_stride * 16);
+        P->bytes_s = std::max(P->bytes_s, (size_t)r.slots * r.s_stride * P->csize);
+        P->bytes_scr = std::max(P->bytes_scr, (size_t)r.slots * r.scr_stride * 8);
+    }
 }
 
 extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
@@ -468,7 +507,7 @@ extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
         P->groups.push_back(g);
     }
     for (auto& d : P->descs) P->s_max = std::max(P->s_max, lr_s(d));
-    layout_slots(P, (int)P->descs.size());
+    layout_slots(P);
     // workspace
     size_t off = 0;
     P->off_c = off;
@@ -483,11 +522,11 @@ extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
     P->off_desc = off;
     off = align256(off + P->descs.size() * sizeof(LRDesc));
     P->off_g = off;
-    off = align256(off + (size_t)P->n_slots * P->g_stride * 16);
+    off = align256(off + P->bytes_g);
     P->off_s = off;
-    off = align256(off + (size_t)P->n_slots * P->s_stride * P->csize);
+    off = align256(off + P->bytes_s);
     P->off_scr = off;
-    off = align256(off + (size_t)P->n_slots * P->scr_stride * 8);
+    off = align256(off + P->bytes_scr);
     P->off_ranks = off;
     off = align256(off + P->descs.size() * 4);
     P->off_scal = off;   // scale (n_slices doubles), maxabs (n_slices u64), flags (u32), change (2 doubles per slice)
@@ -598,40 +637,40 @@ static shlr_status spirit_xupdate(shlr_plan* P, int si);
 static double ortol_for(const shlr_plan* P) { return P->p.precision == SHLR_PREC_MIXED ? 1e-5 : 1e-3; }
 
 template <typename R>
-static shlr_status run_lowrank_groups(shlr_plan* P, const std::vector<LRGroup>& groups, cplx_t<R>* hb, cplx_t<R>* db,
-                                      cplx_t<R>* bb, const cplx_t<R>* wtab, LRDesc* desc_dev, double2* G,
-                                      cplx_t<R>* S, double* scr, int32_t* ranks, uint32_t* flags, int n_slots,
-                                      int64_t g_stride, int64_t s_stride, int64_t scr_stride, int smax) {
-    // The descriptors of all groups are contiguous.  Chunks of up to n_slots
-    // matrices: the Gram products of every group segment in the chunk, then one
-    // eigen-solver launch over the whole chunk, then the reprojections.
+static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_t<R>* bb, const cplx_t<R>* wtab,
+                               LRDesc* desc_dev, double2* G, cplx_t<R>* S, double* scr, int32_t* ranks,
+                               uint32_t* flags) {
+    // Per run, chunks of up to `slots` matrices: the Gram products of every
+    // group segment in the chunk, then one eigen-solver launch over the whole
+    // chunk, then the reprojections.
     const double ortol = ortol_for(P);
-    if (groups.empty()) return SHLR_OK;
-    const int first = groups.front().first;
-    const int total = groups.back().first + groups.back().count - first;
-    for (int c0 = first; c0 < first + total; c0 += n_slots) {
-        const int c1 = std::min(first + total, c0 + n_slots);
-        size_t e0 = 0;
-        STCHK(phase_begin(P, &e0));
-        for (const LRGroup& g : groups) {
-            const int s0 = std::max(c0, g.first), s1 = std::min(c1, g.first + g.count);
-            if (s0 >= s1) continue;
-            HIPCHK(launch_lift_gram<R>(P->stream, hb, db, wtab, desc_dev, g.proto, s0, s1 - s0,
-                                       G + (int64_t)(s0 - c0) * g_stride, g_stride, P->p.beta));
+    for (const LRRun& run : P->runs) {
+        for (int c0 = run.first; c0 < run.first + run.count; c0 += run.slots) {
+            const int c1 = std::min(run.first + run.count, c0 + run.slots);
+            size_t e0 = 0;
+            STCHK(phase_begin(P, &e0));
+            for (int gi = run.g0; gi < run.g1; ++gi) {
+                const LRGroup& g = P->groups[gi];
+                const int s0 = std::max(c0, g.first), s1 = std::min(c1, g.first + g.count);
+                if (s0 >= s1) continue;
+                HIPCHK(launch_lift_gram<R>(P->stream, hb, db, wtab, desc_dev, g.proto, s0, s1 - s0,
+                                           G + (int64_t)(s0 - c0) * run.g_stride, run.g_stride, P->p.beta));
+            }
+            STCHK(phase_end(P, 1, e0));
+            STCHK(phase_begin(P, &e0));
+            HIPCHK(launch_heig_svt<cplx_t<R>>(P->stream, desc_dev, c0, c1 - c0, G, run.g_stride, S, run.s_stride, scr,
+                                              run.scr_stride, ranks, ortol, flags, run.smax));
+            STCHK(phase_end(P, 2, e0));
+            STCHK(phase_begin(P, &e0));
+            for (int gi = run.g0; gi < run.g1; ++gi) {
+                const LRGroup& g = P->groups[gi];
+                const int s0 = std::max(c0, g.first), s1 = std::min(c1, g.first + g.count);
+                if (s0 >= s1) continue;
+                HIPCHK(launch_reproj<R>(P->stream, hb, db, bb, wtab, desc_dev, g.proto, s0, s1 - s0,
+                                        S + (int64_t)(s0 - c0) * run.s_stride, run.s_stride, P->p.beta, P->p.tau));
+            }
+            STCHK(phase_end(P, 3, e0));
         }
-        STCHK(phase_end(P, 1, e0));
-        STCHK(phase_begin(P, &e0));
-        HIPCHK(launch_heig_svt<cplx_t<R>>(P->stream, desc_dev, c0, c1 - c0, G, g_stride, S, s_stride, scr, scr_stride,
-                                          ranks, ortol, flags, smax));
-        STCHK(phase_end(P, 2, e0));
-        STCHK(phase_begin(P, &e0));
-        for (const LRGroup& g : groups) {
-            const int s0 = std::max(c0, g.first), s1 = std::min(c1, g.first + g.count);
-            if (s0 >= s1) continue;
-            HIPCHK(launch_reproj<R>(P->stream, hb, db, bb, wtab, desc_dev, g.proto, s0, s1 - s0,
-                                    S + (int64_t)(s0 - c0) * s_stride, s_stride, P->p.beta, P->p.tau));
-        }
-        STCHK(phase_end(P, 3, e0));
     }
     return SHLR_OK;
 }
@@ -704,8 +743,7 @@ static shlr_status x_update_phase(shlr_plan* P, bool track_change) {
 template <typename R>
 static shlr_status lowrank_phase(shlr_plan* P) {
     Ptrs<R> Q(P);
-    return run_lowrank_groups<R>(P, P->groups, Q.c, Q.c, Q.c, Q.c, Q.desc, Q.g, Q.s, Q.scr, Q.ranks, Q.flags,
-                                 P->n_slots, P->g_stride, P->s_stride, P->scr_stride, P->s_max);
+    return run_lowrank<R>(P, Q.c, Q.c, Q.c, Q.c, Q.desc, Q.g, Q.s, Q.scr, Q.ranks, Q.flags);
 }
 
 // One iteration of Algorithm S1 / S2: X-update, then the Z and multiplier updates.
@@ -1085,10 +1123,21 @@ static shlr_status lowrank_impl(int32_t n_mat, int32_t J, int32_t n, int32_t k, 
     tmp.p.tau = tau;
     tmp.p.precision = sizeof(R) == 4 ? SHLR_PREC_MIXED : SHLR_PREC_FP64;
     tmp.stream = st;
-    STCHK(run_lowrank_groups<R>(&tmp, std::vector<LRGroup>{g}, (C*)h_dev, (C*)d_dev, (C*)b_dev,
-                                (const C*)(ws + L.off_w), (LRDesc*)(ws + L.off_desc), (double2*)(ws + L.off_g),
-                                (C*)(ws + L.off_s), (double*)(ws + L.off_scr), ranks_dev,
-                                (uint32_t*)(ws + L.off_flags), L.slots, L.gst, L.sst, L.scst, L.s));
+    tmp.groups = {g};
+    LRRun run{};
+    run.first = 0;
+    run.count = n_mat;
+    run.g0 = 0;
+    run.g1 = 1;
+    run.smax = L.s;
+    run.slots = L.slots;
+    run.g_stride = L.gst;
+    run.s_stride = L.sst;
+    run.scr_stride = L.scst;
+    tmp.runs = {run};
+    STCHK(run_lowrank<R>(&tmp, (C*)h_dev, (C*)d_dev, (C*)b_dev, (const C*)(ws + L.off_w), (LRDesc*)(ws + L.off_desc),
+                         (double2*)(ws + L.off_g), (C*)(ws + L.off_s), (double*)(ws + L.off_scr), ranks_dev,
+                         (uint32_t*)(ws + L.off_flags)));
     HIPCHK(hipStreamSynchronize(st));   // host descriptor vectors go out of scope
     return SHLR_OK;
 }

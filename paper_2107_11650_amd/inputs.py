@@ -143,6 +143,9 @@ def mask_cartesian_vd(M: int, N: int, R: float = 3.0, n_center: int = 8, seed: i
 
 
 def _poisson_disc_count(M, N, r0, growth, rng_seed, acs):
+    """Dart throwing in a seeded random order: a pixel is kept when no kept pixel lies
+    closer than its radius r0 (1 + growth rho), rho the normalised distance to the centre.
+    The distance from every pixel to the nearest kept one is updated as pixels are kept."""
     rng = np.random.default_rng(rng_seed)
     cm, cn = M // 2, N // 2
     order = rng.permutation(M * N)
@@ -150,23 +153,23 @@ def _poisson_disc_count(M, N, r0, growth, rng_seed, acs):
     # fully sampled centre
     taken[cm - acs // 2: cm - acs // 2 + acs, cn - acs // 2: cn - acs // 2 + acs] = True
     occ = np.zeros((M, N), dtype=bool)
-    rmax = int(np.ceil(r0 * (1.0 + growth))) + 1
+    ii, jj = np.meshgrid(np.arange(M), np.arange(N), indexing="ij")
+    rho = np.hypot((ii - cm) / (M / 2), (jj - cn) / (N / 2)) / np.sqrt(2.0)
+    rad = r0 * (1.0 + growth * rho)
+    w = int(np.ceil(rad.max()))
+    off = np.arange(-w, w + 1)
+    hyp = np.hypot(off[:, None], off[None, :])
+    near = np.full((M, N), np.inf)
+    taken_f, near_f, rad_f = taken.ravel(), near.ravel(), rad.ravel()
     for idx in order:
-        i, j = divmod(int(idx), N)
-        if taken[i, j]:
+        idx = int(idx)
+        if taken_f[idx] or near_f[idx] < rad_f[idx]:
             continue
-        rho = np.hypot((i - cm) / (M / 2), (j - cn) / (N / 2)) / np.sqrt(2.0)
-        r = r0 * (1.0 + growth * rho)
-        ri = int(np.ceil(r))
-        i0, i1 = max(0, i - ri), min(M, i + ri + 1)
-        j0, j1 = max(0, j - ri), min(N, j + ri + 1)
-        win = occ[i0:i1, j0:j1]
-        if win.any():
-            ii, jj = np.nonzero(win)
-            if (np.hypot(ii + i0 - i, jj + j0 - j) < r).any():
-                continue
+        i, j = divmod(idx, N)
         occ[i, j] = True
-    del rmax
+        i0, i1 = max(0, i - w), min(M, i + w + 1)
+        j0, j1 = max(0, j - w), min(N, j + w + 1)
+        np.minimum(near[i0:i1, j0:j1], hyp[i0 - i + w:i1 - i + w, j0 - j + w:j1 - j + w], out=near[i0:i1, j0:j1])
     return taken | occ
 
 
@@ -214,6 +217,15 @@ def mask_t2_cartesian(L: int, N: int, R: int = 6, n_center: int = 16):
 # ---------------------------------------------------------------------------
 # random states for step-level tests
 # ---------------------------------------------------------------------------
+
+def ragged_sizes(n_slices: int = 32, lo: int = 192, hi: int = 320, seed: int = 3000, rates=(4, 5, 6)):
+    """Seeded slice shapes and acceleration rates of a ragged batch: [(M, N, R)], M, N ~ U{lo..hi}."""
+    rng = np.random.default_rng(seed)
+    M = rng.integers(lo, hi + 1, size=n_slices)
+    N = rng.integers(lo, hi + 1, size=n_slices)
+    R = rng.choice(np.asarray(rates), size=n_slices)
+    return [(int(m), int(n), float(r)) for m, n, r in zip(M, N, R)]
+
 
 def random_complex(shape, seed: int, scale: float = 1.0):
     rng = np.random.default_rng(seed)

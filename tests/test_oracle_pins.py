@@ -339,3 +339,16 @@ def test_param_den_has_no_zero():
     mask = np.zeros((8, 16), dtype=bool)
     den = O.param_den(mask, O.ParamParams(k_pe=5, k_l=4, beta=1.0))
     assert den.min() > 0
+
+
+def test_param_oracle_fe_subset_matches_full_run():
+    # the FE positions iterate independently: a subset run equals the same rows of the full run
+    L, J, M, N = 4, 2, 6, 16
+    k = inputs.t2_kspace(J, M, N, L=L, seed=1009)
+    mask = inputs.mask_t2_cartesian(L, N, R=4, n_center=4)
+    Y = inputs.undersample(k, mask[:, None, None, :])
+    prm = O.ParamParams(k_pe=5, k_l=2, lam=1e3, lam2=1.0, beta=3.0, vc=True, iters=3)
+    full = O.shlr_param(Y, mask, prm)
+    hyb = np.transpose(O.ifftc(full, axis=2), (2, 0, 1, 3))          # (M, L, J, N)
+    sub = O.shlr_param(Y, mask, prm, fe_positions=[1, 4])
+    assert rel(sub, hyb[[1, 4]]) < 1e-13
