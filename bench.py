@@ -40,16 +40,75 @@ def workload(J=8, M=256, N=256, seed=0):
     return inputs.undersample(k, mask), mask.astype(np.uint8)
 
 
-def lowrank_work(p, q, csize):
-    """Algorithmic work of one lifted matrix (Gram, eigen, reprojection)."""
-    s, l = min(p, q), max(p, q)
-    return {
-        "gram_flops": 4.0 * l * s * s,          # Hermitian product, complex MAC = 8 flops, half the tiles
-        "reproj_flops": 8.0 * l * s * s,        # full product A S
-        "eig_flops": 13.3 * s ** 3,             # tridiagonalisation + back-transform bookkeeping
-        "gram_bytes": p * q * csize,            # read the multiplier D
-        "reproj_bytes": 2 * p * q * csize,      # read and write D
-    }
+def lowrank_work(shapes):
+    """Algorithmic work of one iteration's lifted matrices [(p, q, count)] (Gram, eigen, reprojection)."""
+    w = {"gram": 0.0, "eig": 0.0, "reproj": 0.0}
+    for p, q, c in shapes:
+        s, l = min(p, q), max(p, q)
+        w["gram"] += c * 4.0 * l * s * s      # Hermitian product: complex MAC = 8 flops, half the tiles
+        w["reproj"] += c * 8.0 * l * s * s    # full product A S
+        w["eig"] += c * 13.3 * s ** 3         # tridiagonalisation + back-transform bookkeeping
+    return w
+
+
+def build_workload(name, prec, n_cg):
+    """(plan, Y, mask, shapes, coil-k-space elements, config dict) of a named workload."""
+    import numpy as np
+    import torch
+    from paper_2107_11650_amd import inputs, shlr
+    kw = 25
+    if name == "pi256":
+        J, M, N = 8, 256, 256
+        Y, mask = workload(J, M, N)
+        p = shlr.Params(M=(M,), N=(N,), J=J, k_row=kw, k_col=kw, lam=1e4, lambda1=10.0, beta=30.0, tau=30.0,
+                        spirit_ksize=5, n_cg=n_cg, precision=prec, max_iter=100)
+        shapes = [(N - kw + 1, kw * J, M), (M - kw + 1, kw * J, N)]
+        cfg = {"workload": "SHLR-S iteration, 8 coils, 256x256 complex64 ellipse phantom (quadratic phase, Gaussian "
+                           "coils), 2D Poisson-disc R=4 + 24x24 centre, Hankel window 25 rows/cols (512 lifts of "
+                           "232x200), SPIRiT 5x5, 10 PCG steps, lambda=1e4, lambda1=10, beta=tau=30",
+               "coils": J, "M": M, "N": N, "window": kw, "spirit_kernel": 5, "n_cg": n_cg}
+        elems = J * M * N
+    elif name == "ragged":
+        J = 12
+        sizes = inputs.ragged_sizes(32, 192, 320, seed=3000)
+        ys, ms = [], []
+        for i, (M, N, R) in enumerate(sizes):
+            k = inputs.phantom_kspace(J, M, N, seed=1000 + i)
+            m = inputs.mask_poisson_disc(M, N, R=R, acs=24, seed=2000 + i)
+            ys.append(inputs.undersample(k, m).ravel())
+            ms.append(m.astype(np.uint8).ravel())
+        Y, mask = np.concatenate(ys), np.concatenate(ms)
+        p = shlr.Params(M=tuple(s[0] for s in sizes), N=tuple(s[1] for s in sizes), J=J, k_row=kw, k_col=kw,
+                        lam=1e4, beta=30.0, tau=30.0, precision=prec, max_iter=100)
+        shapes = []
+        for M, N, _ in sizes:
+            shapes += [(N - kw + 1, kw * J, M), (M - kw + 1, kw * J, N)]
+        cfg = {"workload": "SHLR iteration over a ragged batch: 32 slices, sides U{192..320} (seed 3000), 12 coils, "
+                           "complex64, Poisson-disc R in {4,5,6} + 24x24 centre, window 25, lambda=1e4, beta=tau=30",
+               "slices": 32, "coils": J, "window": kw}
+        elems = int(Y.size)
+    elif name == "t2":
+        L, J, M, N = 8, 12, 256, 256
+        k = inputs.t2_kspace(J, M, N, L=L, seed=1004)
+        m2 = inputs.mask_t2_cartesian(L, N, R=6, n_center=16)
+        Y = inputs.undersample(k, m2[:, None, None, :])
+        mask = m2.astype(np.uint8)
+        p = shlr.Params(model=shlr.MODEL_PARAM, precision=prec, M=(M,), N=(N,), J=J, L=L, k_row=kw, k_col=4,
+                        use_vc=True, lam=1e4, lambda2=2.0, beta=30.0, tau=30.0, max_iter=100)
+        shapes = [(N - kw + 1, kw * J * 2, M * L), (L - 4 + 1, 4 * J, M * N)]
+        cfg = {"workload": "SHLR-VP iteration, T2 series: 8 echoes (TE 10..80 ms, T2 U[30,150] ms per ellipse), "
+                           "12 coils, 256x256 complex64, per-echo shifted R=6 Cartesian + 16 centre lines, PE window 25 "
+                           "with virtual coils (2048 lifts of 232x600), echo window 4 (65536 lifts of 5x48), "
+                           "lambda=1e4, lambda2=2, beta=tau=30",
+               "echoes": L, "coils": J, "M": M, "N": N}
+        elems = L * J * M * N
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    plan = shlr.Plan(p)
+    plan.init(torch.from_numpy(Y).to(plan.cdtype).cuda(), torch.from_numpy(mask).cuda())
+    if name == "pi256":
+        plan.calibrate_spirit(acs=24, reg=1e-3)
+    return plan, Y, mask, shapes, elems, cfg
 
 
 def measured_traffic(phase, prec):
@@ -121,6 +180,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--workload", choices=["pi256", "ragged", "t2"], default="pi256",
+                    help="pi256: the headline 8-coil 256x256 SHLR-S iteration; ragged: 32 slices of 12 coils; "
+                         "t2: the SHLR-VP T2 series")
     ap.add_argument("--check-iters", type=int, default=2,
                     help="iterations compared with the FP64 oracle (also the CPU-baseline sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -149,21 +211,15 @@ def main():
         return
     from paper_2107_11650_amd import shlr
 
-    J, M, N, kw = 8, 256, 256, 25
-    lam, lam1, beta = 1e4, 10.0, 30.0
-    Y, mask = workload(J, M, N)
+    kw, lam, lam1, beta = 25, 1e4, 10.0, 30.0
     prec = shlr.PREC_MIXED if args.precision == "mixed" else shlr.PREC_FP64
-    p = shlr.Params(M=(M,), N=(N,), J=J, k_row=kw, k_col=kw, lam=lam, lambda1=lam1, beta=beta, tau=beta,
-                    spirit_ksize=5, n_cg=args.n_cg, precision=prec, max_iter=100)
-    plan = shlr.Plan(p)
-    yd = torch.from_numpy(Y).to(plan.cdtype).cuda()
-    md = torch.from_numpy(mask).cuda()
-    plan.init(yd, md)
-    plan.calibrate_spirit(acs=24, reg=1e-3)
+    plan, Y, mask, shapes, elems, cfg = build_workload(args.workload, prec, args.n_cg)
 
     # accuracy check leg: K after check_iters iterations from the initial state
-    plan.iterate(args.check_iters)
-    k_check = plan.kspace().cpu().numpy().astype(np.complex128)
+    k_check = None
+    if args.workload == "pi256":
+        plan.iterate(args.check_iters)
+        k_check = plan.kspace().cpu().numpy().astype(np.complex128)
 
     plan.iterate(args.warmup)
     torch.cuda.synchronize()
@@ -178,39 +234,33 @@ def main():
     elapsed = t1 - t0
     value = args.steps / elapsed
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel: algorithmic work of one iteration / launches per iteration
     csize = 8 if prec == shlr.PREC_MIXED else 16
-    pr, qr = N - kw + 1, kw * J
-    pc, qc = M - kw + 1, kw * J
-    wr, wc = lowrank_work(pr, qr, csize), lowrank_work(pc, qc, csize)
-    per_launch = {  # one launch of each low-rank kernel covers every row and column matrix of the step
-        "gram": (M * wr["gram_flops"] + N * wc["gram_flops"]) / 2,
-        "eig": (M * wr["eig_flops"] + N * wc["eig_flops"]) / 2,
-        "reproj": (M * wr["reproj_flops"] + N * wc["reproj_flops"]) / 2,
-    }
-    # rows and columns are two launches per phase per step
+    work = lowrank_work(shapes)
     dom = max(("gram", "eig", "reproj", "xupdate", "spirit"), key=lambda k: phases[k][0])
     ms_dom, n_dom = phases[dom]
     avg_ms = ms_dom / max(n_dom, 1)
+    launches_per_step = n_dom / args.steps
     if dom in ("gram", "reproj"):
         peak = PEAK_TFLOPS_FP32_MFMA if prec == shlr.PREC_MIXED else PEAK_TFLOPS_FP64
-        achieved = per_launch[dom] / (avg_ms * 1e-3) / 1e12
+        achieved = work[dom] / launches_per_step / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "unit": "TFLOP/s"}
     elif dom == "eig":
         peak = PEAK_TFLOPS_FP64
-        achieved = per_launch[dom] / (avg_ms * 1e-3) / 1e12
+        achieved = work[dom] / launches_per_step / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "unit": "TFLOP/s"}
     else:
-        # transform phases: one read and one write of each J x M x N array touched per launch
+        # transform phases: one read and one write of each coil k-space array touched per launch
         peak = PEAK_HBM_GBS
-        bytes_launch = 6 * J * M * N * csize
+        bytes_launch = 6 * elems * csize / launches_per_step
         achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "unit": "GB/s"}
+    traffic = measured_traffic(dom, prec) if args.workload == "pi256" else None
     roof.update({"kernel": dom, "achieved": achieved, "peak": peak, "frac": achieved / peak,
-                 "traffic": measured_traffic(dom, prec), "avg_launch_ms": avg_ms, "launches": n_dom})
+                 "traffic": traffic, "avg_launch_ms": avg_ms, "launches": n_dom})
 
     result = {
-        "metric": METRIC,
+        "metric": METRIC if args.workload == "pi256" else f"SHLR iterations/sec ({args.workload} workload)",
         "value": value,
         "unit": "iterations/s",
         "n_gpus": 1,
@@ -222,21 +272,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == shlr.PREC_MIXED else "f64",
         "data": "synthetic",
-        "config": {
-            "workload": "SHLR-S iteration, 8 coils, 256x256 complex64 ellipse phantom (quadratic phase, Gaussian "
-                        "coils), 2D Poisson-disc R=4 + 24x24 centre, Hankel window 25 rows/cols (512 lifts of "
-                        "232x200), SPIRiT 5x5, 10 PCG steps, lambda=1e4, lambda1=10, beta=tau=30",
-            "coils": J, "M": M, "N": N, "window": kw, "spirit_kernel": 5, "n_cg": args.n_cg,
-            "eig_dtype": "f64",
-        },
+        "config": {**cfg, "eig_dtype": "f64"},
         "phases_ms_per_step": {k: v[0] / args.steps for k, v in phases.items()},
         "roofline": roof,
     }
 
-    if not args.no_diff:
+    if not args.no_diff and args.workload == "pi256":
         result["differentiation"] = diff_leg(args.diff_batch, args.diff_steps, kw, lam, beta)
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "pi256":
         from threadpoolctl import threadpool_info
         from oracle import shlr_oracle as O
         Yn = Y / np.abs(Y).max()
