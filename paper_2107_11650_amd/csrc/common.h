@@ -71,6 +71,50 @@ __device__ inline double dpp_shift_d(double v, int ctrl_sel) {
     }
     return __hiloint2double(rhi, rlo);
 }
+// sum over each row of 16 lanes, valid in the row's lane 15
+__device__ inline double row16_sum_to15(double v) {
+    v += dpp_shift_d(v, 1);
+    v += dpp_shift_d(v, 2);
+    v += dpp_shift_d(v, 4);
+    v += dpp_shift_d(v, 8);
+    return v;
+}
+// a double moved between lanes by a DPP control (all lanes of the row valid)
+template <int CTRL>
+__device__ inline double dpp_move_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ inline double2 dpp_move_z(double2 v) {
+    return make_double2(dpp_move_d<CTRL>(v.x), dpp_move_d<CTRL>(v.y));
+}
+// Sums of four complex values v[0..3] over each row of 16 lanes (reduce-scatter: row rotate
+// by 8, half mirror, then quad butterflies).  On return lane l of a row holds the total of
+// v[k] with k = 2 (l & 8 ? 1 : 0) + ((l & 7) >= 4 ? 1 : 0), and all four lanes of a quad agree.
+__device__ inline double2 row16_reduce4_z(const double2 v[4], int lr) {
+    const bool hi8 = (lr & 8) != 0, hi4 = (lr & 7) >= 4;
+    const double2 sA = hi8 ? v[0] : v[2], sB = hi8 ? v[1] : v[3];
+    double2 kA = hi8 ? v[2] : v[0], kB = hi8 ? v[3] : v[1];
+    const double2 rA = dpp_move_z<0x128>(sA), rB = dpp_move_z<0x128>(sB);   // row_ror:8
+    kA.x += rA.x;
+    kA.y += rA.y;
+    kB.x += rB.x;
+    kB.y += rB.y;
+    const double2 s2 = hi4 ? kA : kB;
+    double2 k2 = hi4 ? kB : kA;
+    const double2 r2 = dpp_move_z<0x141>(s2);                                 // row_half_mirror
+    k2.x += r2.x;
+    k2.y += r2.y;
+    double2 t = dpp_move_z<0xB1>(k2);                                         // quad_perm [1,0,3,2]
+    k2.x += t.x;
+    k2.y += t.y;
+    t = dpp_move_z<0x4E>(k2);                                                 // quad_perm [2,3,0,1]
+    k2.x += t.x;
+    k2.y += t.y;
+    return k2;
+}
 __device__ inline double wave_sum_to63(double v) {
     v += dpp_shift_d(v, 1);
     v += dpp_shift_d(v, 2);

@@ -50,12 +50,30 @@ __device__ inline double block_max(double v, double* red) {
     return t;
 }
 
-// number of eigenvalues of the symmetric tridiagonal (d, e2 = e^2) below x
+// number of eigenvalues of the symmetric tridiagonal (d, e2 = e^2) below x; the entries
+// are read four at a time ahead of the dependent divisions
 __device__ inline int sturm_count(const double* d, const double* e2, int s, double x, double pivmin) {
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     int c = q < 0.0;
-    for (int i = 1; i < s; ++i) {
+    int i = 1;
+    for (; i + 3 < s; i += 4) {
+        const double d0 = d[i], d1 = d[i + 1], d2 = d[i + 2], d3 = d[i + 3];
+        const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
+        q = d0 - x - f0 / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        c += q < 0.0;
+        q = d1 - x - f1 / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        c += q < 0.0;
+        q = d2 - x - f2 / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        c += q < 0.0;
+        q = d3 - x - f3 / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        c += q < 0.0;
+    }
+    for (; i < s; ++i) {
         q = d[i] - x - e2[i - 1] / q;
         if (fabs(q) < pivmin) q = -pivmin;
         c += q < 0.0;
@@ -80,12 +98,71 @@ __device__ inline double start_entry(int i, int k) {
 // i = s-2 .. 0 gives Q x (back-transform), i = 0 .. s-2 gives Q^H x.
 // Reflectors are staged in LDS in chunks shared by all waves; one wave per
 // column, lane l owning rows l, l + 64, ... in registers.  All threads call.
-template <int SL>
-__device__ void apply_reflectors(double2* __restrict__ Xv, int nvec, int s, int smax,
-                                 const double2* __restrict__ A, const double* shv, double2* stage,
-                                 bool adjoint) {
+template <int SL, int VB>
+__device__ void apply_reflectors_t(double2* __restrict__ Xv, int nvec, int s, int smax,
+                                   const double2* __restrict__ A, const double* shv, double2* stage,
+                                   bool adjoint) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nw = EIG_THREADS / 64;
+    // every wave's columns fit one batch: they stay in registers across the chunks
+    const bool resident = nvec <= nw * VB;
+    double2 xr[VB][SL];
+    auto load_cols = [&](int k0) {
+#pragma unroll
+        for (int v = 0; v < VB; ++v)
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) {
+                const int row = sl * 64 + lane;
+                xr[v][sl] = (k0 + v < nvec && row < s) ? Xv[(int64_t)(k0 + v) * s + row] : make_double2(0.0, 0.0);
+            }
+    };
+    auto store_cols = [&](int k0) {
+#pragma unroll
+        for (int v = 0; v < VB; ++v)
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) {
+                const int row = sl * 64 + lane;
+                if (k0 + v < nvec && row < s) Xv[(int64_t)(k0 + v) * s + row] = xr[v][sl];
+            }
+    };
+    auto apply_chunk = [&](int c0, int cnt) {
+        for (int j = 0; j < cnt; ++j) {
+            const int i = adjoint ? c0 + j : s - 2 - c0 - j;
+            const double hh = shv[i];
+            if (!(hh > 0)) continue;
+            double2 ul[SL];
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) {
+                const int row = sl * 64 + lane;
+                ul[sl] = row < s ? stage[j * smax + row] : make_double2(0.0, 0.0);
+            }
+            double dr[VB], di[VB];
+#pragma unroll
+            for (int v = 0; v < VB; ++v) {
+                dr[v] = 0;
+                di[v] = 0;
+#pragma unroll
+                for (int sl = 0; sl < SL; ++sl) {
+                    dr[v] += ul[sl].x * xr[v][sl].x + ul[sl].y * xr[v][sl].y;
+                    di[v] += ul[sl].x * xr[v][sl].y - ul[sl].y * xr[v][sl].x;
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < VB; ++v) {
+                dr[v] = wave_sum_all(dr[v]) / hh;
+                di[v] = wave_sum_all(di[v]) / hh;
+            }
+#pragma unroll
+            for (int v = 0; v < VB; ++v)
+#pragma unroll
+                for (int sl = 0; sl < SL; ++sl) {
+                    xr[v][sl].x -= ul[sl].x * dr[v] - ul[sl].y * di[v];
+                    xr[v][sl].y -= ul[sl].x * di[v] + ul[sl].y * dr[v];
+                }
+        }
+    };
+    __syncthreads();   // Xv was written by every thread
+    if (resident && wave * VB < nvec) load_cols(wave * VB);
     for (int c0 = 0; c0 + 1 < s && nvec > 0; c0 += EIG_STAGE) {
         const int cnt = min(EIG_STAGE, s - 1 - c0);
         __syncthreads();
@@ -95,46 +172,314 @@ __device__ void apply_reflectors(double2* __restrict__ Xv, int nvec, int s, int 
             stage[j * smax + row] = (row > i && shv[i] > 0) ? A[pk(row, i, s)] : make_double2(0.0, 0.0);
         }
         __syncthreads();
-        for (int k = wave; k < nvec; k += nw) {
-            double2 xr[SL];
-#pragma unroll
-            for (int sl = 0; sl < SL; ++sl) {
-                const int row = sl * 64 + lane;
-                xr[sl] = row < s ? Xv[(int64_t)k * s + row] : make_double2(0.0, 0.0);
-            }
-            for (int j = 0; j < cnt; ++j) {
-                const int i = adjoint ? c0 + j : s - 2 - c0 - j;
-                const double hh = shv[i];
-                if (!(hh > 0)) continue;
-                double dr = 0, di = 0;
-                double2 ul[SL];
-#pragma unroll
-                for (int sl = 0; sl < SL; ++sl) {
-                    const int row = sl * 64 + lane;
-                    ul[sl] = row < s ? stage[j * smax + row] : make_double2(0.0, 0.0);
-                    dr += ul[sl].x * xr[sl].x + ul[sl].y * xr[sl].y;
-                    di += ul[sl].x * xr[sl].y - ul[sl].y * xr[sl].x;
-                }
-                for (int off = 32; off > 0; off >>= 1) {
-                    dr += __shfl_xor(dr, off, 64);
-                    di += __shfl_xor(di, off, 64);
-                }
-                dr /= hh;
-                di /= hh;
-#pragma unroll
-                for (int sl = 0; sl < SL; ++sl) {
-                    xr[sl].x -= ul[sl].x * dr - ul[sl].y * di;
-                    xr[sl].y -= ul[sl].x * di + ul[sl].y * dr;
-                }
-            }
-#pragma unroll
-            for (int sl = 0; sl < SL; ++sl) {
-                const int row = sl * 64 + lane;
-                if (row < s) Xv[(int64_t)k * s + row] = xr[sl];
+        if (resident) {
+            if (wave * VB < nvec) apply_chunk(c0, cnt);
+        } else {
+            for (int k0 = wave * VB; k0 < nvec; k0 += nw * VB) {
+                load_cols(k0);
+                apply_chunk(c0, cnt);
+                store_cols(k0);
             }
         }
     }
+    if (resident && wave * VB < nvec) store_cols(wave * VB);
     __syncthreads();
+}
+
+// x <- P_i x for every column of Xv (see apply_reflectors_t); the batch width follows the column count
+template <int SL>
+__device__ void apply_reflectors(double2* __restrict__ Xv, int nvec, int s, int smax,
+                                 const double2* __restrict__ A, const double* shv, double2* stage,
+                                 bool adjoint) {
+    constexpr int nw = EIG_THREADS / 64;
+    if (nvec <= nw) apply_reflectors_t<SL, 1>(Xv, nvec, s, smax, A, shv, stage, adjoint);
+    else if (nvec <= 2 * nw) apply_reflectors_t<SL, 2>(Xv, nvec, s, smax, A, shv, stage, adjoint);
+    else apply_reflectors_t<SL, 4>(Xv, nvec, s, smax, A, shv, stage, adjoint);
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident Householder tridiagonalisation (orders s <= RR_MAXS).
+// One workgroup of 512 threads holds the Hermitian matrix in registers as the
+// 16 x 16 blocks (I, J), I >= J, of its lower triangle (diagonal blocks held
+// in full): wave w owns blocks w, w + 8, ... in column-major block order, and
+// lane l holds row I*16 + l%16, columns J*16 + 4(l/16) + 0..3.  Step i:
+//  (a) every lane applies the pending rank-2 update of step i-1 to its live
+//      elements (rows and columns > i), captures column i+1, and forms the
+//      products with u_i: row partials (reduced over the 4 lane groups) and,
+//      in off-diagonal blocks, column partials (reduced over 16 lanes);
+//  (b) one thread per row gathers p = A u_i / h_i in a fixed block order;
+//      then q = p - (u^H p / 2h) u, column i+1 finished with the update of
+//      step i, and the reflector of step i+1.
+// Four barriers per step; the matrix never leaves the registers.  Outputs the
+// same quantities as the in-memory reduction of k_heig_svt: the reflectors
+// u_i below the diagonal of the packed matrix, and per matrix the diagonal,
+// the complex off-diagonal and h_i as 4 s doubles at the start of the scratch.
+// ---------------------------------------------------------------------------
+constexpr int RR_MAXS = 208;
+constexpr int RR_THREADS = 512;
+
+__device__ inline int rr_bidx(int I, int J, int nb) { return J * nb - (J * (J - 1)) / 2 + (I - J); }
+
+template <int MAXB>
+__global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __restrict__ descs, int m0,
+                                                              double2* __restrict__ Gs, int64_t g_stride,
+                                                              double* __restrict__ scr, int64_t scr_stride) {
+    // separate LDS objects, so that the stores of partial sums do not order the vector loads
+    constexpr int RR_SP = ((RR_MAXS + 15) / 16) * 16;
+    constexpr int RR_NB = RR_SP / 16, RR_NBLK = RR_NB * (RR_NB + 1) / 2;
+    __shared__ double2 up[RR_SP];                 // pending update u_{i-1}, by absolute row
+    __shared__ double2 qp[RR_SP];                 // pending q_{i-1}
+    __shared__ double2 uc[RR_SP];                 // current reflector u_i
+    __shared__ double2 xraw[RR_SP];               // captured column i+1
+    __shared__ double2 yrow[RR_NBLK * 16];        // [block][16] row partials
+    __shared__ double2 ycol[RR_NBLK * 16];        // [block][16] column partials
+    __shared__ double2 salpha[2];                 // [0] alpha of the reflector, [1] p_j
+    __shared__ double red[2 * (RR_THREADS / 64)];  // per-wave partial sums: u^H p, then tails
+    const LRDesc dsc = descs[m0 + blockIdx.x];
+    const int s = lr_s(dsc);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nb = (s + 15) >> 4, sp = nb * 16;
+    const int nblk = nb * (nb + 1) / 2;
+    double2* A = Gs + (int64_t)blockIdx.x * g_stride;
+    double* tri = scr + (int64_t)blockIdx.x * scr_stride;   // diag | off re | off im | h
+    double* tdd = tri;
+    double* ter = tri + s;
+    double* tei = tri + 2 * s;
+    double* thv = tri + 3 * s;
+
+    // block coordinates of this wave's blocks (column-major block order)
+    int bI[MAXB], bJ[MAXB];
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+        int b = wave + 8 * t, J = 0;
+        while (J < nb && b >= nb - J) {
+            b -= nb - J;
+            ++J;
+        }
+        bJ[t] = J;
+        bI[t] = J + b;
+    }
+    double2 av[MAXB][4];
+    const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+        const bool has = wave + 8 * t < nblk;
+        const int r = bI[t] * 16 + lr;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = bJ[t] * 16 + 4 * lg + k;
+            double2 v = make_double2(0.0, 0.0);
+            if (has && r < s && c < s) {
+                if (r >= c) v = A[pk(r, c, s)];
+                else {
+                    v = A[pk(c, r, s)];
+                    v.y = -v.y;
+                }
+            }
+            av[t][k] = v;
+        }
+    }
+    for (int e = tid; e < sp; e += RR_THREADS) {
+        up[e] = make_double2(0.0, 0.0);
+        qp[e] = make_double2(0.0, 0.0);
+        uc[e] = make_double2(0.0, 0.0);
+    }
+    // column 0 into xraw
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+        if (wave + 8 * t < nblk && bJ[t] == 0 && lg == 0) {
+            const int r = bI[t] * 16 + lr;
+            if (r < s) xraw[r] = av[t][0];
+        }
+    }
+    __syncthreads();
+
+    // Thread t works on row j + t of the current column j (every row count here is below 512).
+    // finish_and_reflect: column j (rows >= j, raw in xraw) minus the update (u, q) of step j-1
+    // (in uc / qp, none for j = 0), its diagonal entry, and the reflector of column j into uc.
+    double whh = 1.0;        // h of the current reflector (every thread)
+    bool wrefl = false;
+    double2 xr_keep = make_double2(0.0, 0.0);
+    auto finish_and_reflect = [&](int j, bool pending, double2 q_j) {
+        const int r = j + tid;
+        double tail = 0;
+        if (r < s) {
+            double2 v = xraw[r];
+            if (pending) {
+                const double2 u0 = uc[j];
+                const double2 ur = uc[r], qr = qp[r];
+                v.x -= qr.x * u0.x + qr.y * u0.y + ur.x * q_j.x + ur.y * q_j.y;
+                v.y -= qr.y * u0.x - qr.x * u0.y + ur.y * q_j.x - ur.x * q_j.y;
+            }
+            xr_keep = v;
+            if (r == j) tdd[j] = v.x;
+            if (r == j + 1) salpha[0] = v;
+            if (r > j + 1) tail = cabs2(v);
+        }
+        tail = wave_sum_to63(tail);
+        if (lane == 63) red[RR_THREADS / 64 + wave] = tail;
+        __syncthreads();
+        if (j + 1 >= s) return;
+        tail = 0;
+        for (int w = 0; w < RR_THREADS / 64; ++w) tail += red[RR_THREADS / 64 + w];
+        const double2 al = salpha[0];
+        const bool refl = tail > 0.0;
+        double hh = 1.0, xn = 0.0;
+        double2 ph = make_double2(1.0, 0.0);
+        if (refl) {
+            const double aabs = sqrt(al.x * al.x + al.y * al.y);
+            xn = sqrt(aabs * aabs + tail);
+            if (aabs > 0) ph = make_double2(al.x / aabs, al.y / aabs);
+            hh = xn * xn + aabs * xn;
+        }
+        if (tid == 0) {
+            ter[j] = refl ? -ph.x * xn : al.x;
+            tei[j] = refl ? -ph.y * xn : al.y;
+            thv[j] = refl ? hh : 0.0;
+        }
+        if (r > j && r < s) {
+            double2 u = make_double2(0.0, 0.0);
+            if (refl) {
+                u = (r == j + 1) ? make_double2(al.x + ph.x * xn, al.y + ph.y * xn) : xr_keep;
+                A[pk(r, j, s)] = u;
+            }
+            uc[r] = u;
+        }
+        whh = hh;
+        wrefl = refl;
+    };
+
+    finish_and_reflect(0, false, make_double2(0.0, 0.0));
+    __syncthreads();
+
+    for (int i = 0; i + 1 < s; ++i) {
+        const int jlo = (i + 1) >> 4;
+        const bool pend = i > 0;
+        // (a) pending update, capture of column i+1, products with u_i
+#pragma unroll
+        for (int t = 0; t < MAXB; ++t) {
+            int b = wave + 8 * t;
+            if (b >= nblk || bJ[t] < jlo) continue;   // uniform over the wave
+            int I = bI[t], J = bJ[t];
+            // keep the block's index arithmetic inside the step (it would otherwise be hoisted
+            // into vector registers that the matrix needs)
+            asm volatile("" : "+s"(I), "+s"(J), "+s"(b));
+            const int r = I * 16 + lr;
+            // every element of the block is live (rows and columns > i, inside the matrix)
+            const bool full = J * 16 > i && I * 16 + 16 <= s && J * 16 + 16 <= s;
+            const bool rok = r > i && r < s;
+            double2 upr = make_double2(0.0, 0.0), qpr = upr, ur = upr;
+            if (rok) {
+                ur = uc[r];
+                if (pend) {
+                    upr = up[r];
+                    qpr = qp[r];
+                }
+            }
+            double2 yr = make_double2(0.0, 0.0);
+            double2 yc[4];
+            if (full) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = J * 16 + 4 * lg + k;
+                    double2 a = av[t][k];
+                    if (pend) {
+                        const double2 uq = up[c], qq = qp[c];
+                        a.x -= upr.x * qq.x + upr.y * qq.y + qpr.x * uq.x + qpr.y * uq.y;
+                        a.y -= upr.y * qq.x - upr.x * qq.y + qpr.y * uq.x - qpr.x * uq.y;
+                        av[t][k] = a;
+                    }
+                    const double2 ucc = uc[c];
+                    yr.x += a.x * ucc.x - a.y * ucc.y;
+                    yr.y += a.x * ucc.y + a.y * ucc.x;
+                    yc[k].x = a.x * ur.x + a.y * ur.y;   // conj(a) u_r
+                    yc[k].y = a.x * ur.y - a.y * ur.x;
+                }
+                if (J * 16 == i + 1 && lg == 0) xraw[r] = av[t][0];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = J * 16 + 4 * lg + k;
+                    yc[k] = make_double2(0.0, 0.0);
+                    if (rok && c > i && c < s) {
+                        double2 a = av[t][k];
+                        if (pend) {
+                            const double2 uq = up[c], qq = qp[c];
+                            a.x -= upr.x * qq.x + upr.y * qq.y + qpr.x * uq.x + qpr.y * uq.y;
+                            a.y -= upr.y * qq.x - upr.x * qq.y + qpr.y * uq.x - qpr.x * uq.y;
+                            av[t][k] = a;
+                        }
+                        if (c == i + 1 && r >= c) xraw[r] = a;
+                        const double2 ucc = uc[c];
+                        yr.x += a.x * ucc.x - a.y * ucc.y;
+                        yr.y += a.x * ucc.y + a.y * ucc.x;
+                        yc[k].x = a.x * ur.x + a.y * ur.y;
+                        yc[k].y = a.x * ur.y - a.y * ur.x;
+                    }
+                }
+            }
+            yr.x += __shfl_xor(yr.x, 16, 64);
+            yr.y += __shfl_xor(yr.y, 16, 64);
+            yr.x += __shfl_xor(yr.x, 32, 64);
+            yr.y += __shfl_xor(yr.y, 32, 64);
+            if (lane < 16) yrow[b * 16 + lane] = yr;
+            if (I != J) {
+                // the column sums of the diagonal blocks are their row sums (held in full)
+                const double2 cs = row16_reduce4_z(yc, lr);
+                if ((lr & 3) == 0) {
+                    const int kk = 2 * ((lr >> 3) & 1) + (((lr & 7) >= 4) ? 1 : 0);
+                    ycol[b * 16 + 4 * lg + kk] = cs;
+                }
+            }
+        }
+        __syncthreads();
+        // (b) p = A u_i / h and u^H p over all threads, then q_i, column i+1 and the next reflector
+        {
+            const int j = i + 1;
+            const int r = j + tid;
+            const bool refl = wrefl;
+            const double hh = whh;
+            double2 pv = make_double2(0.0, 0.0);
+            double uhp = 0;
+            if (r < s && refl) {
+                const int I = r >> 4, rr = r & 15;
+                for (int J = jlo; J <= I; ++J) {
+                    const double2 v = yrow[rr_bidx(I, J, nb) * 16 + rr];
+                    pv.x += v.x;
+                    pv.y += v.y;
+                }
+                for (int I2 = I + 1; I2 < nb; ++I2) {
+                    const double2 v = ycol[rr_bidx(I2, I, nb) * 16 + rr];
+                    pv.x += v.x;
+                    pv.y += v.y;
+                }
+                pv.x /= hh;
+                pv.y /= hh;
+                const double2 u = uc[r];
+                uhp = u.x * pv.x + u.y * pv.y;   // Re(conj(u) p)
+                if (r == j) salpha[1] = pv;
+            }
+            uhp = wave_sum_to63(uhp);
+            if (lane == 63) red[wave] = uhp;
+            __syncthreads();
+            uhp = 0;
+            for (int w = 0; w < RR_THREADS / 64; ++w) uhp += red[w];
+            const double Kc = uhp / (2.0 * hh);
+            double2 qj = make_double2(0.0, 0.0);
+            if (refl) {
+                const double2 pj = salpha[1], uj = uc[j];
+                qj = make_double2(pj.x - Kc * uj.x, pj.y - Kc * uj.y);
+            }
+            if (r < s) {
+                const double2 u = refl ? uc[r] : make_double2(0.0, 0.0);
+                up[r] = u;
+                qp[r] = make_double2(pv.x - Kc * u.x, pv.y - Kc * u.y);   // read back by this thread only
+            }
+            finish_and_reflect(j, refl, qj);
+        }
+        __syncthreads();
+    }
 }
 
 template <typename OC, int SL>
@@ -144,7 +489,7 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
                                                              double* __restrict__ scr, int64_t scr_stride,
                                                              int32_t* __restrict__ ranks, double ortol_rel,
                                                              uint32_t* __restrict__ flags, int smax,
-                                                             VjpArgs<OC> vj) {
+                                                             VjpArgs<OC> vj, int tri_in) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int UNR = SL <= 3 ? 4 : (SL == 4 ? 3 : 2);   // columns per wave with loads in flight
     const LRDesc dsc = descs[m0 + blockIdx.x];
@@ -180,191 +525,202 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
     double* W = base + 16 * s + 64;    // s*s interleaved [i*s + k]
     double* LU = W + (int64_t)s * s;   // 2*s*s: X (double2, column-major) of the back-transform
 
-    // ---- 1. tridiagonalisation ---------------------------------------------
-    // Step i: x = column i below the diagonal, P_i = I - u u^H / h maps x to
-    // -phase |x| e_1, and the trailing block becomes A - u q^H - q u^H with
-    // p = A u / h, q = p - (u^H p / 2h) u.  The rank-2 update of step i is
-    // applied lazily during the Hermitian matrix-vector product of step i+1,
-    // which reads (and writes back) only the lower triangle, one column per
-    // wave with lanes over rows (coalesced).  The column that step i+1 reduces
-    // is captured during that sweep and finished in LDS, so each step makes a
-    // single round trip to memory.
-    double2* xcur = uvec;                      // x_i, then u_i
-    double2* xnxt = pvec;                      // x_{i+1} being formed
-    bool pend = false;
-    double part = 0;
-    for (int t = tid; t + 1 < s; t += EIG_THREADS) {
-        const double2 v = A[pk(1 + t, 0, s)];
-        xcur[t] = v;
-        if (t > 0) part += cabs2(v);
-    }
-    if (tid == 0) sdd[0] = A[pk(0, 0, s)].x;
-    double tail = block_sum(part, red);
-    for (int i = 0; i + 1 < s; ++i) {
-        const int ni = s - i - 1;
-        const double2 alpha = xcur[0];
-        const bool refl = tail > 0.0;
-        double hh = 1.0;
-        double2 ph = make_double2(1.0, 0.0);
-        double xn = 0.0;
-        if (refl) {
-            const double aabs = sqrt(cabs2(alpha));
-            xn = sqrt(aabs * aabs + tail);
-            if (aabs > 0) ph = make_double2(alpha.x / aabs, alpha.y / aabs);
-            hh = xn * xn + aabs * xn;
-        }
-        __syncthreads();   // every thread has read xcur[0]
-        if (tid == 0) {
-            if (refl) {
-                xcur[0] = make_double2(alpha.x + ph.x * xn, alpha.y + ph.y * xn);
-                secr[i] = -ph.x * xn;
-                seci[i] = -ph.y * xn;
-                shv[i] = hh;
-            } else {
-                secr[i] = alpha.x;
-                seci[i] = alpha.y;
-                shv[i] = 0.0;
-            }
+    if (tri_in) {
+        // reduced by k_tridiag_rr: diagonal, complex off-diagonal and h_i at the start of the scratch
+        for (int t = tid; t < s; t += EIG_THREADS) {
+            sdd[t] = base[t];
+            secr[t] = base[s + t];
+            seci[t] = base[2 * s + t];
+            shv[t] = base[3 * s + t];
         }
         __syncthreads();
-        // fused sweep: trailing block -= pending update (written back); p = A u;
-        // column i+1 captured into xraw.  UNR columns per wave at a time with all
-        // their loads issued first; slots outside a column are skipped.
-        double2 accr[SL];
-#pragma unroll
-        for (int sl = 0; sl < SL; ++sl) accr[sl] = make_double2(0.0, 0.0);
-        double wur = 0;   // this wave's share of u^H (h p)
-        const int ncol = (pend || refl) ? ni : 1;
-        for (int tc0 = wave; tc0 < ncol; tc0 += UNR * nw) {
-            double2 av[UNR][SL];
-#pragma unroll
-            for (int uu = 0; uu < UNR; ++uu) {
-                const int tc = tc0 + uu * nw;
-#pragma unroll
-                for (int sl = 0; sl < SL; ++sl) {
-                    const int t = sl * 64 + lane;
-                    av[uu][sl] = make_double2(0.0, 0.0);
-                    if (tc < ncol && t >= tc && t < ni) av[uu][sl] = A[pk(i + 1 + t, i + 1 + tc, s)];
+    } else {
+        // ---- 1. tridiagonalisation ---------------------------------------------
+        // Step i: x = column i below the diagonal, P_i = I - u u^H / h maps x to
+        // -phase |x| e_1, and the trailing block becomes A - u q^H - q u^H with
+        // p = A u / h, q = p - (u^H p / 2h) u.  The rank-2 update of step i is
+        // applied lazily during the Hermitian matrix-vector product of step i+1,
+        // which reads (and writes back) only the lower triangle, one column per
+        // wave with lanes over rows (coalesced).  The column that step i+1 reduces
+        // is captured during that sweep and finished in LDS, so each step makes a
+        // single round trip to memory.
+        double2* xcur = uvec;                      // x_i, then u_i
+        double2* xnxt = pvec;                      // x_{i+1} being formed
+        bool pend = false;
+        double part = 0;
+        for (int t = tid; t + 1 < s; t += EIG_THREADS) {
+            const double2 v = A[pk(1 + t, 0, s)];
+            xcur[t] = v;
+            if (t > 0) part += cabs2(v);
+        }
+        if (tid == 0) sdd[0] = A[pk(0, 0, s)].x;
+        double tail = block_sum(part, red);
+        for (int i = 0; i + 1 < s; ++i) {
+            const int ni = s - i - 1;
+            const double2 alpha = xcur[0];
+            const bool refl = tail > 0.0;
+            double hh = 1.0;
+            double2 ph = make_double2(1.0, 0.0);
+            double xn = 0.0;
+            if (refl) {
+                const double aabs = sqrt(cabs2(alpha));
+                xn = sqrt(aabs * aabs + tail);
+                if (aabs > 0) ph = make_double2(alpha.x / aabs, alpha.y / aabs);
+                hh = xn * xn + aabs * xn;
+            }
+            __syncthreads();   // every thread has read xcur[0]
+            if (tid == 0) {
+                if (refl) {
+                    xcur[0] = make_double2(alpha.x + ph.x * xn, alpha.y + ph.y * xn);
+                    secr[i] = -ph.x * xn;
+                    seci[i] = -ph.y * xn;
+                    shv[i] = hh;
+                } else {
+                    secr[i] = alpha.x;
+                    seci[i] = alpha.y;
+                    shv[i] = 0.0;
                 }
             }
-            double pcr[UNR], pci[UNR];
-#pragma unroll
-            for (int uu = 0; uu < UNR; ++uu) {
-                pcr[uu] = 0;
-                pci[uu] = 0;
-                const int tc = tc0 + uu * nw;
-                if (tc >= ncol) continue;   // uniform across the wave
-                const int c = i + 1 + tc;
-                const double2 uc = refl ? xcur[tc] : make_double2(0.0, 0.0);
-                double2 upc = make_double2(0.0, 0.0), qpc = make_double2(0.0, 0.0);
-                if (pend) { upc = up[c]; qpc = qp[c]; }
-#pragma unroll
-                for (int sl = 0; sl < SL; ++sl) {
-                    const int t = sl * 64 + lane;
-                    if (t >= tc && t < ni) {
-                        const int r = i + 1 + t;
-                        double2 a = av[uu][sl];
-                        if (pend) {
-                            const double2 qr = qp[r], ur = up[r];
-                            a.x -= qr.x * upc.x + qr.y * upc.y + ur.x * qpc.x + ur.y * qpc.y;
-                            a.y -= qr.y * upc.x - qr.x * upc.y + ur.y * qpc.x - ur.x * qpc.y;
-                            if (tc > 0) A[pk(r, c, s)] = a;   // column i+1 is finished in LDS instead
+            __syncthreads();
+            // fused sweep: trailing block -= pending update (written back); p = A u;
+            // column i+1 captured into xraw.  UNR columns per wave at a time with all
+            // their loads issued first; slots outside a column are skipped.
+            double2 accr[SL];
+    #pragma unroll
+            for (int sl = 0; sl < SL; ++sl) accr[sl] = make_double2(0.0, 0.0);
+            double wur = 0;   // this wave's share of u^H (h p)
+            const int ncol = (pend || refl) ? ni : 1;
+            for (int tc0 = wave; tc0 < ncol; tc0 += UNR * nw) {
+                double2 av[UNR][SL];
+    #pragma unroll
+                for (int uu = 0; uu < UNR; ++uu) {
+                    const int tc = tc0 + uu * nw;
+    #pragma unroll
+                    for (int sl = 0; sl < SL; ++sl) {
+                        const int t = sl * 64 + lane;
+                        av[uu][sl] = make_double2(0.0, 0.0);
+                        if (tc < ncol && t >= tc && t < ni) av[uu][sl] = A[pk(i + 1 + t, i + 1 + tc, s)];
+                    }
+                }
+                double pcr[UNR], pci[UNR];
+    #pragma unroll
+                for (int uu = 0; uu < UNR; ++uu) {
+                    pcr[uu] = 0;
+                    pci[uu] = 0;
+                    const int tc = tc0 + uu * nw;
+                    if (tc >= ncol) continue;   // uniform across the wave
+                    const int c = i + 1 + tc;
+                    const double2 uc = refl ? xcur[tc] : make_double2(0.0, 0.0);
+                    double2 upc = make_double2(0.0, 0.0), qpc = make_double2(0.0, 0.0);
+                    if (pend) { upc = up[c]; qpc = qp[c]; }
+    #pragma unroll
+                    for (int sl = 0; sl < SL; ++sl) {
+                        const int t = sl * 64 + lane;
+                        if (t >= tc && t < ni) {
+                            const int r = i + 1 + t;
+                            double2 a = av[uu][sl];
+                            if (pend) {
+                                const double2 qr = qp[r], ur = up[r];
+                                a.x -= qr.x * upc.x + qr.y * upc.y + ur.x * qpc.x + ur.y * qpc.y;
+                                a.y -= qr.y * upc.x - qr.x * upc.y + ur.y * qpc.x - ur.x * qpc.y;
+                                if (tc > 0) A[pk(r, c, s)] = a;   // column i+1 is finished in LDS instead
+                            }
+                            if (tc == 0) xraw[t] = a;
+                            if (refl) {
+                                accr[sl].x += a.x * uc.x - a.y * uc.y;
+                                accr[sl].y += a.x * uc.y + a.y * uc.x;
+                                if (t > tc) {
+                                    const double2 ut = xcur[t];
+                                    pcr[uu] += a.x * ut.x + a.y * ut.y;   // conj(a) * u_t
+                                    pci[uu] += a.x * ut.y - a.y * ut.x;
+                                }
+                            }
                         }
-                        if (tc == 0) xraw[t] = a;
-                        if (refl) {
-                            accr[sl].x += a.x * uc.x - a.y * uc.y;
-                            accr[sl].y += a.x * uc.y + a.y * uc.x;
-                            if (t > tc) {
-                                const double2 ut = xcur[t];
-                                pcr[uu] += a.x * ut.x + a.y * ut.y;   // conj(a) * u_t
-                                pci[uu] += a.x * ut.y - a.y * ut.x;
+                    }
+                }
+                if (refl) {
+    #pragma unroll
+                    for (int uu = 0; uu < UNR; ++uu) {
+                        pcr[uu] = wave_sum_to63(pcr[uu]);
+                        pci[uu] = wave_sum_to63(pci[uu]);
+                    }
+                    if (lane == 63) {
+    #pragma unroll
+                        for (int uu = 0; uu < UNR; ++uu) {
+                            const int tc = tc0 + uu * nw;
+                            if (tc < ncol) {
+                                const double2 uc = xcur[tc];
+                                pcol[tc] = make_double2(pcr[uu], pci[uu]);
+                                wur += uc.x * pcr[uu] + uc.y * pci[uu];   // conj(u_tc) * pcol[tc]
                             }
                         }
                     }
                 }
             }
             if (refl) {
-#pragma unroll
-                for (int uu = 0; uu < UNR; ++uu) {
-                    pcr[uu] = wave_sum_to63(pcr[uu]);
-                    pci[uu] = wave_sum_to63(pci[uu]);
-                }
-                if (lane == 63) {
-#pragma unroll
-                    for (int uu = 0; uu < UNR; ++uu) {
-                        const int tc = tc0 + uu * nw;
-                        if (tc < ncol) {
-                            const double2 uc = xcur[tc];
-                            pcol[tc] = make_double2(pcr[uu], pci[uu]);
-                            wur += uc.x * pcr[uu] + uc.y * pci[uu];   // conj(u_tc) * pcol[tc]
-                        }
+    #pragma unroll
+                for (int sl = 0; sl < SL; ++sl) {
+                    const int t = sl * 64 + lane;
+                    if (t < ni) {
+                        prow[wave * smax + t] = accr[sl];
+                        const double2 ut = xcur[t];
+                        wur += ut.x * accr[sl].x + ut.y * accr[sl].y;
                     }
                 }
+                wur = wave_sum_to63(wur);
+                if (lane == 63) red2[wave] = wur;
             }
-        }
-        if (refl) {
-#pragma unroll
-            for (int sl = 0; sl < SL; ++sl) {
-                const int t = sl * 64 + lane;
-                if (t < ni) {
-                    prow[wave * smax + t] = accr[sl];
-                    const double2 ut = xcur[t];
-                    wur += ut.x * accr[sl].x + ut.y * accr[sl].y;
+            __syncthreads();
+            // p, q = p - K u (the new pending update), u stored for the back-transform,
+            // and x_{i+1} = column i+1 with this step's update, plus its tail norm
+            double Kc = 0.0;
+            double2 q0 = make_double2(0.0, 0.0);
+            const double2 u0 = refl ? xcur[0] : make_double2(0.0, 0.0);
+            if (refl) {
+                double uhp = 0;
+                for (int w = 0; w < nw; ++w) uhp += red2[w];
+                Kc = uhp / (2.0 * hh * hh);
+                double pr = pcol[0].x, pi = pcol[0].y;
+                for (int w = 0; w < nw; ++w) {
+                    pr += prow[w * smax].x;
+                    pi += prow[w * smax].y;
+                }
+                q0 = make_double2(pr / hh - Kc * u0.x, pi / hh - Kc * u0.y);
+            }
+            part = 0;
+            for (int t = tid; t < ni; t += EIG_THREADS) {
+                const int r = i + 1 + t;
+                double2 u = make_double2(0.0, 0.0), q = make_double2(0.0, 0.0);
+                if (refl) {
+                    u = xcur[t];
+                    double pr = pcol[t].x, pi = pcol[t].y;
+                    for (int w = 0; w < nw; ++w) {
+                        pr += prow[w * smax + t].x;
+                        pi += prow[w * smax + t].y;
+                    }
+                    q = make_double2(pr / hh - Kc * u.x, pi / hh - Kc * u.y);
+                    up[r] = u;
+                    qp[r] = q;
+                    A[pk(r, i, s)] = u;
+                }
+                double2 x = xraw[t];
+                // (q_r conj(u_c) + u_r conj(q_c)) at c = i + 1
+                x.x -= q.x * u0.x + q.y * u0.y + u.x * q0.x + u.y * q0.y;
+                x.y -= q.y * u0.x - q.x * u0.y + u.y * q0.x - u.x * q0.y;
+                if (t == 0) sdd[i + 1] = x.x;
+                else {
+                    xnxt[t - 1] = x;
+                    if (t > 1) part += cabs2(x);
                 }
             }
-            wur = wave_sum_to63(wur);
-            if (lane == 63) red2[wave] = wur;
+            tail = block_sum(part, red);   // its barriers also publish xnxt, up, qp
+            double2* tmp = xcur;
+            xcur = xnxt;
+            xnxt = tmp;
+            pend = refl;
         }
         __syncthreads();
-        // p, q = p - K u (the new pending update), u stored for the back-transform,
-        // and x_{i+1} = column i+1 with this step's update, plus its tail norm
-        double Kc = 0.0;
-        double2 q0 = make_double2(0.0, 0.0);
-        const double2 u0 = refl ? xcur[0] : make_double2(0.0, 0.0);
-        if (refl) {
-            double uhp = 0;
-            for (int w = 0; w < nw; ++w) uhp += red2[w];
-            Kc = uhp / (2.0 * hh * hh);
-            double pr = pcol[0].x, pi = pcol[0].y;
-            for (int w = 0; w < nw; ++w) {
-                pr += prow[w * smax].x;
-                pi += prow[w * smax].y;
-            }
-            q0 = make_double2(pr / hh - Kc * u0.x, pi / hh - Kc * u0.y);
-        }
-        part = 0;
-        for (int t = tid; t < ni; t += EIG_THREADS) {
-            const int r = i + 1 + t;
-            double2 u = make_double2(0.0, 0.0), q = make_double2(0.0, 0.0);
-            if (refl) {
-                u = xcur[t];
-                double pr = pcol[t].x, pi = pcol[t].y;
-                for (int w = 0; w < nw; ++w) {
-                    pr += prow[w * smax + t].x;
-                    pi += prow[w * smax + t].y;
-                }
-                q = make_double2(pr / hh - Kc * u.x, pi / hh - Kc * u.y);
-                up[r] = u;
-                qp[r] = q;
-                A[pk(r, i, s)] = u;
-            }
-            double2 x = xraw[t];
-            // (q_r conj(u_c) + u_r conj(q_c)) at c = i + 1
-            x.x -= q.x * u0.x + q.y * u0.y + u.x * q0.x + u.y * q0.y;
-            x.y -= q.y * u0.x - q.x * u0.y + u.y * q0.x - u.x * q0.y;
-            if (t == 0) sdd[i + 1] = x.x;
-            else {
-                xnxt[t - 1] = x;
-                if (t > 1) part += cabs2(x);
-            }
-        }
-        tail = block_sum(part, red);   // its barriers also publish xnxt, up, qp
-        double2* tmp = xcur;
-        xcur = xnxt;
-        xnxt = tmp;
-        pend = refl;
     }
-    __syncthreads();
 
     // ---- 2. real tridiagonal via a diagonal unitary ------------------------------
     if (tid == 0) {
@@ -850,10 +1206,27 @@ static size_t heig_lds_bytes(int smax) {
     return (size_t)(6 + nw) * smax * sizeof(double2) + (size_t)9 * smax * sizeof(double) + (2 * nw + 8) * sizeof(double);
 }
 
+bool tridiag_rr_supported(int smax) { return smax >= 2 && smax <= RR_MAXS; }
+
+hipError_t launch_tridiag_rr(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
+                             double* scr, int64_t scr_stride, int smax) {
+    if (!tridiag_rr_supported(smax)) return hipErrorInvalidValue;
+    const int nb = (smax + 15) / 16, nblk = nb * (nb + 1) / 2;
+    const void* fn = nb <= 6 ? (const void*)k_tridiag_rr<3>
+                   : nb <= 8 ? (const void*)k_tridiag_rr<5>
+                   : nb <= 10 ? (const void*)k_tridiag_rr<7>
+                   : nb <= 12 ? (const void*)k_tridiag_rr<10>
+                              : (const void*)k_tridiag_rr<12>;
+    void* args[] = {(void*)&descs, (void*)&m0, (void*)&Gs, (void*)&g_stride, (void*)&scr, (void*)&scr_stride};
+    hipError_t e = hipLaunchKernel(fn, dim3(count), dim3(RR_THREADS), args, 0, st);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
 template <typename OC>
 hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
                            OC* Ss, int64_t s_stride, double* scr, int64_t scr_stride, int32_t* ranks,
-                           double ortol_rel, uint32_t* flags, int smax, const VjpArgs<OC>& vj) {
+                           double ortol_rel, uint32_t* flags, int smax, const VjpArgs<OC>& vj, int tri_in) {
     const size_t lds = heig_lds_bytes(smax);
     const int sl = (smax + 63) / 64;
     const void* fn = sl <= 1 ? (const void*)k_heig_svt<OC, 1>
@@ -866,7 +1239,7 @@ hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int coun
     if (e != hipSuccess) return e;
     void* args[] = {(void*)&descs, (void*)&m0, (void*)&Gs, (void*)&g_stride, (void*)&Ss, (void*)&s_stride, (void*)&scr,
                     (void*)&scr_stride, (void*)&ranks, (void*)&ortol_rel, (void*)&flags, (void*)&smax,
-                    (void*)&vj};
+                    (void*)&vj, (void*)&tri_in};
     e = hipLaunchKernel(fn, dim3(count), dim3(EIG_THREADS), args, lds, st);
     if (e != hipSuccess) return e;
     return hipGetLastError();
@@ -874,9 +1247,9 @@ hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int coun
 
 template hipError_t launch_heig_svt<float2>(hipStream_t, const LRDesc*, int, int, double2*, int64_t, float2*, int64_t,
                                             double*, int64_t, int32_t*, double, uint32_t*, int,
-                                            const VjpArgs<float2>&);
+                                            const VjpArgs<float2>&, int);
 template hipError_t launch_heig_svt<double2>(hipStream_t, const LRDesc*, int, int, double2*, int64_t, double2*,
                                              int64_t, double*, int64_t, int32_t*, double, uint32_t*, int,
-                                             const VjpArgs<double2>&);
+                                             const VjpArgs<double2>&, int);
 
 }  // namespace shlr

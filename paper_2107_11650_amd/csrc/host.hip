@@ -658,8 +658,13 @@ static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_
             }
             STCHK(phase_end(P, 1, e0));
             STCHK(phase_begin(P, &e0));
+            const int rr = tridiag_rr_supported(run.smax) ? 1 : 0;
+            if (rr)
+                HIPCHK(launch_tridiag_rr(P->stream, desc_dev, c0, c1 - c0, G, run.g_stride, scr, run.scr_stride,
+                                         run.smax));
             HIPCHK(launch_heig_svt<cplx_t<R>>(P->stream, desc_dev, c0, c1 - c0, G, run.g_stride, S, run.s_stride, scr,
-                                              run.scr_stride, ranks, ortol, flags, run.smax));
+                                              run.scr_stride, ranks, ortol, flags, run.smax, VjpArgs<cplx_t<R>>(),
+                                              rr));
             STCHK(phase_end(P, 2, e0));
             STCHK(phase_begin(P, &e0));
             for (int gi = run.g0; gi < run.g1; ++gi) {

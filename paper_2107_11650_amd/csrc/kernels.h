@@ -93,6 +93,12 @@ bool lowrank_lds_fits(int csize, int V, int J, int n, int k);
 template <typename OC>
 hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
                            OC* Ss, int64_t s_stride, double* scr, int64_t scr_stride, int32_t* ranks,
-                           double ortol_rel, uint32_t* flags, int smax, const VjpArgs<OC>& vj = VjpArgs<OC>());
+                           double ortol_rel, uint32_t* flags, int smax, const VjpArgs<OC>& vj = VjpArgs<OC>(),
+                           int tri_in = 0);
+// Register-resident Householder reduction of the packed Gram matrices (orders 2..208): reflectors in
+// place, diagonal / off-diagonal / h in the first 4 s doubles of each slot's scratch (then tri_in = 1).
+bool tridiag_rr_supported(int smax);
+hipError_t launch_tridiag_rr(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
+                             double* scr, int64_t scr_stride, int smax);
 
 }  // namespace shlr
