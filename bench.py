@@ -51,7 +51,7 @@ def lowrank_work(shapes):
     return w
 
 
-def build_workload(name, prec, n_cg):
+def build_workload(name, prec, n_cg, tune=True):
     """(plan, Y, mask, shapes, coil-k-space elements, config dict) of a named workload."""
     import numpy as np
     import torch
@@ -105,6 +105,8 @@ def build_workload(name, prec, n_cg):
     else:
         raise SystemExit(f"unknown workload {name}")
     plan = shlr.Plan(p)
+    if tune:
+        cfg["autotune"] = plan.autotune(reps=3).strip().split("\n")
     plan.init(torch.from_numpy(Y).to(plan.cdtype).cuda(), torch.from_numpy(mask).cuda())
     if name == "pi256":
         plan.calibrate_spirit(acs=24, reg=1e-3)
@@ -188,6 +190,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-cg", type=int, default=10)
     ap.add_argument("--no-diff", action="store_true", help="skip the reverse-mode (differentiation) leg")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
     ap.add_argument("--diff-batch", type=int, default=8)
     ap.add_argument("--diff-steps", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -213,7 +216,7 @@ def main():
 
     kw, lam, lam1, beta = 25, 1e4, 10.0, 30.0
     prec = shlr.PREC_MIXED if args.precision == "mixed" else shlr.PREC_FP64
-    plan, Y, mask, shapes, elems, cfg = build_workload(args.workload, prec, args.n_cg)
+    plan, Y, mask, shapes, elems, cfg = build_workload(args.workload, prec, args.n_cg, tune=not args.no_autotune)
 
     # accuracy check leg: K after check_iters iterations from the initial state
     k_check = None

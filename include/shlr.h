@@ -169,6 +169,18 @@ shlr_status shlr_timing_enable(shlr_plan* plan, int32_t enable);
  * lift, 4 SPIRiT PCG.  ms_out[5] milliseconds, launches_out[5] launch counts. */
 shlr_status shlr_timing_read(shlr_plan* plan, double* ms_out, int32_t* launches_out);
 
+/* Choose the launch parameters of the batched low-rank step by timing them on this
+ * plan's own shapes: per bucket of identical lifted-matrix shapes the rows staged per
+ * chunk of the lift + Gram and reprojection products, per run of buckets the
+ * Householder reduction (register-resident or in memory).  Candidates run on
+ * seeded pseudo-random data written into the bound workspace and timed with HIP
+ * events on the plan's stream; reps (1..100) runs each, the best counts.  The
+ * workspace then holds no iterate: call shlr_init before iterating.  report
+ * (host, may be NULL) receives a NUL-terminated text of the choices and times,
+ * truncated to report_len bytes.  The iteration computes the same quantities
+ * with any choice (rounding order aside). */
+shlr_status shlr_autotune(shlr_plan* plan, int32_t reps, char* report, size_t report_len);
+
 /* ---------------------------------------------------------------------------
  * Reverse mode through unrolled iterations.
  *

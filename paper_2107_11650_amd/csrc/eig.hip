@@ -50,8 +50,14 @@ __device__ inline double block_max(double v, double* red) {
     return t;
 }
 
+// 1 / q from the hardware reciprocal and one Newton step (q is kept away from 0)
+__device__ inline double rcp_nr(double q) {
+    const double r = __builtin_amdgcn_rcp(q);
+    return fma(r, fma(-q, r, 1.0), r);
+}
+
 // number of eigenvalues of the symmetric tridiagonal (d, e2 = e^2) below x; the entries
-// are read four at a time ahead of the dependent divisions
+// are read four at a time ahead of the dependent steps
 __device__ inline int sturm_count(const double* d, const double* e2, int s, double x, double pivmin) {
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
@@ -60,21 +66,21 @@ __device__ inline int sturm_count(const double* d, const double* e2, int s, doub
     for (; i + 3 < s; i += 4) {
         const double d0 = d[i], d1 = d[i + 1], d2 = d[i + 2], d3 = d[i + 3];
         const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
-        q = d0 - x - f0 / q;
+        q = d0 - x - f0 * rcp_nr(q);
         if (fabs(q) < pivmin) q = -pivmin;
         c += q < 0.0;
-        q = d1 - x - f1 / q;
+        q = d1 - x - f1 * rcp_nr(q);
         if (fabs(q) < pivmin) q = -pivmin;
         c += q < 0.0;
-        q = d2 - x - f2 / q;
+        q = d2 - x - f2 * rcp_nr(q);
         if (fabs(q) < pivmin) q = -pivmin;
         c += q < 0.0;
-        q = d3 - x - f3 / q;
+        q = d3 - x - f3 * rcp_nr(q);
         if (fabs(q) < pivmin) q = -pivmin;
         c += q < 0.0;
     }
     for (; i < s; ++i) {
-        q = d[i] - x - e2[i - 1] / q;
+        q = d[i] - x - e2[i - 1] * rcp_nr(q);
         if (fabs(q) < pivmin) q = -pivmin;
         c += q < 0.0;
     }
@@ -723,38 +729,77 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
     }
 
     // ---- 2. real tridiagonal via a diagonal unitary ------------------------------
+    // |e_i|, |e_i|^2 and the unit phase of each off-diagonal in parallel, then their
+    // prefix product (one thread) and the Gershgorin bounds (block reductions).
+    for (int t = tid; t < s; t += EIG_THREADS) {
+        double m = 0.0, ur = 1.0, ui = 0.0;
+        if (t + 1 < s) {
+            const double er = secr[t], ei = seci[t];
+            m = sqrt(er * er + ei * ei);
+            if (m > 0) {
+                ur = er / m;
+                ui = ei / m;
+            }
+        }
+        see[t] = m;
+        se2[t] = m * m;
+        sdre[t + 1 < s ? t + 1 : 0] = t + 1 < s ? ur : 1.0;   // unit phase of e_t, at t + 1
+        sdim[t + 1 < s ? t + 1 : 0] = t + 1 < s ? ui : 0.0;
+    }
+    __syncthreads();
     if (tid == 0) {
         double pr = 1.0, pi = 0.0;
         sdre[0] = 1.0;
         sdim[0] = 0.0;
-        for (int i = 0; i + 1 < s; ++i) {
-            const double er = secr[i], ei = seci[i];
-            const double m = sqrt(er * er + ei * ei);
-            see[i] = m;
-            se2[i] = m * m;
-            if (m > 0) {
-                const double ur = er / m, ui = ei / m;
-                const double nr = pr * ur - pi * ui, ni2 = pr * ui + pi * ur;
-                pr = nr;
-                pi = ni2;
-            }
+        int i = 1;
+        for (; i + 3 < s; i += 4) {
+            const double a0 = sdre[i], b0 = sdim[i], a1 = sdre[i + 1], b1 = sdim[i + 1];
+            const double a2 = sdre[i + 2], b2 = sdim[i + 2], a3 = sdre[i + 3], b3 = sdim[i + 3];
+            double nr = pr * a0 - pi * b0, ni = pr * b0 + pi * a0;
+            sdre[i] = nr;
+            sdim[i] = ni;
+            pr = nr * a1 - ni * b1;
+            pi = nr * b1 + ni * a1;
             sdre[i + 1] = pr;
             sdim[i + 1] = pi;
+            nr = pr * a2 - pi * b2;
+            ni = pr * b2 + pi * a2;
+            sdre[i + 2] = nr;
+            sdim[i + 2] = ni;
+            pr = nr * a3 - ni * b3;
+            pi = nr * b3 + ni * a3;
+            sdre[i + 3] = pr;
+            sdim[i + 3] = pi;
         }
-        see[s - 1] = 0.0;
-        se2[s - 1] = 0.0;
-        double gl = DBL_MAX, gu = -DBL_MAX, emax2 = 0;
-        for (int i = 0; i < s; ++i) {
-            const double off = (i > 0 ? see[i - 1] : 0.0) + (i + 1 < s ? see[i] : 0.0);
-            gl = fmin(gl, sdd[i] - off);
-            gu = fmax(gu, sdd[i] + off);
-            if (i + 1 < s) emax2 = fmax(emax2, se2[i]);
+        for (; i < s; ++i) {
+            const double a = sdre[i], b = sdim[i];
+            const double nr = pr * a - pi * b, ni = pr * b + pi * a;
+            pr = nr;
+            pi = ni;
+            sdre[i] = pr;
+            sdim[i] = pi;
         }
-        const double tnorm = fmax(fabs(gl), fabs(gu));
-        sh[0] = gl;
-        sh[1] = gu;
-        sh[2] = tnorm;
-        sh[3] = DBL_MIN * fmax(1.0, emax2) * 4.0 + DBL_MIN;
+    }
+    {
+        double gl = DBL_MAX, gu = -DBL_MAX, emax2 = 0.0, nonfin = 0.0;
+        for (int t = tid; t < s; t += EIG_THREADS) {
+            const double off = (t > 0 ? see[t - 1] : 0.0) + see[t];
+            gl = fmin(gl, sdd[t] - off);
+            gu = fmax(gu, sdd[t] + off);
+            emax2 = fmax(emax2, se2[t]);
+            if (!isfinite(sdd[t]) || !isfinite(se2[t])) nonfin = 1.0;
+        }
+        gl = -block_max(-gl, red);
+        gu = block_max(gu, red);
+        emax2 = block_max(emax2, red);
+        nonfin = block_max(nonfin, red);
+        if (tid == 0) {
+            const double tnorm = nonfin > 0 ? INFINITY : fmax(fabs(gl), fabs(gu));
+            sh[0] = gl;
+            sh[1] = gu;
+            sh[2] = tnorm;
+            sh[3] = DBL_MIN * fmax(1.0, emax2) * 4.0 + DBL_MIN;
+        }
     }
     __syncthreads();
     const double gu = sh[1], tnorm = sh[2], pivmin = sh[3];
@@ -803,20 +848,22 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
     }
     __syncthreads();
 
-    // ---- 4. eigenvectors by twisted factorisation, in LDS ----------------------
+    // ---- 4. eigenvectors by twisted factorisation ---------------------------------
     // For an accurate eigenvalue lk of the tridiagonal T (diagonal sdd, off-
     // diagonal see): T - lk I = L D+ L^T (forward) = U D- U^T (backward);
     // gamma_i = D+_i + D-_i - (d_i - lk) is smallest at the twist r, and
     // z_r = 1, z_i = -L_i z_{i+1} (i < r), z_{i+1} = -U_i z_i (i >= r) solves
-    // (T - lk I) z = gamma_r e_r.  Eigenvalues closer than ortol form a cluster
-    // handled by one thread: each later member is refined by two steps of
-    // inverse iteration with the L D+ L^T factors, each followed by modified
-    // Gram-Schmidt against the earlier members.  Region A of LDS holds
-    // 4 s + 1 doubles (odd stride against bank conflicts) per thread of a batch.
+    // (T - lk I) z = gamma_r e_r, with L_i = e_i / D+_i and U_i = e_i / D-_{i+1}.
+    // Eigenvalues closer than ortol form a cluster handled by one thread: each
+    // later member is refined by two steps of inverse iteration with the
+    // L D+ L^T factors, each followed by modified Gram-Schmidt against the
+    // earlier members.  D+ and U of each thread of a batch live in LDS region A
+    // (2 s + 1 doubles, odd stride against bank conflicts); z is formed in place
+    // in its column of W.
     const double ortol = ortol_rel * tnorm;
     {
         double* wsd = reinterpret_cast<double*>(stage);
-        const int wstride = 4 * s + 1;
+        const int wstride = 2 * s + 1;
         const int cap = max(1, (EIG_STAGE * smax * 2) / wstride);
         int nlead = 0;
         for (int k = 0; k < nabove; ++k) nlead += (k == 0 || slam[k] - slam[k - 1] > ortol);
@@ -826,28 +873,26 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
             for (int k = 1; k <= tid; ++k) rank += (slam[k] - slam[k - 1] > ortol);
         for (int r0 = 0; r0 < nlead; r0 += cap) {
             if (leader && rank >= r0 && rank < r0 + cap) {
-                double* Lf = wsd + (int64_t)(rank - r0) * wstride;
-                double* Dp = Lf + s;
+                double* Dp = wsd + (int64_t)(rank - r0) * wstride;
                 double* Uf = Dp + s;
-                double* z = Uf + s;
                 int kend = tid + 1;
                 while (kend < nabove && slam[kend] - slam[kend - 1] <= ortol) ++kend;
                 double prev = 0;
                 for (int k = tid; k < kend; ++k) {
+                    double* z = W + k;   // column k of W: z[i] at z[i * s]
                     double lk = slam[k];
                     if (k > tid) {
                         const double pertol = 10.0 * DBL_EPSILON * fmax(fabs(lk), tnorm * 1e-3);
                         if (lk - prev < pertol) lk = prev + pertol;
                     }
                     prev = lk;
-                    // forward: D+ and L
+                    // forward: D+
                     double dp = sdd[0] - lk;
                     for (int i = 0; i + 1 < s; ++i) {
                         if (fabs(dp) < pivmin) dp = -pivmin;
                         Dp[i] = dp;
-                        const double l = see[i] / dp;
-                        Lf[i] = l;
-                        dp = sdd[i + 1] - lk - l * see[i];
+                        const double e = see[i];
+                        dp = sdd[i + 1] - lk - e * e * rcp_nr(dp);
                     }
                     if (fabs(dp) < pivmin) dp = -pivmin;
                     Dp[s - 1] = dp;
@@ -857,44 +902,63 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
                     double gbest = fabs(Dp[s - 1]);
                     for (int i = s - 2; i >= 0; --i) {
                         if (fabs(dm) < pivmin) dm = -pivmin;
-                        const double u = see[i] / dm;
+                        const double e = see[i];
+                        const double u = e * rcp_nr(dm);
                         Uf[i] = u;
-                        dm = sdd[i] - lk - u * see[i];
+                        dm = sdd[i] - lk - u * e;
                         const double g = fabs(Dp[i] + dm - (sdd[i] - lk));
                         if (g < gbest) {
                             gbest = g;
                             twist = i;
                         }
                     }
-                    z[twist] = 1.0;
-                    for (int i = twist - 1; i >= 0; --i) z[i] = -Lf[i] * z[i + 1];
-                    for (int i = twist; i + 1 < s; ++i) z[i + 1] = -Uf[i] * z[i];
+                    double zc = 1.0;
+                    z[(int64_t)twist * s] = 1.0;
+                    for (int i = twist - 1; i >= 0; --i) {
+                        zc = -see[i] * rcp_nr(Dp[i]) * zc;
+                        z[(int64_t)i * s] = zc;
+                    }
+                    zc = 1.0;
+                    for (int i = twist; i + 1 < s; ++i) {
+                        zc = -Uf[i] * zc;
+                        z[(int64_t)(i + 1) * s] = zc;
+                    }
                     const int nref = k > tid ? 2 : 0;
                     for (int it = 0; it <= nref; ++it) {
                         if (it > 0) {
                             // z <- (L D+ L^T)^{-1} z
-                            for (int i = 0; i + 1 < s; ++i) z[i + 1] -= Lf[i] * z[i];
-                            for (int i = 0; i < s; ++i) z[i] /= Dp[i];
-                            for (int i = s - 2; i >= 0; --i) z[i] -= Lf[i] * z[i + 1];
+                            double zp = z[0];
+                            for (int i = 0; i + 1 < s; ++i) {
+                                const double zn = z[(int64_t)(i + 1) * s] - see[i] * rcp_nr(Dp[i]) * zp;
+                                z[(int64_t)(i + 1) * s] = zn;
+                                zp = zn;
+                            }
+                            for (int i = 0; i < s; ++i) z[(int64_t)i * s] /= Dp[i];
+                            zp = z[(int64_t)(s - 1) * s];
+                            for (int i = s - 2; i >= 0; --i) {
+                                const double zn = z[(int64_t)i * s] - see[i] * rcp_nr(Dp[i]) * zp;
+                                z[(int64_t)i * s] = zn;
+                                zp = zn;
+                            }
                         }
                         double amax = 0;
-                        for (int i = 0; i < s; ++i) amax = fmax(amax, fabs(z[i]));
+                        for (int i = 0; i < s; ++i) amax = fmax(amax, fabs(z[(int64_t)i * s]));
                         if (!(amax > 0) || !(amax < DBL_MAX)) {
-                            for (int i = 0; i < s; ++i) z[i] = start_entry(i, k + it + 1);
+                            for (int i = 0; i < s; ++i) z[(int64_t)i * s] = start_entry(i, k + it + 1);
                             amax = 1.0;
                         }
-                        for (int i = 0; i < s; ++i) z[i] /= amax;
+                        const double ia = 1.0 / amax;
+                        for (int i = 0; i < s; ++i) z[(int64_t)i * s] *= ia;
                         for (int k2 = tid; k2 < k; ++k2) {
                             double dot = 0;
-                            for (int i = 0; i < s; ++i) dot += W[(int64_t)i * s + k2] * z[i];
-                            for (int i = 0; i < s; ++i) z[i] -= dot * W[(int64_t)i * s + k2];
+                            for (int i = 0; i < s; ++i) dot += W[(int64_t)i * s + k2] * z[(int64_t)i * s];
+                            for (int i = 0; i < s; ++i) z[(int64_t)i * s] -= dot * W[(int64_t)i * s + k2];
                         }
                         double nrm = 0;
-                        for (int i = 0; i < s; ++i) nrm += z[i] * z[i];
+                        for (int i = 0; i < s; ++i) nrm += z[(int64_t)i * s] * z[(int64_t)i * s];
                         nrm = nrm > 0 ? 1.0 / sqrt(nrm) : 0.0;
-                        for (int i = 0; i < s; ++i) z[i] *= nrm;
+                        for (int i = 0; i < s; ++i) z[(int64_t)i * s] *= nrm;
                     }
-                    for (int i = 0; i < s; ++i) W[(int64_t)i * s + k] = z[i];
                 }
             }
             __syncthreads();

@@ -313,6 +313,22 @@ __global__ void k_fill_const(cplx_t<R>* out, int64_t count, R re, R im) {
         out[i] = cmk<cplx_t<R>>(re, im);
 }
 
+// deterministic pseudo-random values in [-scale, scale] (tuning data): a 64-bit mix of the index
+template <typename R>
+__global__ void k_fill_hash(cplx_t<R>* out, int64_t count, uint64_t seed, R scale) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t x = (uint64_t)i * 0x9E3779B97F4A7C15ull + seed;
+        x ^= x >> 31;
+        x *= 0xBF58476D1CE4E5B9ull;
+        x ^= x >> 27;
+        x *= 0x94D049BB133111EBull;
+        x ^= x >> 33;
+        const R a = (R)((double)(x & 0xffffffull) / 8388608.0 - 1.0);
+        const R b = (R)((double)((x >> 24) & 0xffffffull) / 8388608.0 - 1.0);
+        out[i] = cmk<cplx_t<R>>(scale * a, scale * b);
+    }
+}
+
 // running max of |x| (non-negative doubles order like their bit patterns); also flags non-finite values
 template <typename R>
 __global__ void k_maxabs(const cplx_t<R>* in, int64_t count, unsigned long long* out, uint32_t* flags) {
@@ -437,6 +453,12 @@ hipError_t launch_fill_const(hipStream_t st, cplx_t<R>* out, int64_t count, doub
     return hipGetLastError();
 }
 template <typename R>
+hipError_t launch_fill_hash(hipStream_t st, cplx_t<R>* out, int64_t count, uint64_t seed, double scale) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fill_hash<R>), dim3(ew_blocks(count)), dim3(256), 0, st, out, count, seed, (R)scale);
+    return hipGetLastError();
+}
+template <typename R>
 hipError_t launch_maxabs(hipStream_t st, const cplx_t<R>* in, int64_t count, unsigned long long* out,
                          uint32_t* flags) {
     if (count <= 0) return hipSuccess;
@@ -460,6 +482,7 @@ hipError_t launch_zero_doubles(hipStream_t st, double* p, int count) {
     template hipError_t launch_scale_copy<R>(hipStream_t, const cplx_t<R>*, cplx_t<R>*, int64_t, const double*, int); \
     template hipError_t launch_fill_pattern<R>(hipStream_t, cplx_t<R>*, int64_t, const cplx_t<R>*, int64_t, int64_t); \
     template hipError_t launch_fill_const<R>(hipStream_t, cplx_t<R>*, int64_t, double, double);                      \
+    template hipError_t launch_fill_hash<R>(hipStream_t, cplx_t<R>*, int64_t, uint64_t, double);                     \
     template hipError_t launch_maxabs<R>(hipStream_t, const cplx_t<R>*, int64_t, unsigned long long*, uint32_t*);
 SHLR_INST(float)
 SHLR_INST(double)

@@ -112,6 +112,7 @@ static void init_adjoint_host(int n, int k, bool use_w, bool vc, double cst, std
 struct LRGroup {
     int first, count;  // descriptors [first, first + count)
     LRDesc proto;
+    int gram_kc = 0, reproj_kc = 0;   // rows of A per chunk (0: the launchers' default)
 };
 
 // Consecutive groups whose matrix orders are within a factor 2 share the
@@ -121,7 +122,10 @@ struct LRRun {
     int g0, g1;            // groups [g0, g1)
     int smax, slots;
     int64_t g_stride, s_stride, scr_stride;
+    int rr = -1;           // Householder reduction: 1 registers, 0 memory, -1 registers when supported
 };
+
+static int run_uses_rr(const LRRun& r) { return r.rr >= 0 ? r.rr : (tridiag_rr_supported(r.smax) ? 1 : 0); }
 
 struct SliceLayout {
     int M, N;
@@ -172,6 +176,7 @@ struct shlr_plan {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int iters_total = 0;
+    bool tuned = false;   // shlr_autotune chose the launch parameters
     // per-phase HIP-event timing (phase: 0 transforms + X-update, 1 Gram, 2 eigen-SVT, 3 reprojection, 4 SPIRiT)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -654,11 +659,12 @@ static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_
                 const int s0 = std::max(c0, g.first), s1 = std::min(c1, g.first + g.count);
                 if (s0 >= s1) continue;
                 HIPCHK(launch_lift_gram<R>(P->stream, hb, db, wtab, desc_dev, g.proto, s0, s1 - s0,
-                                           G + (int64_t)(s0 - c0) * run.g_stride, run.g_stride, P->p.beta));
+                                           G + (int64_t)(s0 - c0) * run.g_stride, run.g_stride, P->p.beta,
+                                           g.gram_kc));
             }
             STCHK(phase_end(P, 1, e0));
             STCHK(phase_begin(P, &e0));
-            const int rr = tridiag_rr_supported(run.smax) ? 1 : 0;
+            const int rr = run_uses_rr(run);
             if (rr)
                 HIPCHK(launch_tridiag_rr(P->stream, desc_dev, c0, c1 - c0, G, run.g_stride, scr, run.scr_stride,
                                          run.smax));
@@ -672,7 +678,8 @@ static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_
                 const int s0 = std::max(c0, g.first), s1 = std::min(c1, g.first + g.count);
                 if (s0 >= s1) continue;
                 HIPCHK(launch_reproj<R>(P->stream, hb, db, bb, wtab, desc_dev, g.proto, s0, s1 - s0,
-                                        S + (int64_t)(s0 - c0) * run.s_stride, run.s_stride, P->p.beta, P->p.tau));
+                                        S + (int64_t)(s0 - c0) * run.s_stride, run.s_stride, P->p.beta, P->p.tau,
+                                        g.reproj_kc));
             }
             STCHK(phase_end(P, 3, e0));
         }
@@ -1170,3 +1177,4 @@ extern "C" shlr_status shlr_lowrank_lines(int32_t precision, int32_t n_mat, int3
 // ---------------------------------------------------------------------------
 #include "spirit_host.inc"
 #include "unrolled.inc"
+#include "autotune.inc"

@@ -57,17 +57,19 @@ hipError_t launch_fill_pattern(hipStream_t st, cplx_t<R>* out, int64_t count, co
 template <typename R>
 hipError_t launch_fill_const(hipStream_t st, cplx_t<R>* out, int64_t count, double re, double im);
 template <typename R>
+hipError_t launch_fill_hash(hipStream_t st, cplx_t<R>* out, int64_t count, uint64_t seed, double scale);
+template <typename R>
 hipError_t launch_maxabs(hipStream_t st, const cplx_t<R>* in, int64_t count, unsigned long long* out, uint32_t* flags);
 hipError_t launch_zero_doubles(hipStream_t st, double* p, int count);
 
 template <typename R>
 hipError_t launch_lift_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* wtab,
                             const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, double2* Gs,
-                            int64_t g_stride, double beta);
+                            int64_t g_stride, double beta, int kc = 0);
 template <typename R>
 hipError_t launch_reproj(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cplx_t<R>* bb, const cplx_t<R>* wtab,
                          const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, const cplx_t<R>* Ss,
-                         int64_t s_stride, double beta, double tau);
+                         int64_t s_stride, double beta, double tau, int kc = 0);
 template <typename R>
 hipError_t launch_cross_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* gb,
                              const cplx_t<R>* gdb, const cplx_t<R>* wtab, const LRDesc* descs_dev,

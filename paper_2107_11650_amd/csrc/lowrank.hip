@@ -695,12 +695,12 @@ static hipError_t launch_gram_t(dim3 grid, size_t lds, hipStream_t st, const cpl
 template <typename R>
 hipError_t launch_lift_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* wtab,
                             const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, double2* Gs,
-                            int64_t g_stride, double beta) {
+                            int64_t g_stride, double beta, int kc) {
     const int s = lr_s(proto);
     const int nt = (s + 15) / 16;
     const int n_units = (nt + 1) / 2;
     const int groups = (n_units + LR_WAVES - 1) / LR_WAVES;
-    int KC = 16;
+    int KC = (kc == 4 || kc == 8 || kc == 16 || kc == 32) ? kc : 16;   // rows of A staged per chunk
     while (KC > 4 && gram_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT) KC /= 2;
     if (gram_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT) return hipErrorInvalidValue;
     const size_t lds = gram_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC);
@@ -730,10 +730,10 @@ static hipError_t launch_reproj_t(dim3 grid, size_t lds, hipStream_t st, const c
 template <typename R>
 hipError_t launch_reproj(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cplx_t<R>* bb, const cplx_t<R>* wtab,
                          const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, const cplx_t<R>* Ss,
-                         int64_t s_stride, double beta, double tau) {
+                         int64_t s_stride, double beta, double tau, int kc) {
     const int s = lr_s(proto), l = lr_l(proto);
     const int nt = (s + 15) / 16;
-    int KC = 64;
+    int KC = (kc >= 16 && kc <= 64 && kc % 16 == 0) ? kc : 64;   // rows of A per chunk
     while (KC > 16 && (reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT || KC > ((l + 15) / 16) * 16))
         KC -= 16;
     const size_t lds = reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC);
@@ -750,14 +750,14 @@ hipError_t launch_reproj(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cpl
 }
 
 template hipError_t launch_lift_gram<float>(hipStream_t, const float2*, const float2*, const float2*, const LRDesc*,
-                                            const LRDesc&, int, int, double2*, int64_t, double);
+                                            const LRDesc&, int, int, double2*, int64_t, double, int);
 template hipError_t launch_lift_gram<double>(hipStream_t, const double2*, const double2*, const double2*,
-                                             const LRDesc*, const LRDesc&, int, int, double2*, int64_t, double);
+                                             const LRDesc*, const LRDesc&, int, int, double2*, int64_t, double, int);
 template hipError_t launch_reproj<float>(hipStream_t, const float2*, float2*, float2*, const float2*, const LRDesc*,
-                                         const LRDesc&, int, int, const float2*, int64_t, double, double);
+                                         const LRDesc&, int, int, const float2*, int64_t, double, double, int);
 template hipError_t launch_reproj<double>(hipStream_t, const double2*, double2*, double2*, const double2*,
                                           const LRDesc*, const LRDesc&, int, int, const double2*, int64_t, double,
-                                          double);
+                                          double, int);
 
 template <typename R>
 static size_t cross_lds_bytes(int V, int J, int n, int s, int KC) {

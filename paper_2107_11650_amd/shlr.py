@@ -36,7 +36,7 @@ EXPORTED = [
     "shlr_calibrate_spirit", "shlr_init", "shlr_iterate", "shlr_iterate_graph", "shlr_get_kspace",
     "shlr_reconstruct", "shlr_fft_lines", "shlr_lowrank_workspace_size", "shlr_lowrank_lines",
     "shlr_last_error", "shlr_version", "shlr_timing_enable", "shlr_timing_read",
-    "shlr_unrolled_sizes", "shlr_unrolled_forward", "shlr_unrolled_backward",
+    "shlr_unrolled_sizes", "shlr_unrolled_forward", "shlr_unrolled_backward", "shlr_autotune",
 ]
 TIMING_PHASES = ("xupdate", "gram", "eig", "reproj", "spirit")
 
@@ -87,6 +87,7 @@ _lib.shlr_unrolled_sizes.argtypes = [_vp, _i32, ctypes.POINTER(ctypes.c_size_t),
 _lib.shlr_unrolled_forward.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, ctypes.c_size_t]
 _lib.shlr_unrolled_backward.argtypes = [_vp, _i32, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp,
                                         ctypes.POINTER(ctypes.c_double)]
+_lib.shlr_autotune.argtypes = [_vp, _i32, ctypes.c_char_p, ctypes.c_size_t]
 _lib.shlr_timing_enable.argtypes = [_vp, _i32]
 _lib.shlr_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
 _lib.shlr_last_error.restype = ctypes.c_char_p
@@ -208,6 +209,13 @@ class Plan:
     def iterate_async(self, n, graph=False):
         f = _lib.shlr_iterate_graph if graph else _lib.shlr_iterate
         _check(f(self._h, int(n), None))
+
+    def autotune(self, reps=3):
+        """Time the launch choices on this plan's shapes and keep the fastest; returns the report.
+        The plan must be initialised again afterwards."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(_lib.shlr_autotune(self._h, int(reps), buf, ctypes.c_size_t(len(buf))))
+        return buf.value.decode()
 
     def timing_enable(self, on=True):
         _check(_lib.shlr_timing_enable(self._h, int(on)))

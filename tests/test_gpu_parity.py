@@ -301,3 +301,33 @@ def test_spirit_calibrated_on_device(prec, tol):
     e = nmse(out, ref)
     print(f"SPIRiT calibrated {prec}: nmse={e:.3e}", flush=True)
     assert e < tol
+
+
+# ---------------------------------------------------------------------------
+# autotuned launch parameters
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotune_keeps_the_iterates(prec):
+    shlr = _lib()
+    Y, mask = pi_problem(4, 64, 64, seed=5)
+    prm = O.PIParams(k_row=8, k_col=8, lam=1e4, beta=10.0, vc=True, iters=6)
+    ref = O.shlr_pi(Y, mask, prm)
+    pr = shlr.PREC_FP64 if prec == "fp64" else shlr.PREC_MIXED
+    p = shlr.Params(M=(64,), N=(64,), J=4, k_row=8, k_col=8, lam=prm.lam, beta=prm.beta, use_vc=True,
+                    precision=pr)
+    outs = []
+    for tune in (False, True):
+        plan = shlr.Plan(p)
+        if tune:
+            rep = plan.autotune(reps=2)
+            print(rep, flush=True)
+            assert "group 0:" in rep and "Householder reduction" in rep
+        plan.init(dev(Y, plan.cdtype), dev(mask.astype(np.uint8), torch.uint8))
+        plan.iterate(prm.iters)
+        outs.append(host(plan.kspace()))
+        plan.close()
+    e_ref, e_pair = nmse(outs[1], ref), nmse(outs[1], outs[0])
+    print(f"autotune {prec}: nmse vs oracle {e_ref:.3e}, vs untuned {e_pair:.3e}", flush=True)
+    assert e_ref < (1e-18 if prec == "fp64" else 1e-5)
+    assert e_pair < (1e-20 if prec == "fp64" else 1e-9)
