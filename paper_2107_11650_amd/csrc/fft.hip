@@ -4,8 +4,13 @@
 // DFT convention: DC at index n/2 on both sides, 1/sqrt(n) scaling, so the
 // transform is unitary and its adjoint is its inverse (as Eq. 15 requires).
 // The transform itself is a mixed-radix Stockham FFT in LDS (radix 4, 2 and
-// every remaining prime; a prime radix is applied as a direct small DFT).
+// every remaining small prime; a prime radix is applied as a direct small DFT).
+// A length with a prime factor above 31 goes through Bluestein's chirp-z form
+// instead: X_k = conj(w_k) sum_j (x_j conj(w_j)) w_{k-j}, w_j = exp(i pi j^2 / n),
+// the convolution done by power-of-two FFTs of size f >= 2n - 1 in LDS.
 // The centring is folded into the load and store indices.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -88,45 +93,121 @@ __device__ C* fft_run(C* b0, C* b1, const C* tw, int n, int NL, const FftPlan& p
     return b0;
 }
 
+// LDS of a line-transform block: twiddles of size f, then (Bluestein) the FFT of
+// the chirp (f) and the chirp (n), then two line buffers of NL x f.
+template <typename C>
+struct FftLds {
+    C *tw, *bt, *wch, *b0, *b1;
+};
+template <typename C>
+__device__ inline FftLds<C> fft_setup(unsigned char* smem, const FftPlan& pl, int NL, int tid, int nth) {
+    FftLds<C> L;
+    const int f = pl.f, n = pl.n;
+    L.tw = reinterpret_cast<C*>(smem);
+    L.bt = L.tw + f;
+    L.wch = L.bt + (pl.blue ? f : 0);
+    L.b0 = L.wch + (pl.blue ? n : 0);
+    L.b1 = L.b0 + NL * f;
+    make_twiddles(L.tw, f, tid, nth);
+    if (pl.blue) {
+        // chirp w_j = exp(i pi j^2 / n), the angle reduced exactly (j^2 mod 2n)
+        for (int j = tid; j < n; j += nth) {
+            const int64_t q = ((int64_t)j * j) % (2 * (int64_t)n);
+            double sn, cs;
+            sincospi((double)q / (double)n, &sn, &cs);
+            L.wch[j] = cmk<C>(cs, sn);
+        }
+        __syncthreads();
+        // b_j = w_j for |j| < n (circularly), transformed once per block
+        for (int j = tid; j < f; j += nth) {
+            C v = cmk<C>(0, 0);
+            if (j < n) v = L.wch[j];
+            else if (f - j < n) v = L.wch[f - j];
+            L.b0[j] = v;
+        }
+        __syncthreads();
+        C* r = fft_run(L.b0, L.b1, L.tw, f, 1, pl, false, tid, nth);
+        for (int j = tid; j < f; j += nth) L.bt[j] = r[j];
+    }
+    __syncthreads();
+    return L;
+}
+
+// DFT (inverse if inv, unnormalised) of NL lines of length n held with line stride
+// f in b0; returns the buffer that holds the result (same stride).
+template <typename C>
+__device__ C* dft_run(const FftLds<C>& L, int NL, const FftPlan& pl, bool inv, int tid, int nth) {
+    if (!pl.blue) return fft_run(L.b0, L.b1, L.tw, pl.f, NL, pl, inv, tid, nth);
+    const int n = pl.n, f = pl.f;
+    // inverse by conjugation: conj(DFT(conj(x)))
+    for (int e = tid; e < NL * f; e += nth) {
+        const int line = e / f, j = e - line * f;
+        C v = cmk<C>(0, 0);
+        if (j < n) {
+            C x = L.b0[line * f + j];
+            if (inv) x.y = -x.y;
+            v = cmulc(L.wch[j], x);   // conj(w_j) x_j
+        }
+        L.b0[line * f + j] = v;
+    }
+    __syncthreads();
+    C* r = fft_run(L.b0, L.b1, L.tw, f, NL, pl, false, tid, nth);
+    for (int e = tid; e < NL * f; e += nth) r[e] = cmul(r[e], L.bt[e % f]);
+    __syncthreads();
+    C* o = (r == L.b0) ? L.b1 : L.b0;
+    C* r2 = fft_run(r, o, L.tw, f, NL, pl, true, tid, nth);
+    const double invf = 1.0 / (double)f;
+    for (int e = tid; e < NL * n; e += nth) {
+        const int line = e / n, k = e - line * n;
+        C v = cmulc(L.wch[k], r2[line * f + k]);   // conj(w_k) c_k
+        v.x *= invf;
+        v.y *= invf;
+        if (inv) v.y = -v.y;
+        r2[line * f + k] = v;
+    }
+    __syncthreads();
+    return r2;
+}
+
 // dst[line][(i - c) mod n] = src[line][i]  (centred load), for nl lines
 template <typename C>
-__device__ inline void load_lines_centred(C* dst, const C* src, const LineAddr& a, int g0, int nl, int n, int tid,
-                                          int nth) {
+__device__ inline void load_lines_centred(C* dst, const C* src, const LineAddr& a, int g0, int nl, int n, int ls,
+                                          int tid, int nth) {
     const int c = n / 2;
     if (a.es == 1) {
         for (int e = tid; e < nl * n; e += nth) {
             const int line = e / n, i = e - line * n;
             int t = i - c;
             if (t < 0) t += n;
-            dst[line * n + t] = src[line_off(a, g0 + line) + i];
+            dst[line * ls + t] = src[line_off(a, g0 + line) + i];
         }
     } else {
         for (int e = tid; e < nl * n; e += nth) {
             const int line = e % nl, i = e / nl;
             int t = i - c;
             if (t < 0) t += n;
-            dst[line * n + t] = src[line_off(a, g0 + line) + (int64_t)i * a.es];
+            dst[line * ls + t] = src[line_off(a, g0 + line) + (int64_t)i * a.es];
         }
     }
 }
 
 template <typename C, typename R>
-__device__ inline void store_lines_centred(C* dstg, const C* res, const LineAddr& a, int g0, int nl, int n, R scale,
-                                           int tid, int nth) {
+__device__ inline void store_lines_centred(C* dstg, const C* res, const LineAddr& a, int g0, int nl, int n, int ls,
+                                           R scale, int tid, int nth) {
     const int c = n / 2;
     if (a.es == 1) {
         for (int e = tid; e < nl * n; e += nth) {
             const int line = e / n, i = e - line * n;
             int f = i - c;
             if (f < 0) f += n;
-            dstg[line_off(a, g0 + line) + i] = cscale(res[line * n + f], scale);
+            dstg[line_off(a, g0 + line) + i] = cscale(res[line * ls + f], scale);
         }
     } else {
         for (int e = tid; e < nl * n; e += nth) {
             const int line = e % nl, i = e / nl;
             int f = i - c;
             if (f < 0) f += n;
-            dstg[line_off(a, g0 + line) + (int64_t)i * a.es] = cscale(res[line * n + f], scale);
+            dstg[line_off(a, g0 + line) + (int64_t)i * a.es] = cscale(res[line * ls + f], scale);
         }
     }
 }
@@ -137,18 +218,15 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(const cplx_t<R>* in, 
                                                            R scale) {
     using C = cplx_t<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int n = pl.n;
-    C* tw = reinterpret_cast<C*>(smem_raw);
-    C* b0 = tw + n;
-    C* b1 = b0 + NL * n;
+    const int n = pl.n, ls = pl.f;
     const int tid = threadIdx.x;
-    make_twiddles(tw, n, tid, FFT_THREADS);
+    const FftLds<C> L = fft_setup<C>(smem_raw, pl, NL, tid, FFT_THREADS);
     const int g0 = blockIdx.x * NL;
     const int nl = min(NL, n_lines - g0);
-    load_lines_centred(b0, in, ia, g0, nl, n, tid, FFT_THREADS);
+    load_lines_centred(L.b0, in, ia, g0, nl, n, ls, tid, FFT_THREADS);
     __syncthreads();
-    C* res = fft_run(b0, b1, tw, n, nl, pl, inverse != 0, tid, FFT_THREADS);
-    store_lines_centred(out, res, oa, g0, nl, n, scale, tid, FFT_THREADS);
+    C* res = dft_run(L, nl, pl, inverse != 0, tid, FFT_THREADS);
+    store_lines_centred(out, res, oa, g0, nl, n, ls, scale, tid, FFT_THREADS);
 }
 
 // ---------------------------------------------------------------------------
@@ -181,12 +259,10 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
                                                            double* __restrict__ change_acc, int rhs_only) {
     using C = cplx_t<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int n = x.n;
-    C* tw = reinterpret_cast<C*>(smem_raw);
-    C* b0 = tw + n;
-    C* b1 = b0 + NL * n;
+    const int n = x.n, ls = pl.f;
     const int tid = threadIdx.x;
-    make_twiddles(tw, n, tid, FFT_THREADS);
+    const FftLds<C> L = fft_setup<C>(smem_raw, pl, NL, tid, FFT_THREADS);
+    C* b0 = L.b0;
     const int g0 = blockIdx.x * NL;
     const int nl = min(NL, x.n_rows - g0);
     const int c = n / 2;
@@ -199,7 +275,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
             row_digits(x, g0 + line, d2, d1, d0);
             int t = i - c;
             if (t < 0) t += n;
-            b0[line * n + t] = base_bo[row_off(x.bo, d2, d1, d0) + i];
+            b0[line * ls + t] = base_bo[row_off(x.bo, d2, d1, d0) + i];
         }
     } else {
         for (int e = tid; e < nl * n; e += FFT_THREADS) {
@@ -208,12 +284,12 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
             row_digits(x, g0 + line, d2, d1, d0);
             int t = i - c;
             if (t < 0) t += n;
-            b0[line * n + t] = base_bo[row_off(x.bo, d2, d1, d0) + (int64_t)i * x.bo.es];
+            b0[line * ls + t] = base_bo[row_off(x.bo, d2, d1, d0) + (int64_t)i * x.bo.es];
         }
     }
     __syncthreads();
-    C* res = fft_run(b0, b1, tw, n, nl, pl, false, tid, FFT_THREADS);
-    C* oth = (res == b0) ? b1 : b0;
+    C* res = dft_run(L, nl, pl, false, tid, FFT_THREADS);
+    C* oth = (res == L.b0) ? L.b1 : L.b0;
     // 2. combine; write K and stage K (centred) for the inverse transform
     double dsum = 0, osum = 0;
     for (int e = tid; e < nl * n; e += FFT_THREADS) {
@@ -222,7 +298,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
         row_digits(x, g0 + line, d2, d1, d0);
         int f = i - c;
         if (f < 0) f += n;
-        const C cv = cscale(res[line * n + f], sc);
+        const C cv = cscale(res[line * ls + f], sc);
         const C av = base_a[row_off(x.a, d2, d1, d0) + (int64_t)i * x.a.es];
         const int64_t yo = row_off(x.y, d2, d1, d0) + (int64_t)i * x.y.es;
         const int64_t ko = row_off(x.k, d2, d1, d0) + (int64_t)i * x.k.es;
@@ -251,7 +327,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
             osum += (double)ko_old.x * ko_old.x + (double)ko_old.y * ko_old.y;
         }
         base_k[ko] = kv;
-        oth[line * n + f] = kv;
+        oth[line * ls + f] = kv;
     }
     if (rhs_only) return;   // uniform: the right-hand side of Eq. 15 only
     if (change_acc) {
@@ -266,7 +342,10 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
     }
     __syncthreads();
     // 3. inverse transform of K and store the hybrid rows
-    C* res2 = fft_run(oth, res, tw, n, nl, pl, true, tid, FFT_THREADS);
+    FftLds<C> L2 = L;   // the staged K is in oth
+    L2.b0 = oth;
+    L2.b1 = res;
+    C* res2 = dft_run(L2, nl, pl, true, tid, FFT_THREADS);
     if (x.out.es == 1) {
         for (int e = tid; e < nl * n; e += FFT_THREADS) {
             const int line = e / n, i = e - line * n;
@@ -274,7 +353,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
             row_digits(x, g0 + line, d2, d1, d0);
             int f = i - c;
             if (f < 0) f += n;
-            base_out[row_off(x.out, d2, d1, d0) + i] = cscale(res2[line * n + f], sc);
+            base_out[row_off(x.out, d2, d1, d0) + i] = cscale(res2[line * ls + f], sc);
         }
     } else {
         for (int e = tid; e < nl * n; e += FFT_THREADS) {
@@ -283,7 +362,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
             row_digits(x, g0 + line, d2, d1, d0);
             int f = i - c;
             if (f < 0) f += n;
-            base_out[row_off(x.out, d2, d1, d0) + (int64_t)i * x.out.es] = cscale(res2[line * n + f], sc);
+            base_out[row_off(x.out, d2, d1, d0) + (int64_t)i * x.out.es] = cscale(res2[line * ls + f], sc);
         }
     }
 }
@@ -353,26 +432,52 @@ __global__ void k_zero_doubles(double* p, int count) {
 // host launchers
 // ---------------------------------------------------------------------------
 
-FftPlan make_fft_plan(int n) {
-    FftPlan p;
-    p.n = n;
+static void radix_stages(FftPlan& p, int m) {
     p.nst = 0;
-    int m = n;
     while (m % 4 == 0 && p.nst < FFT_MAX_STAGES) { p.radix[p.nst++] = 4; m /= 4; }
     while (m % 2 == 0 && p.nst < FFT_MAX_STAGES) { p.radix[p.nst++] = 2; m /= 2; }
     for (int f = 3; m > 1 && p.nst < FFT_MAX_STAGES; f += 2) {
         while (m % f == 0 && p.nst < FFT_MAX_STAGES) { p.radix[p.nst++] = f; m /= f; }
     }
+}
+
+constexpr int FFT_BLUE_PRIME = 31;    // a larger prime factor goes through the chirp-z form
+constexpr int FFT_BLUE_MAXF = 2048;   // largest chirp-z FFT held in LDS
+
+FftPlan make_fft_plan(int n) {
+    FftPlan p;
+    p.n = n;
+    p.f = n;
+    p.blue = 0;
+    int m = n, lpf = 1;
+    for (int f = 2; (int64_t)f * f <= m; ++f)
+        while (m % f == 0) {
+            lpf = f;
+            m /= f;
+        }
+    if (m > 1) lpf = std::max(lpf, m);
+    int f2 = 1;
+    while (f2 < 2 * n - 1) f2 *= 2;
+    if (lpf > FFT_BLUE_PRIME && f2 <= FFT_BLUE_MAXF) {
+        p.blue = 1;
+        p.f = f2;
+    }
+    radix_stages(p, p.f);
     return p;
 }
 
 template <typename R>
-static int fft_lines_per_block(int n, bool strided) {
+static int fft_lines_per_block(const FftPlan& pl, bool strided) {
     int budget = (sizeof(R) == 4 ? 2048 : 1024) * (strided ? 2 : 1);
-    int nl = budget / n;
+    if (pl.blue) budget = sizeof(R) == 4 ? 4096 : 2048;
+    int nl = budget / pl.f;
     if (nl < 1) nl = 1;
     if (nl > 64) nl = 64;
     return nl;
+}
+template <typename R>
+static size_t fft_lds_bytes(const FftPlan& pl, int NL) {
+    return (size_t)(pl.f + (pl.blue ? pl.f + pl.n : 0) + 2 * NL * pl.f) * sizeof(cplx_t<R>);
 }
 
 template <typename R>
@@ -380,8 +485,8 @@ hipError_t launch_fft_lines(hipStream_t st, const cplx_t<R>* in, cplx_t<R>* out,
                             const LineAddr& oa, int n, int n_lines, int inverse, double scale) {
     if (n_lines <= 0) return hipSuccess;
     FftPlan pl = make_fft_plan(n);
-    const int NL = fft_lines_per_block<R>(n, ia.es != 1 || oa.es != 1);
-    const size_t lds = (size_t)(n + 2 * NL * n) * sizeof(cplx_t<R>);
+    const int NL = fft_lines_per_block<R>(pl, ia.es != 1 || oa.es != 1);
+    const size_t lds = fft_lds_bytes<R>(pl, NL);
     hipError_t e = hipFuncSetAttribute((const void*)k_fft_lines<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
@@ -397,8 +502,8 @@ hipError_t launch_xupd_rows(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>
                             double lam, double beta, int hard_dc, double* change_acc) {
     if (x.n_rows <= 0) return hipSuccess;
     FftPlan pl = make_fft_plan(x.n);
-    const int NL = fft_lines_per_block<R>(x.n, x.bo.es != 1 || x.out.es != 1);
-    const size_t lds = (size_t)(x.n + 2 * NL * x.n) * sizeof(cplx_t<R>);
+    const int NL = fft_lines_per_block<R>(pl, x.bo.es != 1 || x.out.es != 1);
+    const size_t lds = fft_lds_bytes<R>(pl, NL);
     hipError_t e = hipFuncSetAttribute((const void*)k_xupd_rows<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
@@ -414,8 +519,8 @@ hipError_t launch_xupd_rows_rhs(hipStream_t st, const cplx_t<R>* bo, const cplx_
                                 double beta) {
     if (x.n_rows <= 0) return hipSuccess;
     FftPlan pl = make_fft_plan(x.n);
-    const int NL = fft_lines_per_block<R>(x.n, x.bo.es != 1 || x.out.es != 1);
-    const size_t lds = (size_t)(x.n + 2 * NL * x.n) * sizeof(cplx_t<R>);
+    const int NL = fft_lines_per_block<R>(pl, x.bo.es != 1 || x.out.es != 1);
+    const size_t lds = fft_lds_bytes<R>(pl, NL);
     hipError_t e = hipFuncSetAttribute((const void*)k_xupd_rows<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;

@@ -10,8 +10,12 @@ namespace shlr {
 
 constexpr int FFT_MAX_STAGES = 24;
 
+// n: line length; f: size of the FFT actually run (n, or for Bluestein's chirp-z
+// transform a power of two >= 2n - 1); radix: the Stockham stages of size f.
 struct FftPlan {
     int n;
+    int f;
+    int blue;
     int nst;
     int radix[FFT_MAX_STAGES];
 };

@@ -45,7 +45,9 @@ def _needs_gpu():
 # F^1D
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n", [1, 2, 3, 8, 57, 64, 193, 256, 320])
+# 37, 74, 193, 197, 311, 1021: a prime factor above 31, chirp-z form (FFT sizes 128 .. 2048);
+# 1031: too long for the chirp-z LDS buffers, direct prime radix
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 37, 57, 64, 74, 193, 197, 256, 311, 320, 1021, 1031])
 @pytest.mark.parametrize("inverse", [False, True])
 def test_fft_lines(n, inverse):
     shlr = _lib()
@@ -186,6 +188,20 @@ def test_pi_ragged_vc_hard(vc, hard):
     assert e < 1e-18
     if hard:
         assert np.array_equal(out[:, mask], Y[:, mask]) or nmse(out[:, mask], Y[:, mask]) < 1e-28
+
+
+def test_pi_prime_sizes_chirp_z():
+    # 37 x 41 k-space: both line lengths go through the chirp-z transform, in the line FFT and
+    # in the fused X-update
+    shlr = _lib()
+    Y, mask = pi_problem(3, 37, 41, seed=9, n_center=6)
+    prm = O.PIParams(k_row=7, k_col=6, lam=1e4, beta=10.0, vc=True, iters=5)
+    ref = O.shlr_pi(Y, mask, prm)
+    for prec, tol in ((shlr.PREC_FP64, 1e-18), (shlr.PREC_MIXED, 1e-5)):
+        out = run_pi_gpu(Y, mask, prm, prec)
+        e = nmse(out, ref)
+        print(f"PI 37x41 prec={prec}: nmse={e:.3e}", flush=True)
+        assert e < tol
 
 
 def test_pi_multislice_batch():
