@@ -115,8 +115,9 @@ struct LRGroup {
     int gram_kc = 0, reproj_kc = 0;   // rows of A per chunk (0: the launchers' default)
 };
 
-// Consecutive groups whose matrix orders are within a factor 2 share the
-// eigen-solver slots: chunks of up to `slots` matrices, strides for order smax.
+// Consecutive groups of one eigen-solver class whose matrix orders are within a
+// factor 2 share the eigen-solver slots: chunks of up to `slots` matrices,
+// strides for order smax.
 struct LRRun {
     int first, count;      // descriptors [first, first + count)
     int g0, g1;            // groups [g0, g1)
@@ -300,6 +301,32 @@ static LRDesc make_desc(int64_t h_off, int h_cs, int h_es, int64_t b_off, int b_
 
 static const size_t SLOT_BUDGET = (size_t)3 << 30;   // eigen-solver scratch for one chunk
 
+// Eigen-solver class of a matrix order: register-resident reductions (order <= 208) apart
+// from in-memory ones, then by the number of 64-row tiles the eigen kernel is built for.
+static int order_class(int s) { return (tridiag_rr_supported(s) ? 0 : 16) + (s + 63) / 64; }
+
+// Groups sorted by class (stable), the descriptors laid out again in that order, so that the
+// runs formed below hold matrices of one class.
+static void order_groups(shlr_plan* P) {
+    std::vector<int> idx(P->groups.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        return order_class(lr_s(P->groups[a].proto)) < order_class(lr_s(P->groups[b].proto));
+    });
+    std::vector<LRDesc> d;
+    std::vector<LRGroup> g;
+    d.reserve(P->descs.size());
+    for (int i : idx) {
+        LRGroup x = P->groups[i];
+        const int first = (int)d.size();
+        for (int k = 0; k < x.count; ++k) d.push_back(P->descs[x.first + k]);
+        x.first = first;
+        g.push_back(x);
+    }
+    P->descs.swap(d);
+    P->groups.swap(g);
+}
+
 static void layout_slots(shlr_plan* P) {
     P->runs.clear();
     P->bytes_g = P->bytes_s = P->bytes_scr = 0;
@@ -313,7 +340,7 @@ static void layout_slots(shlr_plan* P) {
                 lo = std::min(lo, lr_s(P->groups[gj].proto));
                 hi = std::max(hi, lr_s(P->groups[gj].proto));
             }
-            if (hi <= 2 * lo) {
+            if (hi <= 2 * lo && order_class(sg) == order_class(r.smax)) {
                 r.g1 = gi + 1;
                 r.count += g.count;
                 r.smax = hi;
@@ -512,6 +539,7 @@ extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
         P->groups.push_back(g);
     }
     for (auto& d : P->descs) P->s_max = std::max(P->s_max, lr_s(d));
+    order_groups(P);
     layout_slots(P);
     // workspace
     size_t off = 0;
