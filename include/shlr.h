@@ -160,13 +160,15 @@ shlr_status shlr_reconstruct(shlr_plan* plan, const void* y_dev, const uint8_t* 
  * recorded on the plan's stream around every launch of a phase.  enable != 0
  * starts (and resets) the accumulation; enable == 0 stops it.  shlr_iterate_graph
  * is not timed. */
-#define SHLR_TIMING_PHASES 5
+#define SHLR_TIMING_PHASES 6
 shlr_status shlr_timing_enable(shlr_plan* plan, int32_t enable);
 
 /* Read the accumulated times (synchronises the stream).  Phase index:
  * 0 transforms and X-update (Eq. 15 / S7), 1 lift + Gram, 2 eigen-solve and
  * threshold (Eq. 16), 3 reprojection + multiplier update (Eq. 13) + adjoint
- * lift, 4 SPIRiT PCG.  ms_out[5] milliseconds, launches_out[5] launch counts. */
+ * lift, 4 SPIRiT PCG, 5 register-resident Householder reduction of the Gram
+ * matrices (the first stage of the eigen-solve where it applies).
+ * ms_out[6] milliseconds, launches_out[6] launch counts. */
 shlr_status shlr_timing_read(shlr_plan* plan, double* ms_out, int32_t* launches_out);
 
 /* Choose the launch parameters of the batched low-rank step by timing them on this

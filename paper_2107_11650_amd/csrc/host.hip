@@ -178,7 +178,8 @@ struct shlr_plan {
     hipGraphExec_t graph_exec = nullptr;
     int iters_total = 0;
     bool tuned = false;   // shlr_autotune chose the launch parameters
-    // per-phase HIP-event timing (phase: 0 transforms + X-update, 1 Gram, 2 eigen-SVT, 3 reprojection, 4 SPIRiT)
+    // per-phase HIP-event timing (phase: 0 transforms + X-update, 1 Gram, 2 eigen-SVT, 3 reprojection, 4 SPIRiT,
+    // 5 register-resident Householder reduction)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -691,11 +692,14 @@ static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_
                                            g.gram_kc));
             }
             STCHK(phase_end(P, 1, e0));
-            STCHK(phase_begin(P, &e0));
             const int rr = run_uses_rr(run);
-            if (rr)
+            if (rr) {
+                STCHK(phase_begin(P, &e0));
                 HIPCHK(launch_tridiag_rr(P->stream, desc_dev, c0, c1 - c0, G, run.g_stride, scr, run.scr_stride,
                                          run.smax));
+                STCHK(phase_end(P, 5, e0));
+            }
+            STCHK(phase_begin(P, &e0));
             HIPCHK(launch_heig_svt<cplx_t<R>>(P->stream, desc_dev, c0, c1 - c0, G, run.g_stride, S, run.s_stride, scr,
                                               run.scr_stride, ranks, ortol, flags, run.smax, VjpArgs<cplx_t<R>>(),
                                               rr));

@@ -38,7 +38,7 @@ EXPORTED = [
     "shlr_last_error", "shlr_version", "shlr_timing_enable", "shlr_timing_read",
     "shlr_unrolled_sizes", "shlr_unrolled_forward", "shlr_unrolled_backward", "shlr_autotune",
 ]
-TIMING_PHASES = ("xupdate", "gram", "eig", "reproj", "spirit")
+TIMING_PHASES = ("xupdate", "gram", "eig", "reproj", "spirit", "tridiag")
 
 
 class ShlrError(RuntimeError):
