@@ -115,6 +115,28 @@ __device__ inline double2 row16_reduce4_z(const double2 v[4], int lr) {
     k2.y += t.y;
     return k2;
 }
+// v + v[lane ^ 32] and v + v[lane ^ 16] in every lane, with the gfx950 lane-swap
+// instructions (VALU only).  permlane32_swap(a, b) exchanges the upper half of a
+// with the lower half of b; permlane16_swap(a, b) the odd rows of a with the even
+// rows of b.  With a = b = v the two results hold v and its partner lane in
+// opposite order, so their sum is the butterfly sum in every lane.
+__device__ inline double xor32_sum(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+__device__ inline double xor16_sum(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+// the maximum over the 64 lanes, in every lane
+__device__ inline double wave_max_all(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
 __device__ inline double wave_sum_to63(double v) {
     v += dpp_shift_d(v, 1);
     v += dpp_shift_d(v, 2);

@@ -226,6 +226,31 @@ constexpr int RR_THREADS = 512;
 
 __device__ inline int rr_bidx(int I, int J, int nb) { return J * nb - (J * (J - 1)) / 2 + (I - J); }
 
+// a - (u_r conj(q_c) + q_r conj(u_c)): one element of the pending Hermitian rank-2 update
+__device__ inline double2 rank2_sub(double2 a, double2 ur, double2 qr, double2 uc, double2 qc) {
+    a.x = fma(-ur.x, qc.x, a.x);
+    a.x = fma(-ur.y, qc.y, a.x);
+    a.x = fma(-qr.x, uc.x, a.x);
+    a.x = fma(-qr.y, uc.y, a.x);
+    a.y = fma(-ur.y, qc.x, a.y);
+    a.y = fma(ur.x, qc.y, a.y);
+    a.y = fma(-qr.y, uc.x, a.y);
+    a.y = fma(qr.x, uc.y, a.y);
+    return a;
+}
+// acc + a b
+__device__ inline double2 cfma(double2 a, double2 b, double2 acc) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+// conj(a) b
+__device__ inline double2 cconj_mul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, a.y * b.y), fma(a.x, b.y, -(a.y * b.x)));
+}
+
 template <int MAXB>
 __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __restrict__ descs, int m0,
                                                               double2* __restrict__ Gs, int64_t g_stride,
@@ -391,16 +416,12 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
                     const int c = J * 16 + 4 * lg + k;
                     double2 a = av[t][k];
                     if (pend) {
-                        const double2 uq = up[c], qq = qp[c];
-                        a.x -= upr.x * qq.x + upr.y * qq.y + qpr.x * uq.x + qpr.y * uq.y;
-                        a.y -= upr.y * qq.x - upr.x * qq.y + qpr.y * uq.x - qpr.x * uq.y;
+                        a = rank2_sub(a, upr, qpr, up[c], qp[c]);
                         av[t][k] = a;
                     }
                     const double2 ucc = uc[c];
-                    yr.x += a.x * ucc.x - a.y * ucc.y;
-                    yr.y += a.x * ucc.y + a.y * ucc.x;
-                    yc[k].x = a.x * ur.x + a.y * ur.y;   // conj(a) u_r
-                    yc[k].y = a.x * ur.y - a.y * ur.x;
+                    yr = cfma(a, ucc, yr);
+                    yc[k] = cconj_mul(a, ur);   // conj(a) u_r
                 }
                 if (J * 16 == i + 1 && lg == 0) xraw[r] = av[t][0];
             } else {
@@ -411,24 +432,18 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
                     if (rok && c > i && c < s) {
                         double2 a = av[t][k];
                         if (pend) {
-                            const double2 uq = up[c], qq = qp[c];
-                            a.x -= upr.x * qq.x + upr.y * qq.y + qpr.x * uq.x + qpr.y * uq.y;
-                            a.y -= upr.y * qq.x - upr.x * qq.y + qpr.y * uq.x - qpr.x * uq.y;
+                            a = rank2_sub(a, upr, qpr, up[c], qp[c]);
                             av[t][k] = a;
                         }
                         if (c == i + 1 && r >= c) xraw[r] = a;
                         const double2 ucc = uc[c];
-                        yr.x += a.x * ucc.x - a.y * ucc.y;
-                        yr.y += a.x * ucc.y + a.y * ucc.x;
-                        yc[k].x = a.x * ur.x + a.y * ur.y;
-                        yc[k].y = a.x * ur.y - a.y * ur.x;
+                        yr = cfma(a, ucc, yr);
+                        yc[k] = cconj_mul(a, ur);
                     }
                 }
             }
-            yr.x += __shfl_xor(yr.x, 16, 64);
-            yr.y += __shfl_xor(yr.y, 16, 64);
-            yr.x += __shfl_xor(yr.x, 32, 64);
-            yr.y += __shfl_xor(yr.y, 32, 64);
+            yr.x = xor32_sum(xor16_sum(yr.x));
+            yr.y = xor32_sum(xor16_sum(yr.y));
             if (lane < 16) yrow[b * 16 + lane] = yr;
             if (I != J) {
                 // the column sums of the diagonal blocks are their row sums (held in full)
@@ -923,6 +938,9 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
                         zc = -Uf[i] * zc;
                         z[(int64_t)(i + 1) * s] = zc;
                     }
+                    // a single eigenvector is normalised by the whole block below; in a cluster
+                    // every member is normalised here before the next one is orthogonalised
+                    if (kend == tid + 1) break;
                     const int nref = k > tid ? 2 : 0;
                     for (int it = 0; it <= nref; ++it) {
                         if (it > 0) {
@@ -964,6 +982,41 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
             __syncthreads();
         }
     }
+    // unit scale of every column of W, one wave per column with lanes over rows: 1 / (amax ||z / amax||);
+    // a zero or non-finite column is replaced by a start vector first
+    double* zsc = secr;   // the complex off-diagonal is no longer needed
+    for (int k = wave; k < nabove; k += nw) {
+        double zv[SL];
+        double amax = 0;
+#pragma unroll
+        for (int sl = 0; sl < SL; ++sl) {
+            const int row = sl * 64 + lane;
+            zv[sl] = row < s ? W[(int64_t)row * s + k] : 0.0;
+            amax = fmax(amax, fabs(zv[sl]));
+        }
+        amax = wave_max_all(amax);
+        if (!(amax > 0) || !(amax < DBL_MAX)) {
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) {
+                const int row = sl * 64 + lane;
+                zv[sl] = row < s ? start_entry(row, k + 1) : 0.0;
+                if (row < s) W[(int64_t)row * s + k] = zv[sl];
+            }
+            amax = 0;
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) amax = fmax(amax, fabs(zv[sl]));
+            amax = wave_max_all(amax);
+        }
+        const double ia = 1.0 / amax;
+        double ss = 0;
+#pragma unroll
+        for (int sl = 0; sl < SL; ++sl) {
+            const double t = zv[sl] * ia;
+            ss = fma(t, t, ss);
+        }
+        ss = wave_sum_all(ss);
+        if (lane == 0) zsc[k] = ss > 0 ? ia / sqrt(ss) : 0.0;
+    }
     __syncthreads();
 
     // ---- 5. back-transform: X = Q diag(phase) W sqrt(f) ----------------------
@@ -976,7 +1029,7 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
         const int k = e / s, row = e - k * s;
         const double sig = sqrt(fmax(slam[k], 0.0));
         const double f = sig > 0 ? fmax(1.0 - thr / sig, 0.0) : 0.0;
-        const double w = W[(int64_t)row * s + k] * (vjp ? 1.0 : sqrt(f));
+        const double w = W[(int64_t)row * s + k] * zsc[k] * (vjp ? 1.0 : sqrt(f));
         X[(int64_t)k * s + row] = make_double2(sdre[row] * w, sdim[row] * w);
     }
     apply_reflectors<SL>(X, r, s, smax, A, shv, stage, false);
