@@ -26,6 +26,18 @@ __device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x 
 __device__ inline double2 cmulc(double2 a, double2 b) { return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
 __device__ inline float2 cmulc(float2 a, float2 b) { return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
 __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+// acc + a b as four fused multiply-adds
+__device__ inline double2 cfma(double2 a, double2 b, double2 acc) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+// conj(a) b
+__device__ inline double2 cconj_mul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, a.y * b.y), fma(a.x, b.y, -(a.y * b.x)));
+}
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
@@ -195,8 +207,14 @@ __host__ __device__ inline int lr_l(const LRDesc& d) { return lr_side(d) == 0 ? 
 __host__ __device__ inline int64_t pk(int r, int c, int s) { return (int64_t)c * (2 * s - c - 1) / 2 + r; }
 __host__ __device__ inline int64_t packed_size(int s) { return (int64_t)s * (s + 1) / 2; }
 
-// Per-slot scratch of the eigen-solver, in doubles, for matrices of order s.
-__host__ __device__ inline int64_t eig_scratch_doubles(int s) { return 3LL * s * s + 16LL * s + 64; }
+// Groups of 16 consecutive Householder reflectors (0 .. s-2) in the blocked back-transform.
+__host__ __device__ inline int wy_groups(int s) { return (s + 14) / 16; }
+// Per-slot scratch of the eigen-solver, in doubles, for matrices of order s: small vectors, the
+// tridiagonal eigenvectors (s^2), the back-transformed vectors (2 s^2) and one 16 x 16 complex
+// factor per reflector group.
+__host__ __device__ inline int64_t eig_scratch_doubles(int s) {
+    return 3LL * s * s + 16LL * s + 64 + 512LL * wy_groups(s);
+}
 
 // Reverse-mode arguments of the eigen-SVT kernel (all null in the forward).
 template <typename OC>

@@ -25,6 +25,13 @@ constexpr int EIG_THREADS = 512;
 constexpr int EIG_MAXS = 320;                    // largest supported order
 constexpr int EIG_STAGE = 6 + EIG_THREADS / 64;  // smax-sized double2 rows of LDS region A (staging)
 
+// double2 entries of LDS region A: the staging rows, and at least one 16 x 16 tile per wave plus
+// one more for the blocked back-transform
+__host__ __device__ inline int heig_region_a(int smax) {
+    const int a = EIG_STAGE * smax, b = (EIG_THREADS / 64 + 1) * 256;
+    return a > b ? a : b;
+}
+
 __device__ inline double block_sum(double v, double* red) {
     // all threads must call; returns the total to every thread
     const int tid = threadIdx.x;
@@ -204,6 +211,167 @@ __device__ void apply_reflectors(double2* __restrict__ Xv, int nvec, int s, int 
 }
 
 // ---------------------------------------------------------------------------
+// Blocked back-transformation on the FP64 matrix cores.  The reflectors of
+// columns 16g .. 16g+15 form V_g (s x 16, zero above each reflector's first
+// row), and P_16g P_16g+1 ... P_16g+15 = I - V_g T_g V_g^H with T_g upper
+// triangular: T_jj = 1/h_j, T[0:j, j] = -(1/h_j) T[0:j, 0:j] V_g[:, 0:j]^H v_j
+// (a skipped reflector, h = 0, gives a zero row and column).
+// MFMA 16x16x4 operand layout: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; element q of the accumulator is D[l / 16 + 4 q][l % 16].
+// ---------------------------------------------------------------------------
+
+// element (row, i) of reflector i (u_i below the diagonal of column i of the packed matrix)
+__device__ inline double2 refl_elem(const double2* __restrict__ A, const double* shv, int row, int i, int s) {
+    return (i < s - 1 && row > i && row < s && shv[i] > 0) ? A[pk(row, i, s)] : make_double2(0.0, 0.0);
+}
+
+// Every T_g, one wave per group (groups dealt out in snake order by size): G = V_g^H V_g on the
+// matrix cores into the wave's LDS tile, then lane a forms row a of T_g.  Tg: [group][16][16].
+__device__ __attribute__((always_inline)) void wy_factors(const double2* __restrict__ A, const double* shv, int s, double2* __restrict__ Tg,
+                           double2* gbuf) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int nw = EIG_THREADS / 64;
+    const int ng = wy_groups(s);
+    const int lr = lane & 15, lk = lane >> 4;
+    double2* G = gbuf + wave * 256;
+    for (int m = 0; nw * m < ng; ++m) {
+        const int g = nw * m + ((m & 1) ? nw - 1 - wave : wave);
+        if (g >= ng) continue;   // uniform over the wave
+        doublex4 gr = {0.0, 0.0, 0.0, 0.0}, gi = {0.0, 0.0, 0.0, 0.0};
+        const int i = 16 * g + lr;
+        for (int row0 = 16 * g; row0 < s; row0 += 4) {
+            // A = conj(V)^T and B = V take the same element in each lane
+            const double2 v = refl_elem(A, shv, row0 + lk, i, s);
+            gr = mfma16(v.x, v.x, gr);
+            gr = mfma16(v.y, v.y, gr);
+            gi = mfma16(v.x, v.y, gi);
+            gi = mfma16(-v.y, v.x, gi);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) G[(lk + 4 * q) * 16 + lr] = make_double2(gr[q], gi[q]);
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // the wave's own LDS tile, read below
+        if (lane < 16) {
+            const int a = lane;
+            double2 trow[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int ij = 16 * g + j;
+                const double hj = ij < s - 1 ? shv[ij] : 0.0;
+                const double tau = hj > 0 ? 1.0 / hj : 0.0;
+                double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int b = 0; b < j; ++b) acc = cfma(trow[b], G[b * 16 + j], acc);   // zero for b < a
+                trow[j] = j < a ? make_double2(0.0, 0.0)
+                        : j == a ? make_double2(tau, 0.0)
+                                 : make_double2(-tau * acc.x, -tau * acc.y);
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) Tg[(g * 16 + a) * 16 + j] = trow[j];
+        }
+    }
+}
+
+// X <- Q X for the s x r column-major X (global), Q = P_0 P_1 ... P_{s-2}: groups g = last .. 0,
+// each X <- X - V_g T_g V_g^H X.  Per 16-column tile of X, wave w holds the 16-row tiles
+// w, w + 8, ... as MFMA accumulators; W = V_g^H X is summed over the waves through LDS (pbuf:
+// one 16 x 16 tile per wave, wfull: the sum), Y = T_g W is formed by every wave in the
+// accumulator layout that X -= V_g Y takes as its B operand.  All threads call.
+template <int SL>
+__device__ __attribute__((always_inline)) void backtransform_wy(double2* __restrict__ X, int r, int s, const double2* __restrict__ A,
+                                 const double* shv, const double2* __restrict__ Tg, double2* pbuf, double2* wfull) {
+    constexpr int RTW = (SL + 1) / 2;   // 16-row tiles per wave (SL * 64 >= s rows)
+    constexpr int nw = EIG_THREADS / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int ng = wy_groups(s), nrt = (s + 15) / 16;
+    __syncthreads();   // X, Tg written by every thread
+    for (int ct = 0; ct * 16 < r; ++ct) {
+        const int col = ct * 16 + lr;
+        doublex4 xr[RTW], xi[RTW];
+#pragma unroll
+        for (int m = 0; m < RTW; ++m) {
+            const int rt = wave + nw * m;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = rt * 16 + lk + 4 * q;
+                const double2 v = (rt < nrt && row < s && col < r) ? X[(int64_t)col * s + row] : make_double2(0.0, 0.0);
+                xr[m][q] = v.x;
+                xi[m][q] = v.y;
+            }
+        }
+        for (int g = ng - 1; g >= 0; --g) {
+            // W = V_g^H X over this wave's row tiles (rows below 16 g + 1 are zero in V_g)
+            doublex4 wr = {0.0, 0.0, 0.0, 0.0}, wi = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int m = 0; m < RTW; ++m) {
+                const int rt = wave + nw * m;
+                if (rt >= nrt || rt < g) continue;   // uniform over the wave
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double2 v = refl_elem(A, shv, rt * 16 + 4 * q + lk, 16 * g + lr, s);
+                    wr = mfma16(v.x, xr[m][q], wr);
+                    wr = mfma16(v.y, xi[m][q], wr);
+                    wi = mfma16(v.x, xi[m][q], wi);
+                    wi = mfma16(-v.y, xr[m][q], wi);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pbuf[wave * 256 + (lk + 4 * q) * 16 + lr] = make_double2(wr[q], wi[q]);
+            __syncthreads();
+            {
+                const int e = tid >> 1;
+                double sum = 0.0;
+                if (tid & 1) {
+#pragma unroll
+                    for (int w = 0; w < nw; ++w) sum += pbuf[w * 256 + e].y;
+                    wfull[e].y = sum;
+                } else {
+#pragma unroll
+                    for (int w = 0; w < nw; ++w) sum += pbuf[w * 256 + e].x;
+                    wfull[e].x = sum;
+                }
+            }
+            __syncthreads();
+            // Y = T_g W (every wave; Y stays in registers)
+            doublex4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const double2 t = Tg[(g * 16 + lr) * 16 + 4 * ks + lk];
+                const double2 w = wfull[(4 * ks + lk) * 16 + lr];
+                yr = mfma16(t.x, w.x, yr);
+                yr = mfma16(-t.y, w.y, yr);
+                yi = mfma16(t.x, w.y, yi);
+                yi = mfma16(t.y, w.x, yi);
+            }
+            // X -= V_g Y
+#pragma unroll
+            for (int m = 0; m < RTW; ++m) {
+                const int rt = wave + nw * m;
+                if (rt >= nrt || rt < g) continue;
+#pragma unroll
+                for (int kq = 0; kq < 4; ++kq) {
+                    const double2 v = refl_elem(A, shv, rt * 16 + lr, 16 * g + 4 * kq + lk, s);
+                    xr[m] = mfma16(-v.x, yr[kq], xr[m]);
+                    xr[m] = mfma16(v.y, yi[kq], xr[m]);
+                    xi[m] = mfma16(-v.x, yi[kq], xi[m]);
+                    xi[m] = mfma16(-v.y, yr[kq], xi[m]);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < RTW; ++m) {
+            const int rt = wave + nw * m;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = rt * 16 + lk + 4 * q;
+                if (rt < nrt && row < s && col < r) X[(int64_t)col * s + row] = make_double2(xr[m][q], xi[m][q]);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // Register-resident Householder tridiagonalisation (orders s <= RR_MAXS).
 // One workgroup of 512 threads holds the Hermitian matrix in registers as the
 // 16 x 16 blocks (I, J), I >= J, of its lower triangle (diagonal blocks held
@@ -238,18 +406,7 @@ __device__ inline double2 rank2_sub(double2 a, double2 ur, double2 qr, double2 u
     a.y = fma(qr.x, uc.y, a.y);
     return a;
 }
-// acc + a b
-__device__ inline double2 cfma(double2 a, double2 b, double2 acc) {
-    acc.x = fma(a.x, b.x, acc.x);
-    acc.x = fma(-a.y, b.y, acc.x);
-    acc.y = fma(a.x, b.y, acc.y);
-    acc.y = fma(a.y, b.x, acc.y);
-    return acc;
-}
-// conj(a) b
-__device__ inline double2 cconj_mul(double2 a, double2 b) {
-    return make_double2(fma(a.x, b.x, a.y * b.y), fma(a.x, b.y, -(a.y * b.x)));
-}
+
 
 template <int MAXB>
 __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __restrict__ descs, int m0,
@@ -504,7 +661,7 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
 }
 
 template <typename OC, int SL>
-__global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __restrict__ descs, int m0,
+__global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const LRDesc* __restrict__ descs, int m0,
                                                              double2* __restrict__ Gs, int64_t g_stride,
                                                              OC* __restrict__ Ss, int64_t s_stride,
                                                              double* __restrict__ scr, int64_t scr_stride,
@@ -528,7 +685,7 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
     double2* xraw = pcol + smax;
     double2* prow = xraw + smax;                       // nw * smax
     double2* stage = uvec;                             // region A reused: EIG_STAGE * smax double2
-    double* sdd = reinterpret_cast<double*>(prow + nw * smax);
+    double* sdd = reinterpret_cast<double*>(uvec + heig_region_a(smax));
     double* se2 = sdd + smax;
     double* see = se2 + smax;
     double* shv = see + smax;
@@ -1032,7 +1189,9 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
         const double w = W[(int64_t)row * s + k] * zsc[k] * (vjp ? 1.0 : sqrt(f));
         X[(int64_t)k * s + row] = make_double2(sdre[row] * w, sdim[row] * w);
     }
-    apply_reflectors<SL>(X, r, s, smax, A, shv, stage, false);
+    double2* Tg = reinterpret_cast<double2*>(LU + 2LL * s * s);
+    wy_factors(A, shv, s, Tg, stage);
+    backtransform_wy<SL>(X, r, s, A, shv, Tg, stage, stage + nw * 256);
 
     if (vjp) {
         // ---- 5b. reverse-mode derivative of the threshold map ----------------
@@ -1251,62 +1410,61 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
         }
         __syncthreads();
     }
-    // ---- 6. S = X X^H (row-major, ld = s) ------------------------------------
-    // X is staged in LDS in column chunks; the lower triangle is accumulated in
-    // FP64 (in the now free packed Gram storage when several chunks are needed).
-    const int kc = (EIG_STAGE * smax) / max(s, 1);
-    const int64_t ntri = (int64_t)s * (s + 1) / 2;
-    for (int k0 = 0; k0 < r; k0 += kc) {
-        const int k1 = min(r, k0 + kc);
-        __syncthreads();
-        for (int e = tid; e < (k1 - k0) * s; e += EIG_THREADS) {
-            double2 x = X[(int64_t)k0 * s + e];
+    // ---- 6. S = X X^H (row-major, ld = s) on the matrix cores ------------------
+    // 16 x 16 tiles of the lower block triangle, one wave per tile; each
+    // off-diagonal tile is also written conjugate-transposed.  With the
+    // derivative X holds the unscaled eigenvectors and sqrt(f) scales both
+    // operands.
+    {
+        double* sgf = se2;   // sqrt(f_k) or 1 (se2 is not needed after the bisection)
+        for (int k = tid; k < r; k += EIG_THREADS) {
+            double g = 1.0;
             if (vjp) {
-                const double sig = sqrt(fmax(slam[k0 + e / s], 0.0));
-                const double g = sqrt(sig > 0 ? fmax(1.0 - thr / sig, 0.0) : 0.0);
-                x.x *= g;
-                x.y *= g;
+                const double sig = sqrt(fmax(slam[k], 0.0));
+                g = sqrt(sig > 0 ? fmax(1.0 - thr / sig, 0.0) : 0.0);
             }
-            stage[e] = x;
+            sgf[k] = g;
         }
         __syncthreads();
-        for (int64_t e = tid; e < ntri; e += EIG_THREADS) {
-            // e -> (a, b), a >= b, column-major packed
-            int b = (int)((2.0 * s + 1.0 - sqrt((2.0 * s + 1.0) * (2.0 * s + 1.0) - 8.0 * (double)e)) * 0.5);
-            if (b < 0) b = 0;
-            if (b > s - 1) b = s - 1;
-            while (b > 0 && pk(b, b, s) > e) --b;
-            while (b + 1 < s && pk(b + 1, b + 1, s) <= e) ++b;
-            const int a = (int)(e - pk(b, b, s)) + b;
-            double sr = 0, si = 0;
-            for (int k = 0; k < k1 - k0; ++k) {
-                const double2 xa = stage[k * s + a], xb = stage[k * s + b];
-                sr += xa.x * xb.x + xa.y * xb.y;
-                si += xa.y * xb.x - xa.x * xb.y;
+        const int lr = lane & 15, lk = lane >> 4;
+        const int nrt = (s + 15) / 16, ntile = nrt * (nrt + 1) / 2;
+        for (int t = wave; t < ntile; t += nw) {
+            int tb = 0, rem = t;
+            while (rem >= nrt - tb) {
+                rem -= nrt - tb;
+                ++tb;
             }
-            if (k0 > 0) {
-                const double2 o = A[e];
-                sr += o.x;
-                si += o.y;
+            const int ta = tb + rem;
+            const int ra = ta * 16 + lr, rb = tb * 16 + lr;
+            doublex4 sr = {0.0, 0.0, 0.0, 0.0}, si = {0.0, 0.0, 0.0, 0.0};
+            for (int k0 = 0; k0 < r; k0 += 4) {
+                const int k = k0 + lk;
+                double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+                if (k < r) {
+                    const double g = sgf[k];
+                    if (ra < s) a = cscale(X[(int64_t)k * s + ra], g);
+                    if (rb < s) b = cscale(X[(int64_t)k * s + rb], g);
+                }
+                // S[ra][rb] += a conj(b)
+                sr = mfma16(a.x, b.x, sr);
+                sr = mfma16(a.y, b.y, sr);
+                si = mfma16(a.y, b.x, si);
+                si = mfma16(-a.x, b.y, si);
             }
-            if (k1 < r) {
-                A[e] = make_double2(sr, si);
-            } else {
-                OC o;
-                o.x = sr;
-                o.y = si;
-                S[(int64_t)a * s + b] = o;
-                o.y = -si;
-                S[(int64_t)b * s + a] = o;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ia = ta * 16 + lk + 4 * q, jb = tb * 16 + lr;
+                if (ia < s && jb < s) {
+                    OC o;
+                    o.x = sr[q];
+                    o.y = si[q];
+                    S[(int64_t)ia * s + jb] = o;
+                    if (ta != tb) {
+                        o.y = -si[q];
+                        S[(int64_t)jb * s + ia] = o;
+                    }
+                }
             }
-        }
-    }
-    if (r == 0) {
-        for (int e = tid; e < s * s; e += EIG_THREADS) {
-            OC o;
-            o.x = 0;
-            o.y = 0;
-            S[e] = o;
         }
     }
     if (tid == 0) {
@@ -1320,7 +1478,8 @@ __global__ __launch_bounds__(EIG_THREADS, 4) void k_heig_svt(const LRDesc* __res
 // dynamic LDS bytes of k_heig_svt for matrices of order <= smax
 static size_t heig_lds_bytes(int smax) {
     const int nw = EIG_THREADS / 64;
-    return (size_t)(6 + nw) * smax * sizeof(double2) + (size_t)9 * smax * sizeof(double) + (2 * nw + 8) * sizeof(double);
+    return (size_t)heig_region_a(smax) * sizeof(double2) + (size_t)9 * smax * sizeof(double) +
+           (2 * nw + 8) * sizeof(double);
 }
 
 bool tridiag_rr_supported(int smax) { return smax >= 2 && smax <= RR_MAXS; }

@@ -74,6 +74,7 @@ LR_CASES = [
     (5, 3, 16, 1, False, True),       # k = 1: the coil matrix
     (4, 8, 256, 25, False, True),     # 232 x 200: the 8-coil 256 x 256 row lifts
     (3, 12, 256, 25, True, True),     # 232 x 600: 12-coil virtual-coil PE lifts
+    (3, 6, 320, 45, False, True),     # 276 x 270: order above 256 (five 64-row slabs, in-memory reduction)
 ]
 
 
