@@ -239,13 +239,19 @@ __device__ __attribute__((always_inline)) void wy_factors(const double2* __restr
         if (g >= ng) continue;   // uniform over the wave
         doublex4 gr = {0.0, 0.0, 0.0, 0.0}, gi = {0.0, 0.0, 0.0, 0.0};
         const int i = 16 * g + lr;
-        for (int row0 = 16 * g; row0 < s; row0 += 4) {
-            // A = conj(V)^T and B = V take the same element in each lane
-            const double2 v = refl_elem(A, shv, row0 + lk, i, s);
-            gr = mfma16(v.x, v.x, gr);
-            gr = mfma16(v.y, v.y, gr);
-            gi = mfma16(v.x, v.y, gi);
-            gi = mfma16(-v.y, v.x, gi);
+        for (int row0 = 16 * g; row0 < s; row0 += 32) {
+            // A = conj(V)^T and B = V take the same element in each lane; eight 4-row steps
+            // with their loads issued first
+            double2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = refl_elem(A, shv, row0 + 4 * u + lk, i, s);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                gr = mfma16(v[u].x, v[u].x, gr);
+                gr = mfma16(v[u].y, v[u].y, gr);
+                gi = mfma16(v[u].x, v[u].y, gi);
+                gi = mfma16(-v[u].y, v[u].x, gi);
+            }
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) G[(lk + 4 * q) * 16 + lr] = make_double2(gr[q], gi[q]);
@@ -273,12 +279,12 @@ __device__ __attribute__((always_inline)) void wy_factors(const double2* __restr
 
 // X <- Q X for the s x r column-major X (global), Q = P_0 P_1 ... P_{s-2}: groups g = last .. 0,
 // each X <- X - V_g T_g V_g^H X.  Per 16-column tile of X, wave w holds the 16-row tiles
-// w, w + 8, ... as MFMA accumulators; W = V_g^H X is summed over the waves through LDS (pbuf:
-// one 16 x 16 tile per wave, wfull: the sum), Y = T_g W is formed by every wave in the
-// accumulator layout that X -= V_g Y takes as its B operand.  All threads call.
+// w, w + 8, ... as MFMA accumulators; the partial tiles of W = V_g^H X go to LDS (pbuf, one
+// 16 x 16 tile per wave), wave 0 sums them and forms Y = T_g W (ybuf), whose accumulator
+// layout is the B operand layout of X -= V_g Y.  Two barriers per group.  All threads call.
 template <int SL>
 __device__ __attribute__((always_inline)) void backtransform_wy(double2* __restrict__ X, int r, int s, const double2* __restrict__ A,
-                                 const double* shv, const double2* __restrict__ Tg, double2* pbuf, double2* wfull) {
+                                 const double* shv, const double2* __restrict__ Tg, double2* pbuf, double2* ybuf) {
     constexpr int RTW = (SL + 1) / 2;   // 16-row tiles per wave (SL * 64 >= s rows)
     constexpr int nw = EIG_THREADS / 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -306,43 +312,57 @@ __device__ __attribute__((always_inline)) void backtransform_wy(double2* __restr
             for (int m = 0; m < RTW; ++m) {
                 const int rt = wave + nw * m;
                 if (rt >= nrt || rt < g) continue;   // uniform over the wave
+                double2 v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = refl_elem(A, shv, rt * 16 + 4 * q + lk, 16 * g + lr, s);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const double2 v = refl_elem(A, shv, rt * 16 + 4 * q + lk, 16 * g + lr, s);
-                    wr = mfma16(v.x, xr[m][q], wr);
-                    wr = mfma16(v.y, xi[m][q], wr);
-                    wi = mfma16(v.x, xi[m][q], wi);
-                    wi = mfma16(-v.y, xr[m][q], wi);
+                    wr = mfma16(v[q].x, xr[m][q], wr);
+                    wr = mfma16(v[q].y, xi[m][q], wr);
+                    wi = mfma16(v[q].x, xi[m][q], wi);
+                    wi = mfma16(-v[q].y, xr[m][q], wi);
                 }
+            }
+            // operands of Y = T_g W (wave 0) and of X -= V_g Y, loaded while the partial sums are combined
+            double2 tv[4], vd[RTW][4];
+            if (wave == 0) {
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) tv[ks] = Tg[(g * 16 + lr) * 16 + 4 * ks + lk];
+            }
+#pragma unroll
+            for (int m = 0; m < RTW; ++m) {
+                const int rt = wave + nw * m;
+#pragma unroll
+                for (int kq = 0; kq < 4; ++kq)
+                    vd[m][kq] = (rt < nrt && rt >= g) ? refl_elem(A, shv, rt * 16 + lr, 16 * g + 4 * kq + lk, s)
+                                                      : make_double2(0.0, 0.0);
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) pbuf[wave * 256 + (lk + 4 * q) * 16 + lr] = make_double2(wr[q], wi[q]);
             __syncthreads();
-            {
-                const int e = tid >> 1;
-                double sum = 0.0;
-                if (tid & 1) {
+            // wave 0: W = sum of the partial tiles (fixed order), Y = T_g W into ybuf
+            if (wave == 0) {
+                doublex4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int w = 0; w < nw; ++w) sum += pbuf[w * 256 + e].y;
-                    wfull[e].y = sum;
-                } else {
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int e = (4 * ks + lk) * 16 + lr;
+                    double2 w = pbuf[e];
 #pragma unroll
-                    for (int w = 0; w < nw; ++w) sum += pbuf[w * 256 + e].x;
-                    wfull[e].x = sum;
+                    for (int w8 = 1; w8 < nw; ++w8) w = cadd(w, pbuf[w8 * 256 + e]);
+                    const double2 t = tv[ks];
+                    yr = mfma16(t.x, w.x, yr);
+                    yr = mfma16(-t.y, w.y, yr);
+                    yi = mfma16(t.x, w.y, yi);
+                    yi = mfma16(t.y, w.x, yi);
                 }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ybuf[(lk + 4 * q) * 16 + lr] = make_double2(yr[q], yi[q]);
             }
             __syncthreads();
-            // Y = T_g W (every wave; Y stays in registers)
-            doublex4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+            // B operand of step kq: Y[4 kq + l / 16][l % 16]
+            double2 yv[4];
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const double2 t = Tg[(g * 16 + lr) * 16 + 4 * ks + lk];
-                const double2 w = wfull[(4 * ks + lk) * 16 + lr];
-                yr = mfma16(t.x, w.x, yr);
-                yr = mfma16(-t.y, w.y, yr);
-                yi = mfma16(t.x, w.y, yi);
-                yi = mfma16(t.y, w.x, yi);
-            }
+            for (int kq = 0; kq < 4; ++kq) yv[kq] = ybuf[(lk + 4 * kq) * 16 + lr];
             // X -= V_g Y
 #pragma unroll
             for (int m = 0; m < RTW; ++m) {
@@ -350,11 +370,11 @@ __device__ __attribute__((always_inline)) void backtransform_wy(double2* __restr
                 if (rt >= nrt || rt < g) continue;
 #pragma unroll
                 for (int kq = 0; kq < 4; ++kq) {
-                    const double2 v = refl_elem(A, shv, rt * 16 + lr, 16 * g + 4 * kq + lk, s);
-                    xr[m] = mfma16(-v.x, yr[kq], xr[m]);
-                    xr[m] = mfma16(v.y, yi[kq], xr[m]);
-                    xi[m] = mfma16(-v.x, yi[kq], xi[m]);
-                    xi[m] = mfma16(-v.y, yr[kq], xi[m]);
+                    const double2 v = vd[m][kq];
+                    xr[m] = mfma16(-v.x, yv[kq].x, xr[m]);
+                    xr[m] = mfma16(v.y, yv[kq].y, xr[m]);
+                    xi[m] = mfma16(-v.x, yv[kq].y, xi[m]);
+                    xi[m] = mfma16(-v.y, yv[kq].x, xi[m]);
                 }
             }
         }
@@ -700,7 +720,7 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
     double2* A = Gs + (int64_t)blockIdx.x * g_stride;   // packed lower triangle
     OC* S = Ss + (int64_t)blockIdx.x * s_stride;
     double* base = scr + (int64_t)blockIdx.x * scr_stride;
-    double* W = base + 16 * s + 64;    // s*s interleaved [i*s + k]
+    double* W = base + 16 * s + 64;    // s x s, column k: tridiagonal eigenvector k
     double* LU = W + (int64_t)s * s;   // 2*s*s: X (double2, column-major) of the back-transform
 
     if (tri_in) {
@@ -1051,7 +1071,7 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
                 while (kend < nabove && slam[kend] - slam[kend - 1] <= ortol) ++kend;
                 double prev = 0;
                 for (int k = tid; k < kend; ++k) {
-                    double* z = W + k;   // column k of W: z[i] at z[i * s]
+                    double* z = W + (int64_t)k * s;   // column k of W (column-major)
                     double lk = slam[k];
                     if (k > tid) {
                         const double pertol = 10.0 * DBL_EPSILON * fmax(fabs(lk), tnorm * 1e-3);
@@ -1085,15 +1105,15 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
                         }
                     }
                     double zc = 1.0;
-                    z[(int64_t)twist * s] = 1.0;
+                    z[twist] = 1.0;
                     for (int i = twist - 1; i >= 0; --i) {
                         zc = -see[i] * rcp_nr(Dp[i]) * zc;
-                        z[(int64_t)i * s] = zc;
+                        z[i] = zc;
                     }
                     zc = 1.0;
                     for (int i = twist; i + 1 < s; ++i) {
                         zc = -Uf[i] * zc;
-                        z[(int64_t)(i + 1) * s] = zc;
+                        z[i + 1] = zc;
                     }
                     // a single eigenvector is normalised by the whole block below; in a cluster
                     // every member is normalised here before the next one is orthogonalised
@@ -1104,35 +1124,35 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
                             // z <- (L D+ L^T)^{-1} z
                             double zp = z[0];
                             for (int i = 0; i + 1 < s; ++i) {
-                                const double zn = z[(int64_t)(i + 1) * s] - see[i] * rcp_nr(Dp[i]) * zp;
-                                z[(int64_t)(i + 1) * s] = zn;
+                                const double zn = z[i + 1] - see[i] * rcp_nr(Dp[i]) * zp;
+                                z[i + 1] = zn;
                                 zp = zn;
                             }
-                            for (int i = 0; i < s; ++i) z[(int64_t)i * s] /= Dp[i];
-                            zp = z[(int64_t)(s - 1) * s];
+                            for (int i = 0; i < s; ++i) z[i] /= Dp[i];
+                            zp = z[s - 1];
                             for (int i = s - 2; i >= 0; --i) {
-                                const double zn = z[(int64_t)i * s] - see[i] * rcp_nr(Dp[i]) * zp;
-                                z[(int64_t)i * s] = zn;
+                                const double zn = z[i] - see[i] * rcp_nr(Dp[i]) * zp;
+                                z[i] = zn;
                                 zp = zn;
                             }
                         }
                         double amax = 0;
-                        for (int i = 0; i < s; ++i) amax = fmax(amax, fabs(z[(int64_t)i * s]));
+                        for (int i = 0; i < s; ++i) amax = fmax(amax, fabs(z[i]));
                         if (!(amax > 0) || !(amax < DBL_MAX)) {
-                            for (int i = 0; i < s; ++i) z[(int64_t)i * s] = start_entry(i, k + it + 1);
+                            for (int i = 0; i < s; ++i) z[i] = start_entry(i, k + it + 1);
                             amax = 1.0;
                         }
                         const double ia = 1.0 / amax;
-                        for (int i = 0; i < s; ++i) z[(int64_t)i * s] *= ia;
+                        for (int i = 0; i < s; ++i) z[i] *= ia;
                         for (int k2 = tid; k2 < k; ++k2) {
                             double dot = 0;
-                            for (int i = 0; i < s; ++i) dot += W[(int64_t)i * s + k2] * z[(int64_t)i * s];
-                            for (int i = 0; i < s; ++i) z[(int64_t)i * s] -= dot * W[(int64_t)i * s + k2];
+                            for (int i = 0; i < s; ++i) dot += W[(int64_t)k2 * s + i] * z[i];
+                            for (int i = 0; i < s; ++i) z[i] -= dot * W[(int64_t)k2 * s + i];
                         }
                         double nrm = 0;
-                        for (int i = 0; i < s; ++i) nrm += z[(int64_t)i * s] * z[(int64_t)i * s];
+                        for (int i = 0; i < s; ++i) nrm += z[i] * z[i];
                         nrm = nrm > 0 ? 1.0 / sqrt(nrm) : 0.0;
-                        for (int i = 0; i < s; ++i) z[(int64_t)i * s] *= nrm;
+                        for (int i = 0; i < s; ++i) z[i] *= nrm;
                     }
                 }
             }
@@ -1148,7 +1168,7 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
 #pragma unroll
         for (int sl = 0; sl < SL; ++sl) {
             const int row = sl * 64 + lane;
-            zv[sl] = row < s ? W[(int64_t)row * s + k] : 0.0;
+            zv[sl] = row < s ? W[(int64_t)k * s + row] : 0.0;
             amax = fmax(amax, fabs(zv[sl]));
         }
         amax = wave_max_all(amax);
@@ -1157,7 +1177,7 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
             for (int sl = 0; sl < SL; ++sl) {
                 const int row = sl * 64 + lane;
                 zv[sl] = row < s ? start_entry(row, k + 1) : 0.0;
-                if (row < s) W[(int64_t)row * s + k] = zv[sl];
+                if (row < s) W[(int64_t)k * s + row] = zv[sl];
             }
             amax = 0;
 #pragma unroll
@@ -1172,7 +1192,15 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
             ss = fma(t, t, ss);
         }
         ss = wave_sum_all(ss);
-        if (lane == 0) zsc[k] = ss > 0 ? ia / sqrt(ss) : 0.0;
+        if (lane == 0) {
+            // with the threshold factor sqrt(f_k), except for the derivative (unscaled vectors)
+            double fk = 1.0;
+            if (vj.C == nullptr) {
+                const double sig = sqrt(fmax(slam[k], 0.0));
+                fk = sqrt(sig > 0 ? fmax(1.0 - thr / sig, 0.0) : 0.0);
+            }
+            zsc[k] = ss > 0 ? fk * ia / sqrt(ss) : 0.0;
+        }
     }
     __syncthreads();
 
@@ -1182,12 +1210,22 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
     const int r = nabove;
     double2* X = reinterpret_cast<double2*>(LU);
     const bool vjp = vj.C != nullptr;
-    for (int e = tid; e < s * r; e += EIG_THREADS) {
-        const int k = e / s, row = e - k * s;
-        const double sig = sqrt(fmax(slam[k], 0.0));
-        const double f = sig > 0 ? fmax(1.0 - thr / sig, 0.0) : 0.0;
-        const double w = W[(int64_t)row * s + k] * zsc[k] * (vjp ? 1.0 : sqrt(f));
-        X[(int64_t)k * s + row] = make_double2(sdre[row] * w, sdim[row] * w);
+    for (int e0 = tid; e0 < s * r; e0 += 4 * EIG_THREADS) {   // loads of a batch ahead of its stores
+        double wv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * EIG_THREADS;
+            wv[u] = e < s * r ? W[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * EIG_THREADS;
+            if (e < s * r) {
+                const int k = e / s, row = e - k * s;
+                const double w = wv[u] * zsc[k];
+                X[e] = make_double2(sdre[row] * w, sdim[row] * w);
+            }
+        }
     }
     double2* Tg = reinterpret_cast<double2*>(LU + 2LL * s * s);
     wy_factors(A, shv, s, Tg, stage);
