@@ -443,6 +443,8 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
     __shared__ double2 ycol[RR_NBLK * 16];        // [block][16] column partials
     __shared__ double2 salpha[2];                 // [0] alpha of the reflector, [1] p_j
     __shared__ double red[2 * (RR_THREADS / 64)];  // per-wave partial sums: u^H p, then tails
+    __shared__ double rh[2];                      // h of the current reflector and 1 / h
+    __shared__ int rrefl;                         // whether the current column is reflected
     const LRDesc dsc = descs[m0 + blockIdx.x];
     const int s = lr_s(dsc);
     const int tid = threadIdx.x, lane = tid & 63;
@@ -506,9 +508,6 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
     // Thread t works on row j + t of the current column j (every row count here is below 512).
     // finish_and_reflect: column j (rows >= j, raw in xraw) minus the update (u, q) of step j-1
     // (in uc / qp, none for j = 0), its diagonal entry, and the reflector of column j into uc.
-    double whh = 1.0;        // h of the current reflector (every thread)
-    bool wrefl = false;
-    double2 xr_keep = make_double2(0.0, 0.0);
     auto finish_and_reflect = [&](int j, bool pending, double2 q_j) {
         const int r = j + tid;
         double tail = 0;
@@ -520,7 +519,7 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
                 v.x -= qr.x * u0.x + qr.y * u0.y + ur.x * q_j.x + ur.y * q_j.y;
                 v.y -= qr.y * u0.x - qr.x * u0.y + ur.y * q_j.x - ur.x * q_j.y;
             }
-            xr_keep = v;
+            xraw[r] = v;   // kept in LDS across the barrier below (this thread's own entry)
             if (r == j) tdd[j] = v.x;
             if (r == j + 1) salpha[0] = v;
             if (r > j + 1) tail = cabs2(v);
@@ -549,13 +548,16 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
         if (r > j && r < s) {
             double2 u = make_double2(0.0, 0.0);
             if (refl) {
-                u = (r == j + 1) ? make_double2(al.x + ph.x * xn, al.y + ph.y * xn) : xr_keep;
+                u = (r == j + 1) ? make_double2(al.x + ph.x * xn, al.y + ph.y * xn) : xraw[r];
                 A[pk(r, j, s)] = u;
             }
             uc[r] = u;
         }
-        whh = hh;
-        wrefl = refl;
+        if (tid == 0) {
+            rh[0] = hh;
+            rh[1] = 1.0 / hh;
+            rrefl = refl;
+        }
     };
 
     finish_and_reflect(0, false, make_double2(0.0, 0.0));
@@ -573,6 +575,11 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
             // keep the block's index arithmetic inside the step (it would otherwise be hoisted
             // into vector registers that the matrix needs)
             asm volatile("" : "+s"(I), "+s"(J), "+s"(b));
+            // the lane index is recomputed here for the same reason (two VALU instructions instead
+            // of a spilled offset reloaded from scratch memory in every block)
+            int ln;
+            asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+            const int lr = ln & 15, lg = ln >> 4;
             const int r = I * 16 + lr;
             // every element of the block is live (rows and columns > i, inside the matrix)
             const bool full = J * 16 > i && I * 16 + 16 <= s && J * 16 + 16 <= s;
@@ -621,7 +628,7 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
             }
             yr.x = xor32_sum(xor16_sum(yr.x));
             yr.y = xor32_sum(xor16_sum(yr.y));
-            if (lane < 16) yrow[b * 16 + lane] = yr;
+            if (ln < 16) yrow[b * 16 + ln] = yr;
             if (I != J) {
                 // the column sums of the diagonal blocks are their row sums (held in full)
                 const double2 cs = row16_reduce4_z(yc, lr);
@@ -636,24 +643,27 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
         {
             const int j = i + 1;
             const int r = j + tid;
-            const bool refl = wrefl;
-            const double hh = whh;
+            const bool refl = rrefl != 0;
+            const double hh = rh[0], ihh = rh[1];
             double2 pv = make_double2(0.0, 0.0);
             double uhp = 0;
             if (r < s && refl) {
+                // row partials of blocks (I, jlo .. I), then column partials of blocks (I + 1 .. nb-1, I)
                 const int I = r >> 4, rr = r & 15;
+#pragma unroll 4
                 for (int J = jlo; J <= I; ++J) {
                     const double2 v = yrow[rr_bidx(I, J, nb) * 16 + rr];
                     pv.x += v.x;
                     pv.y += v.y;
                 }
+#pragma unroll 4
                 for (int I2 = I + 1; I2 < nb; ++I2) {
                     const double2 v = ycol[rr_bidx(I2, I, nb) * 16 + rr];
                     pv.x += v.x;
                     pv.y += v.y;
                 }
-                pv.x /= hh;
-                pv.y /= hh;
+                pv.x *= ihh;
+                pv.y *= ihh;
                 const double2 u = uc[r];
                 uhp = u.x * pv.x + u.y * pv.y;   // Re(conj(u) p)
                 if (r == j) salpha[1] = pv;

@@ -297,27 +297,68 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
             accR[t] = A4{0, 0, 0, 0};
             accI[t] = A4{0, 0, 0, 0};
         }
-        // tiles of this wave: t-th tile = wave + t * LR_WAVES
-        for (int kk = 0; kk < s_pad; kk += 4) {
+        // tiles of this wave: t-th tile = wave + t * LR_WAVES.  The B operands (rows of S, from
+        // L2) of step kk + 4 are loaded while the products of step kk run, where the registers
+        // allow it (up to 8 FP32 or 4 FP64 tiles per wave).
+        constexpr bool PF = sizeof(R) * MAXT <= 32;
+        auto load_s = [&](int kk, C* dst) {
+            const int kidx = kk + lk;
+#pragma unroll
+            for (int t = 0; t < MAXT; ++t) {
+                const int tile = wave + t * LR_WAVES;
+                const int col = (tile % nt) * 16 + li;
+                dst[t] = (tile < ntile && kidx < s && col < s) ? S[(int64_t)kidx * s + col] : cmk<C>(0, 0);
+            }
+        };
+        auto mma_step = [&](int kk, const C* sb) {
             const int kidx = kk + lk;
 #pragma unroll
             for (int t = 0; t < MAXT; ++t) {
                 const int tile = wave + t * LR_WAVES;
                 if (tile < ntile) {
-                    const int It = tile / nt, Jt = tile - It * nt;
-                    const int arow = (It * 16 + li) * ldA + kidx;
+                    const int arow = ((tile / nt) * 16 + li) * ldA + kidx;
                     const R ar = Ar[arow], ai = Ai[arow];
-                    const int col = Jt * 16 + li;
-                    R sr = 0, si = 0;
-                    if (kidx < s && col < s) {
-                        const C sv = S[(int64_t)kidx * s + col];
-                        sr = sv.x;
-                        si = sv.y;
-                    }
+                    const R sr = sb[t].x, si = sb[t].y;
                     accR[t] = mfma16(ar, sr, accR[t]);
                     accR[t] = mfma16(-ai, si, accR[t]);
                     accI[t] = mfma16(ar, si, accI[t]);
                     accI[t] = mfma16(ai, sr, accI[t]);
+                }
+            }
+        };
+        if constexpr (PF) {
+            C sb[MAXT];
+            load_s(0, sb);
+            for (int kk = 0; kk < s_pad; kk += 4) {
+                C sn[MAXT];
+                if (kk + 4 < s_pad) load_s(kk + 4, sn);
+                mma_step(kk, sb);
+                if (kk + 4 < s_pad) {
+#pragma unroll
+                    for (int t = 0; t < MAXT; ++t) sb[t] = sn[t];
+                }
+            }
+        } else {
+            for (int kk = 0; kk < s_pad; kk += 4) {
+                const int kidx = kk + lk;
+#pragma unroll
+                for (int t = 0; t < MAXT; ++t) {
+                    const int tile = wave + t * LR_WAVES;
+                    if (tile < ntile) {
+                        const int arow = ((tile / nt) * 16 + li) * ldA + kidx;
+                        const R ar = Ar[arow], ai = Ai[arow];
+                        const int col = (tile % nt) * 16 + li;
+                        R sr = 0, si = 0;
+                        if (kidx < s && col < s) {
+                            const C sv = S[(int64_t)kidx * s + col];
+                            sr = sv.x;
+                            si = sv.y;
+                        }
+                        accR[t] = mfma16(ar, sr, accR[t]);
+                        accR[t] = mfma16(-ai, si, accR[t]);
+                        accI[t] = mfma16(ar, si, accI[t]);
+                        accI[t] = mfma16(ai, sr, accI[t]);
+                    }
                 }
             }
         }
