@@ -470,37 +470,45 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
         bJ[t] = J;
         bI[t] = J + b;
     }
-    double2 av[MAXB][4];
-    const int lr = lane & 15, lg = lane >> 4;
+    // block (I, J) in the accumulator layout of the FP64 matrix cores: element q of lane l is
+    // (row I*16 + l/16 + 4q, column J*16 + l%16); real and imaginary parts in separate registers
+    doublex4 ar_[MAXB], ai_[MAXB];
+    {
+        const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
-    for (int t = 0; t < MAXB; ++t) {
-        const bool has = wave + 8 * t < nblk;
-        const int r = bI[t] * 16 + lr;
+        for (int t = 0; t < MAXB; ++t) {
+            const bool has = wave + 8 * t < nblk;
+            const int c = bJ[t] * 16 + lr;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int c = bJ[t] * 16 + 4 * lg + k;
-            double2 v = make_double2(0.0, 0.0);
-            if (has && r < s && c < s) {
-                if (r >= c) v = A[pk(r, c, s)];
-                else {
-                    v = A[pk(c, r, s)];
-                    v.y = -v.y;
+            for (int q = 0; q < 4; ++q) {
+                const int r = bI[t] * 16 + lk + 4 * q;
+                double2 v = make_double2(0.0, 0.0);
+                if (has && r < s && c < s) {
+                    if (r >= c) v = A[pk(r, c, s)];
+                    else {
+                        v = A[pk(c, r, s)];
+                        v.y = -v.y;
+                    }
+                }
+                ar_[t][q] = v.x;
+                ai_[t][q] = v.y;
+            }
+        }
+        for (int e = tid; e < sp; e += RR_THREADS) {
+            up[e] = make_double2(0.0, 0.0);
+            qp[e] = make_double2(0.0, 0.0);
+            uc[e] = make_double2(0.0, 0.0);
+        }
+        // column 0 into xraw
+#pragma unroll
+        for (int t = 0; t < MAXB; ++t) {
+            if (wave + 8 * t < nblk && bJ[t] == 0 && lr == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = bI[t] * 16 + lk + 4 * q;
+                    if (r < s) xraw[r] = make_double2(ar_[t][q], ai_[t][q]);
                 }
             }
-            av[t][k] = v;
-        }
-    }
-    for (int e = tid; e < sp; e += RR_THREADS) {
-        up[e] = make_double2(0.0, 0.0);
-        qp[e] = make_double2(0.0, 0.0);
-        uc[e] = make_double2(0.0, 0.0);
-    }
-    // column 0 into xraw
-#pragma unroll
-    for (int t = 0; t < MAXB; ++t) {
-        if (wave + 8 * t < nblk && bJ[t] == 0 && lg == 0) {
-            const int r = bI[t] * 16 + lr;
-            if (r < s) xraw[r] = av[t][0];
         }
     }
     __syncthreads();
@@ -545,6 +553,7 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
             tei[j] = refl ? -ph.y * xn : al.y;
             thv[j] = refl ? hh : 0.0;
         }
+        if (r == j) uc[j] = make_double2(0.0, 0.0);   // entries at and above the column stay zero
         if (r > j && r < s) {
             double2 u = make_double2(0.0, 0.0);
             if (refl) {
@@ -566,75 +575,63 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
     for (int i = 0; i + 1 < s; ++i) {
         const int jlo = (i + 1) >> 4;
         const bool pend = i > 0;
-        // (a) pending update, capture of column i+1, products with u_i
+        // (a) pending update on the matrix cores, capture of column i+1, products with u_i.  The
+        // whole block is updated: entries of u, q at and above the reduced columns are zero in uc,
+        // so the stale values there never reach a live product.
 #pragma unroll
         for (int t = 0; t < MAXB; ++t) {
             int b = wave + 8 * t;
             if (b >= nblk || bJ[t] < jlo) continue;   // uniform over the wave
             int I = bI[t], J = bJ[t];
             // keep the block's index arithmetic inside the step (it would otherwise be hoisted
-            // into vector registers that the matrix needs)
+            // into vector registers that the matrix needs); the lane index is recomputed too
             asm volatile("" : "+s"(I), "+s"(J), "+s"(b));
-            // the lane index is recomputed here for the same reason (two VALU instructions instead
-            // of a spilled offset reloaded from scratch memory in every block)
             int ln;
             asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
-            const int lr = ln & 15, lg = ln >> 4;
-            const int r = I * 16 + lr;
-            // every element of the block is live (rows and columns > i, inside the matrix)
-            const bool full = J * 16 > i && I * 16 + 16 <= s && J * 16 + 16 <= s;
-            const bool rok = r > i && r < s;
-            double2 upr = make_double2(0.0, 0.0), qpr = upr, ur = upr;
-            if (rok) {
-                ur = uc[r];
-                if (pend) {
-                    upr = up[r];
-                    qpr = qp[r];
+            const int lr = ln & 15, lk = ln >> 4;
+            if (pend) {
+                // D -= [u_r q_r] [q_c u_c]^H: A = (u_r.x, u_r.y, q_r.x, q_r.y) by row, B = (q_c.x, q_c.y,
+                // u_c.x, u_c.y) by column; the imaginary part takes A' = (u_r.y, -u_r.x, q_r.y, -q_r.x)
+                const double2 va = (lk < 2 ? up : qp)[I * 16 + lr];
+                const double2 vb = (lk < 2 ? qp : up)[J * 16 + lr];
+                const bool odd = (lk & 1) != 0;
+                const double a1 = odd ? va.y : va.x, a2 = odd ? -va.x : va.y, b1 = odd ? vb.y : vb.x;
+                ar_[t] = mfma16(-a1, b1, ar_[t]);
+                ai_[t] = mfma16(-a2, b1, ai_[t]);
+            }
+            const int cc = i + 1 - J * 16;
+            if (cc >= 0 && cc < 16 && lr == cc) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = I * 16 + lk + 4 * q;
+                    if (r > i && r < s) xraw[r] = make_double2(ar_[t][q], ai_[t][q]);
                 }
             }
-            double2 yr = make_double2(0.0, 0.0);
-            double2 yc[4];
-            if (full) {
+            // column partials conj(A)^T u over the block's rows: in-lane, then across the four rows of lanes
+            const double2 uC = uc[J * 16 + lr];
+            double2 ycl = make_double2(0.0, 0.0);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int c = J * 16 + 4 * lg + k;
-                    double2 a = av[t][k];
-                    if (pend) {
-                        a = rank2_sub(a, upr, qpr, up[c], qp[c]);
-                        av[t][k] = a;
-                    }
-                    const double2 ucc = uc[c];
-                    yr = cfma(a, ucc, yr);
-                    yc[k] = cconj_mul(a, ur);   // conj(a) u_r
-                }
-                if (J * 16 == i + 1 && lg == 0) xraw[r] = av[t][0];
+            for (int q = 0; q < 4; ++q) {
+                const double2 uR = uc[I * 16 + lk + 4 * q];
+                const double2 av = make_double2(ar_[t][q], ai_[t][q]);
+                ycl.x = fma(av.x, uR.x, fma(av.y, uR.y, ycl.x));
+                ycl.y = fma(av.x, uR.y, fma(-av.y, uR.x, ycl.y));
+            }
+            ycl.x = xor32_sum(xor16_sum(ycl.x));
+            ycl.y = xor32_sum(xor16_sum(ycl.y));
+            if (I == J) {
+                // a diagonal block is held in full and Hermitian: its column sums are its row sums
+                if (lk == 0) yrow[b * 16 + lr] = ycl;
             } else {
+                if (lk == 0) ycol[b * 16 + lr] = ycl;
+                // row partials A u_C: one per row held by the lane, summed over the 16 columns
+                double2 yq[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int c = J * 16 + 4 * lg + k;
-                    yc[k] = make_double2(0.0, 0.0);
-                    if (rok && c > i && c < s) {
-                        double2 a = av[t][k];
-                        if (pend) {
-                            a = rank2_sub(a, upr, qpr, up[c], qp[c]);
-                            av[t][k] = a;
-                        }
-                        if (c == i + 1 && r >= c) xraw[r] = a;
-                        const double2 ucc = uc[c];
-                        yr = cfma(a, ucc, yr);
-                        yc[k] = cconj_mul(a, ur);
-                    }
-                }
-            }
-            yr.x = xor32_sum(xor16_sum(yr.x));
-            yr.y = xor32_sum(xor16_sum(yr.y));
-            if (ln < 16) yrow[b * 16 + ln] = yr;
-            if (I != J) {
-                // the column sums of the diagonal blocks are their row sums (held in full)
-                const double2 cs = row16_reduce4_z(yc, lr);
+                for (int q = 0; q < 4; ++q) yq[q] = cmul(make_double2(ar_[t][q], ai_[t][q]), uC);
+                const double2 rs = row16_reduce4_z(yq, lr);
                 if ((lr & 3) == 0) {
                     const int kk = 2 * ((lr >> 3) & 1) + (((lr & 7) >= 4) ? 1 : 0);
-                    ycol[b * 16 + 4 * lg + kk] = cs;
+                    yrow[b * 16 + lk + 4 * kk] = rs;
                 }
             }
         }
