@@ -395,12 +395,14 @@ __device__ __attribute__((always_inline)) void backtransform_wy(double2* __restr
 // Register-resident Householder tridiagonalisation (orders s <= RR_MAXS).
 // One workgroup of 512 threads holds the Hermitian matrix in registers as the
 // 16 x 16 blocks (I, J), I >= J, of its lower triangle (diagonal blocks held
-// in full): wave w owns blocks w, w + 8, ... in column-major block order, and
-// lane l holds row I*16 + l%16, columns J*16 + 4(l/16) + 0..3.  Step i:
-//  (a) every lane applies the pending rank-2 update of step i-1 to its live
-//      elements (rows and columns > i), captures column i+1, and forms the
-//      products with u_i: row partials (reduced over the 4 lane groups) and,
-//      in off-diagonal blocks, column partials (reduced over 16 lanes);
+// in full): wave w owns blocks w, w + 8, ... in column-major block order, in
+// the accumulator layout of the FP64 matrix cores (lane l holds column
+// J*16 + l%16, rows I*16 + l/16 + 4q, q = 0..3).  Step i:
+//  (a) every wave applies the pending rank-2 update of step i-1 to its live
+//      blocks as two 16x16x4 MFMAs per block ([u q] times [q u]^H), captures
+//      column i+1, and forms the products with u_i: column partials (in-lane,
+//      then across the four rows of lanes) and, in off-diagonal blocks, row
+//      partials (reduced over 16 lanes);
 //  (b) one thread per row gathers p = A u_i / h_i in a fixed block order;
 //      then q = p - (u^H p / 2h) u, column i+1 finished with the update of
 //      step i, and the reflector of step i+1.
