@@ -1019,6 +1019,10 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
         const int ngroups = EIG_THREADS / G;
         const int grp = tid / G, gl_ = tid % G;
         const double slack = 2.0 * DBL_EPSILON * tnorm + pivmin;
+        // relative width at which a bracket is final: full FP64 accuracy for FP64 outputs and for the
+        // derivative (its resolvent solves sit next to each eigenvalue); 1e-10 when S is rounded to
+        // FP32, which is far below the FP32 rounding of the products around it
+        const double bw = (sizeof(OC) == sizeof(double2) || vj.C != nullptr) ? 2.0 * DBL_EPSILON : 1e-10;
         for (int k0 = 0; k0 < nabove; k0 += ngroups) {   // uniform trip count
             const int kk = k0 + grp;
             const bool act = kk < nabove;
@@ -1026,7 +1030,7 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
             double lo = t2, hi = gu + slack + fabs(gu) * 4.0 * DBL_EPSILON;
             for (int it = 0; it < 80; ++it) {
                 const double width = hi - lo;
-                bool done = !(width > 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin);
+                bool done = !(width > bw * fmax(fabs(lo), fabs(hi)) + pivmin);
                 // the whole wave iterates while any of its groups is active
                 const double step = width / (double)(G + 1);
                 const double x = lo + step * (double)(gl_ + 1);
