@@ -368,6 +368,110 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
 }
 
 // ---------------------------------------------------------------------------
+// SPIRiT operator of the X-update (Eq. 3 inside Eq. 15) with fewer passes:
+//   k_spirit_cols: for one image column n of all J coils, the inverse column
+//     transform, the per-pixel product with Aimg = (Gimg - I)^H (Gimg - I)
+//     (J x J, [pixel][a][b]) and the forward column transform, in one block;
+//     t and y are [J][M][N] with t already transformed along its rows;
+//   k_fft_rows_apply: the forward row transform of y fused with the PCG
+//     operator Ap = den p + lambda1 y, in place, and one partial Re<p, Ap>
+//     per block (fixed order).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(FFT_THREADS) void k_spirit_cols(const cplx_t<R>* __restrict__ t,
+                                                             cplx_t<R>* __restrict__ y,
+                                                             const cplx_t<R>* __restrict__ A, int J, int M, int N,
+                                                             FftPlan pl) {
+    using C = cplx_t<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x, n = blockIdx.x, ls = pl.f, c = M / 2;
+    const int64_t MN = (int64_t)M * N;
+    const FftLds<C> L = fft_setup<C>(smem_raw, pl, J, tid, FFT_THREADS);
+    for (int e = tid; e < J * M; e += FFT_THREADS) {
+        const int j = e / M, m = e - j * M;
+        int q = m - c;
+        if (q < 0) q += M;
+        L.b0[j * ls + q] = t[j * MN + (int64_t)m * N + n];
+    }
+    __syncthreads();
+    C* res = dft_run(L, J, pl, true, tid, FFT_THREADS);
+    C* oth = (res == L.b0) ? L.b1 : L.b0;
+    const R sc = (R)(1.0 / sqrt((double)M));
+    for (int m = tid; m < M; m += FFT_THREADS) {
+        int q = m - c;
+        if (q < 0) q += M;
+        const C* Ap = A + ((int64_t)m * N + n) * J * J;
+        for (int a = 0; a < J; ++a) {
+            R sr = 0, si = 0;
+            for (int b = 0; b < J; ++b) {
+                const C mv = Ap[a * J + b], v = res[b * ls + q];
+                sr += mv.x * v.x - mv.y * v.y;
+                si += mv.x * v.y + mv.y * v.x;
+            }
+            oth[a * ls + q] = cmk<C>(sr * sc, si * sc);
+        }
+    }
+    __syncthreads();
+    FftLds<C> L2 = L;   // the product is staged in oth
+    L2.b0 = oth;
+    L2.b1 = res;
+    C* r2 = dft_run(L2, J, pl, false, tid, FFT_THREADS);
+    for (int e = tid; e < J * M; e += FFT_THREADS) {
+        const int j = e / M, m = e - j * M;
+        int q = m - c;
+        if (q < 0) q += M;
+        y[j * MN + (int64_t)m * N + n] = cscale(r2[j * ls + q], sc);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_apply(cplx_t<R>* __restrict__ io,
+                                                                const cplx_t<R>* __restrict__ p, int J, int M, int N,
+                                                                FftPlan pl, int NL, const uint8_t* __restrict__ mask,
+                                                                const R* __restrict__ rtab, int64_t rr_off,
+                                                                int64_t rc_off, R lam, R beta, R lam1,
+                                                                double* __restrict__ partials) {
+    using C = cplx_t<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[FFT_THREADS / 64];
+    const int tid = threadIdx.x, ls = pl.f, c = N / 2;
+    const FftLds<C> L = fft_setup<C>(smem_raw, pl, NL, tid, FFT_THREADS);
+    const int g0 = blockIdx.x * NL;
+    const int nl = min(NL, J * M - g0);
+    for (int e = tid; e < nl * N; e += FFT_THREADS) {
+        const int line = e / N, i = e - line * N;
+        int q = i - c;
+        if (q < 0) q += N;
+        L.b0[line * ls + q] = io[(int64_t)(g0 + line) * N + i];
+    }
+    __syncthreads();
+    C* res = dft_run(L, nl, pl, false, tid, FFT_THREADS);
+    const R sc = (R)(1.0 / sqrt((double)N));
+    double acc = 0;
+    for (int e = tid; e < nl * N; e += FFT_THREADS) {
+        const int line = e / N, i = e - line * N;
+        int q = i - c;
+        if (q < 0) q += N;
+        const int m = (g0 + line) % M;
+        const int64_t ge = (int64_t)(g0 + line) * N + i;
+        const C tv = cscale(res[line * ls + q], sc);
+        const R d = (mask[(int64_t)m * N + i] ? lam : (R)0) + beta * (rtab[rr_off + i] + rtab[rc_off + m]);
+        const C pv = p[ge];
+        const C a = cmk<C>(d * pv.x + lam1 * tv.x, d * pv.y + lam1 * tv.y);
+        io[ge] = a;
+        acc += (double)pv.x * a.x + (double)pv.y * a.y;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double tsum = 0;
+        for (int w = 0; w < FFT_THREADS / 64; ++w) tsum += red[w];
+        partials[blockIdx.x] = tsum;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // element-wise helpers
 // ---------------------------------------------------------------------------
 
@@ -575,6 +679,42 @@ hipError_t launch_zero_doubles(hipStream_t st, double* p, int count) {
     return hipGetLastError();
 }
 
+template <typename R>
+int spirit_fused_blocks(int J, int M, int N) {
+    const FftPlan pm = make_fft_plan(M), pn = make_fft_plan(N);
+    if (fft_lds_bytes<R>(pm, J) > 160 * 1024) return 0;
+    const int NL = fft_lines_per_block<R>(pn, false);
+    return (J * M + NL - 1) / NL;
+}
+
+template <typename R>
+hipError_t launch_spirit_cols(hipStream_t st, const cplx_t<R>* t, cplx_t<R>* y, const cplx_t<R>* A, int J, int M,
+                              int N) {
+    const FftPlan pl = make_fft_plan(M);
+    const size_t lds = fft_lds_bytes<R>(pl, J);
+    hipError_t e = hipFuncSetAttribute((const void*)k_spirit_cols<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_spirit_cols<R>), dim3(N), dim3(FFT_THREADS), lds, st, t, y, A, J, M, N, pl);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_fft_rows_apply(hipStream_t st, cplx_t<R>* io, const cplx_t<R>* p, int J, int M, int N,
+                                 const uint8_t* mask, const R* rtab, int64_t rr_off, int64_t rc_off, double lam,
+                                 double beta, double lam1, double* partials) {
+    const FftPlan pl = make_fft_plan(N);
+    const int NL = fft_lines_per_block<R>(pl, false);
+    const size_t lds = fft_lds_bytes<R>(pl, NL);
+    hipError_t e = hipFuncSetAttribute((const void*)k_fft_rows_apply<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    const int blocks = (J * M + NL - 1) / NL;
+    hipLaunchKernelGGL((k_fft_rows_apply<R>), dim3(blocks), dim3(FFT_THREADS), lds, st, io, p, J, M, N, pl, NL, mask,
+                       rtab, rr_off, rc_off, (R)lam, (R)beta, (R)lam1, partials);
+    return hipGetLastError();
+}
+
 #define SHLR_INST(R)                                                                                                 \
     template hipError_t launch_fft_lines<R>(hipStream_t, const cplx_t<R>*, cplx_t<R>*, const LineAddr&,              \
                                             const LineAddr&, int, int, int, double);                                 \
@@ -588,7 +728,13 @@ hipError_t launch_zero_doubles(hipStream_t st, double* p, int count) {
     template hipError_t launch_fill_pattern<R>(hipStream_t, cplx_t<R>*, int64_t, const cplx_t<R>*, int64_t, int64_t); \
     template hipError_t launch_fill_const<R>(hipStream_t, cplx_t<R>*, int64_t, double, double);                      \
     template hipError_t launch_fill_hash<R>(hipStream_t, cplx_t<R>*, int64_t, uint64_t, double);                     \
-    template hipError_t launch_maxabs<R>(hipStream_t, const cplx_t<R>*, int64_t, unsigned long long*, uint32_t*);
+    template hipError_t launch_maxabs<R>(hipStream_t, const cplx_t<R>*, int64_t, unsigned long long*, uint32_t*);   \
+    template int spirit_fused_blocks<R>(int, int, int);                                                              \
+    template hipError_t launch_spirit_cols<R>(hipStream_t, const cplx_t<R>*, cplx_t<R>*, const cplx_t<R>*, int, int, \
+                                              int);                                                                  \
+    template hipError_t launch_fft_rows_apply<R>(hipStream_t, cplx_t<R>*, const cplx_t<R>*, int, int, int,           \
+                                                 const uint8_t*, const R*, int64_t, int64_t, double, double, double, \
+                                                 double*);
 SHLR_INST(float)
 SHLR_INST(double)
 

@@ -52,6 +52,17 @@ template <typename R>
 hipError_t launch_xupd_rows_rhs(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>* a, const cplx_t<R>* y,
                                 cplx_t<R>* rhs, const uint8_t* m, const R* rtab, const XupdRows& x, double lam,
                                 double beta);
+// SPIRiT operator in three passes: number of partial sums of the fused row pass, 0 when the column
+// pass does not fit the LDS
+template <typename R>
+int spirit_fused_blocks(int J, int M, int N);
+template <typename R>
+hipError_t launch_spirit_cols(hipStream_t st, const cplx_t<R>* t, cplx_t<R>* y, const cplx_t<R>* A, int J, int M,
+                              int N);
+template <typename R>
+hipError_t launch_fft_rows_apply(hipStream_t st, cplx_t<R>* io, const cplx_t<R>* p, int J, int M, int N,
+                                 const uint8_t* mask, const R* rtab, int64_t rr_off, int64_t rc_off, double lam,
+                                 double beta, double lam1, double* partials);
 template <typename R>
 hipError_t launch_scale_copy(hipStream_t st, const cplx_t<R>* in, cplx_t<R>* out, int64_t count,
                              const double* scale_ptr, int invert);

@@ -248,8 +248,8 @@ hipError_t launch_pcg_init(hipStream_t st, const cplx_t<R>* b, const cplx_t<R>* 
     return hipGetLastError();
 }
 
-hipError_t launch_pcg_scalar(hipStream_t st, const double* partials, double* scal, int mode) {
-    hipLaunchKernelGGL(k_pcg_scalar, dim3(1), dim3(PCG_THREADS), 0, st, partials, PCG_BLOCKS, scal, mode);
+hipError_t launch_pcg_scalar(hipStream_t st, const double* partials, int n_partials, double* scal, int mode) {
+    hipLaunchKernelGGL(k_pcg_scalar, dim3(1), dim3(PCG_THREADS), 0, st, partials, n_partials, scal, mode);
     return hipGetLastError();
 }
 
