@@ -16,7 +16,7 @@
 
 namespace shlr {
 
-constexpr int FFT_THREADS = 256;
+constexpr int FFT_THREADS = 512;
 __device__ inline int64_t line_off(const LineAddr& a, int g) {
     const int g1 = g / a.n0, g0 = g - (g / a.n0) * a.n0;
     return a.base + (int64_t)g1 * a.s1 + (int64_t)g0 * a.s0;
@@ -377,8 +377,9 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
 //     operator Ap = den p + lambda1 y, in place, and one partial Re<p, Ap>
 //     per block (fixed order).
 // ---------------------------------------------------------------------------
+constexpr int SPC_THREADS = 1024;
 template <typename R>
-__global__ __launch_bounds__(FFT_THREADS) void k_spirit_cols(const cplx_t<R>* __restrict__ t,
+__global__ __launch_bounds__(SPC_THREADS) void k_spirit_cols(const cplx_t<R>* __restrict__ t,
                                                              cplx_t<R>* __restrict__ y,
                                                              const cplx_t<R>* __restrict__ A, int J, int M, int N,
                                                              FftPlan pl) {
@@ -386,37 +387,37 @@ __global__ __launch_bounds__(FFT_THREADS) void k_spirit_cols(const cplx_t<R>* __
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x, n = blockIdx.x, ls = pl.f, c = M / 2;
     const int64_t MN = (int64_t)M * N;
-    const FftLds<C> L = fft_setup<C>(smem_raw, pl, J, tid, FFT_THREADS);
-    for (int e = tid; e < J * M; e += FFT_THREADS) {
+    const FftLds<C> L = fft_setup<C>(smem_raw, pl, J, tid, SPC_THREADS);
+    for (int e = tid; e < J * M; e += SPC_THREADS) {
         const int j = e / M, m = e - j * M;
         int q = m - c;
         if (q < 0) q += M;
         L.b0[j * ls + q] = t[j * MN + (int64_t)m * N + n];
     }
     __syncthreads();
-    C* res = dft_run(L, J, pl, true, tid, FFT_THREADS);
+    C* res = dft_run(L, J, pl, true, tid, SPC_THREADS);
     C* oth = (res == L.b0) ? L.b1 : L.b0;
     const R sc = (R)(1.0 / sqrt((double)M));
-    for (int m = tid; m < M; m += FFT_THREADS) {
+    // one (pixel, output coil) pair per thread: the J threads of a pixel read its J x J block coalesced
+    for (int e = tid; e < M * J; e += SPC_THREADS) {
+        const int m = e / J, a = e - m * J;
         int q = m - c;
         if (q < 0) q += M;
-        const C* Ap = A + ((int64_t)m * N + n) * J * J;
-        for (int a = 0; a < J; ++a) {
-            R sr = 0, si = 0;
-            for (int b = 0; b < J; ++b) {
-                const C mv = Ap[a * J + b], v = res[b * ls + q];
-                sr += mv.x * v.x - mv.y * v.y;
-                si += mv.x * v.y + mv.y * v.x;
-            }
-            oth[a * ls + q] = cmk<C>(sr * sc, si * sc);
+        const C* Ar = A + (((int64_t)m * N + n) * J + a) * J;
+        R sr = 0, si = 0;
+        for (int b = 0; b < J; ++b) {
+            const C mv = Ar[b], v = res[b * ls + q];
+            sr += mv.x * v.x - mv.y * v.y;
+            si += mv.x * v.y + mv.y * v.x;
         }
+        oth[a * ls + q] = cmk<C>(sr * sc, si * sc);
     }
     __syncthreads();
     FftLds<C> L2 = L;   // the product is staged in oth
     L2.b0 = oth;
     L2.b1 = res;
-    C* r2 = dft_run(L2, J, pl, false, tid, FFT_THREADS);
-    for (int e = tid; e < J * M; e += FFT_THREADS) {
+    C* r2 = dft_run(L2, J, pl, false, tid, SPC_THREADS);
+    for (int e = tid; e < J * M; e += SPC_THREADS) {
         const int j = e / M, m = e - j * M;
         int q = m - c;
         if (q < 0) q += M;
@@ -695,7 +696,7 @@ hipError_t launch_spirit_cols(hipStream_t st, const cplx_t<R>* t, cplx_t<R>* y, 
     hipError_t e = hipFuncSetAttribute((const void*)k_spirit_cols<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_spirit_cols<R>), dim3(N), dim3(FFT_THREADS), lds, st, t, y, A, J, M, N, pl);
+    hipLaunchKernelGGL((k_spirit_cols<R>), dim3(N), dim3(SPC_THREADS), lds, st, t, y, A, J, M, N, pl);
     return hipGetLastError();
 }
 
