@@ -258,7 +258,7 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
                                                        const cplx_t<R>* __restrict__ wtab,
                                                        const LRDesc* __restrict__ descs, int m0,
                                                        const cplx_t<R>* __restrict__ Ss, int64_t s_stride,
-                                                       R inv_beta, R tau, int KC) {
+                                                       R inv_beta, R tau, int KC, int stage_s) {
     using C = cplx_t<R>;
     using A4 = acc4_t<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -277,6 +277,7 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
     R* Ar = reinterpret_cast<R*>(Bacc + utab);
     R* Ai = Ar + KC * ldA;
     C* Rst = reinterpret_cast<C*>(Ar);  // R staging reuses the A planes: KC x s_pad complex fits in 2*KC*ldA reals
+    C* Sst = reinterpret_cast<C*>(Ai + KC * ldA);   // two staged steps of S: 2 x 4 x s_pad
 
     load_line_table<R>(U, hb, wtab, d, tid, LR_THREADS);
     for (int e = tid; e < utab; e += LR_THREADS) Bacc[e] = cmk<C>(0, 0);
@@ -297,48 +298,29 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
             accR[t] = A4{0, 0, 0, 0};
             accI[t] = A4{0, 0, 0, 0};
         }
-        // tiles of this wave: t-th tile = wave + t * LR_WAVES.  The B operands (rows of S, from
-        // L2) of step kk + 4 are loaded while the products of step kk run, where the registers
-        // allow it (up to 8 FP32 or 4 FP64 tiles per wave).
-        constexpr bool PF = sizeof(R) * MAXT <= 32;
-        auto load_s = [&](int kk, C* dst) {
-            const int kidx = kk + lk;
+        // tiles of this wave: t-th tile = wave + t * LR_WAVES.  The four rows of S that step kk
+        // needs are staged in LDS (two buffers); the rows of step kk + 4 are loaded from L2 into
+        // registers while the products of step kk run, and written to the other buffer after them.
+        const int srow = 4 * s_pad;   // entries per staged step (s_pad <= 320: at most 3 per thread)
+        constexpr int SVN = 3;
+        C sv[SVN];
+        auto load_rows = [&](int kk) {
 #pragma unroll
-            for (int t = 0; t < MAXT; ++t) {
-                const int tile = wave + t * LR_WAVES;
-                const int col = (tile % nt) * 16 + li;
-                dst[t] = (tile < ntile && kidx < s && col < s) ? S[(int64_t)kidx * s + col] : cmk<C>(0, 0);
+            for (int u = 0; u < SVN; ++u) {
+                const int e = tid + u * LR_THREADS;
+                const int row = kk + e / s_pad, col = e % s_pad;
+                sv[u] = (e < srow && row < s && col < s) ? S[(int64_t)row * s + col] : cmk<C>(0, 0);
             }
         };
-        auto mma_step = [&](int kk, const C* sb) {
-            const int kidx = kk + lk;
+        auto store_rows = [&](C* dst) {
 #pragma unroll
-            for (int t = 0; t < MAXT; ++t) {
-                const int tile = wave + t * LR_WAVES;
-                if (tile < ntile) {
-                    const int arow = ((tile / nt) * 16 + li) * ldA + kidx;
-                    const R ar = Ar[arow], ai = Ai[arow];
-                    const R sr = sb[t].x, si = sb[t].y;
-                    accR[t] = mfma16(ar, sr, accR[t]);
-                    accR[t] = mfma16(-ai, si, accR[t]);
-                    accI[t] = mfma16(ar, si, accI[t]);
-                    accI[t] = mfma16(ai, sr, accI[t]);
-                }
+            for (int u = 0; u < SVN; ++u) {
+                const int e = tid + u * LR_THREADS;
+                if (e < srow) dst[e] = sv[u];
             }
         };
-        if constexpr (PF) {
-            C sb[MAXT];
-            load_s(0, sb);
-            for (int kk = 0; kk < s_pad; kk += 4) {
-                C sn[MAXT];
-                if (kk + 4 < s_pad) load_s(kk + 4, sn);
-                mma_step(kk, sb);
-                if (kk + 4 < s_pad) {
-#pragma unroll
-                    for (int t = 0; t < MAXT; ++t) sb[t] = sn[t];
-                }
-            }
-        } else {
+        if (!stage_s) {
+            // LDS too small for the staged rows: B operands straight from L2
             for (int kk = 0; kk < s_pad; kk += 4) {
                 const int kidx = kk + lk;
 #pragma unroll
@@ -350,9 +332,9 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
                         const int col = (tile % nt) * 16 + li;
                         R sr = 0, si = 0;
                         if (kidx < s && col < s) {
-                            const C sv = S[(int64_t)kidx * s + col];
-                            sr = sv.x;
-                            si = sv.y;
+                            const C svv = S[(int64_t)kidx * s + col];
+                            sr = svv.x;
+                            si = svv.y;
                         }
                         accR[t] = mfma16(ar, sr, accR[t]);
                         accR[t] = mfma16(-ai, si, accR[t]);
@@ -361,6 +343,31 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
                     }
                 }
             }
+        } else {
+        load_rows(0);
+        store_rows(Sst);
+        __syncthreads();
+        for (int kk = 0; kk < s_pad; kk += 4) {
+            const int kidx = kk + lk;
+            const C* cur = Sst + ((kk >> 2) & 1) * srow;
+            C* nxt = Sst + (((kk >> 2) & 1) ^ 1) * srow;
+            if (kk + 4 < s_pad) load_rows(kk + 4);
+#pragma unroll
+            for (int t = 0; t < MAXT; ++t) {
+                const int tile = wave + t * LR_WAVES;
+                if (tile < ntile) {
+                    const int arow = ((tile / nt) * 16 + li) * ldA + kidx;
+                    const R ar = Ar[arow], ai = Ai[arow];
+                    const C sb = cur[lk * s_pad + (tile % nt) * 16 + li];
+                    accR[t] = mfma16(ar, sb.x, accR[t]);
+                    accR[t] = mfma16(-ai, sb.y, accR[t]);
+                    accI[t] = mfma16(ar, sb.y, accI[t]);
+                    accI[t] = mfma16(ai, sb.x, accI[t]);
+                }
+            }
+            if (kk + 4 < s_pad) store_rows(nxt);
+            __syncthreads();
+        }
         }
         __syncthreads();  // A planes are dead from here on; reuse them for R
         // epilogue: multiplier update and R staging
@@ -700,10 +707,12 @@ static size_t gram_lds_bytes(int V, int J, int n, int s, int KC) {
     int s_pad = ((s + 15) / 16) * 16;
     return (size_t)V * J * n * sizeof(cplx_t<R>) + 2 * (size_t)KC * (s_pad + 4) * sizeof(R);
 }
+// stage: with the two staged steps of S (8 s_pad complex) after the A planes
 template <typename R>
-static size_t reproj_lds_bytes(int V, int J, int n, int s, int KC) {
+static size_t reproj_lds_bytes(int V, int J, int n, int s, int KC, bool stage = false) {
     int s_pad = ((s + 15) / 16) * 16;
-    return 2 * (size_t)V * J * n * sizeof(cplx_t<R>) + 2 * (size_t)KC * (s_pad + 4) * sizeof(R);
+    return 2 * (size_t)V * J * n * sizeof(cplx_t<R>) + 2 * (size_t)KC * (s_pad + 4) * sizeof(R) +
+           (stage ? 8 * (size_t)s_pad * sizeof(cplx_t<R>) : 0);
 }
 
 constexpr size_t LDS_LIMIT = 160 * 1024;
@@ -759,12 +768,12 @@ hipError_t launch_lift_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>
 template <typename R, int MAXT>
 static hipError_t launch_reproj_t(dim3 grid, size_t lds, hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db,
                                   cplx_t<R>* bb, const cplx_t<R>* wtab, const LRDesc* descs, int m0,
-                                  const cplx_t<R>* Ss, int64_t sst, R inv_beta, R tau, int KC) {
+                                  const cplx_t<R>* Ss, int64_t sst, R inv_beta, R tau, int KC, int stage) {
     hipError_t e = hipFuncSetAttribute((const void*)k_reproj<R, MAXT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_reproj<R, MAXT>), grid, dim3(LR_THREADS), lds, st, hb, db, bb, wtab, descs, m0, Ss, sst,
-                       inv_beta, tau, KC);
+                       inv_beta, tau, KC, stage);
     return hipGetLastError();
 }
 
@@ -777,16 +786,23 @@ hipError_t launch_reproj(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cpl
     int KC = (kc >= 16 && kc <= 64 && kc % 16 == 0) ? kc : 64;   // rows of A per chunk
     while (KC > 16 && (reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT || KC > ((l + 15) / 16) * 16))
         KC -= 16;
-    const size_t lds = reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC);
+    size_t lds = reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC);
     if (lds > LDS_LIMIT) return hipErrorInvalidValue;
+    // rows of S staged through LDS where the space allows
+    const int stage = reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC, true) <= LDS_LIMIT ? 1 : 0;
+    if (stage) lds = reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC, true);
     const int tiles = (KC / 16) * nt;
     const int need = (tiles + LR_WAVES - 1) / LR_WAVES;
     dim3 grid(count);
     const R ib = (R)(1.0 / beta), tt = (R)tau;
-    if (need <= 2) return launch_reproj_t<R, 2>(grid, lds, st, hb, db, bb, wtab, descs_dev, m0, Ss, s_stride, ib, tt, KC);
-    if (need <= 4) return launch_reproj_t<R, 4>(grid, lds, st, hb, db, bb, wtab, descs_dev, m0, Ss, s_stride, ib, tt, KC);
-    if (need <= 8) return launch_reproj_t<R, 8>(grid, lds, st, hb, db, bb, wtab, descs_dev, m0, Ss, s_stride, ib, tt, KC);
-    if (need <= 12) return launch_reproj_t<R, 12>(grid, lds, st, hb, db, bb, wtab, descs_dev, m0, Ss, s_stride, ib, tt, KC);
+    if (need <= 2)
+        return launch_reproj_t<R, 2>(grid, lds, st, hb, db, bb, wtab, descs_dev, m0, Ss, s_stride, ib, tt, KC, stage);
+    if (need <= 4)
+        return launch_reproj_t<R, 4>(grid, lds, st, hb, db, bb, wtab, descs_dev, m0, Ss, s_stride, ib, tt, KC, stage);
+    if (need <= 8)
+        return launch_reproj_t<R, 8>(grid, lds, st, hb, db, bb, wtab, descs_dev, m0, Ss, s_stride, ib, tt, KC, stage);
+    if (need <= 12)
+        return launch_reproj_t<R, 12>(grid, lds, st, hb, db, bb, wtab, descs_dev, m0, Ss, s_stride, ib, tt, KC, stage);
     return hipErrorInvalidValue;
 }
 
