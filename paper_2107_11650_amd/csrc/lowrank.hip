@@ -286,7 +286,10 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
     const C* S = Ss + (int64_t)blockIdx.x * s_stride;
     const int li = lane & 15, lk = lane >> 4;
     const int rt = KC / 16;               // row tiles per chunk
-    const int ntile = rt * nt;            // tiles per chunk
+    // tiles of this wave: one row tile It_w and the column tiles kw, kw + nwi, ... (the waves that
+    // share a row tile split its column tiles), so the A operand of a step is read once per wave
+    const int It_w = wave % rt, kw = wave / rt;
+    const int nwi = (LR_WAVES - It_w + rt - 1) / rt;
 
     for (int r0 = 0; r0 < l; r0 += KC) {
         __syncthreads();
@@ -323,13 +326,13 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
             // LDS too small for the staged rows: B operands straight from L2
             for (int kk = 0; kk < s_pad; kk += 4) {
                 const int kidx = kk + lk;
+                const int arow = (It_w * 16 + li) * ldA + kidx;
+                const R ar = Ar[arow], ai = Ai[arow];
 #pragma unroll
                 for (int t = 0; t < MAXT; ++t) {
-                    const int tile = wave + t * LR_WAVES;
-                    if (tile < ntile) {
-                        const int arow = ((tile / nt) * 16 + li) * ldA + kidx;
-                        const R ar = Ar[arow], ai = Ai[arow];
-                        const int col = (tile % nt) * 16 + li;
+                    const int Jt = kw + nwi * t;
+                    if (Jt < nt) {
+                        const int col = Jt * 16 + li;
                         R sr = 0, si = 0;
                         if (kidx < s && col < s) {
                             const C svv = S[(int64_t)kidx * s + col];
@@ -352,17 +355,19 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
             const C* cur = Sst + ((kk >> 2) & 1) * srow;
             C* nxt = Sst + (((kk >> 2) & 1) ^ 1) * srow;
             if (kk + 4 < s_pad) load_rows(kk + 4);
+            // every operand of the step is read before the products (one wait per step)
+            const int arow = (It_w * 16 + li) * ldA + kidx;
+            const R ar = Ar[arow], ai = Ai[arow];
+            C sb[MAXT];
+#pragma unroll
+            for (int t = 0; t < MAXT; ++t) sb[t] = cur[lk * s_pad + min(kw + nwi * t, nt - 1) * 16 + li];
 #pragma unroll
             for (int t = 0; t < MAXT; ++t) {
-                const int tile = wave + t * LR_WAVES;
-                if (tile < ntile) {
-                    const int arow = ((tile / nt) * 16 + li) * ldA + kidx;
-                    const R ar = Ar[arow], ai = Ai[arow];
-                    const C sb = cur[lk * s_pad + (tile % nt) * 16 + li];
-                    accR[t] = mfma16(ar, sb.x, accR[t]);
-                    accR[t] = mfma16(-ai, sb.y, accR[t]);
-                    accI[t] = mfma16(ar, sb.y, accI[t]);
-                    accI[t] = mfma16(ai, sb.x, accI[t]);
+                if (kw + nwi * t < nt) {   // uniform over the wave
+                    accR[t] = mfma16(ar, sb[t].x, accR[t]);
+                    accR[t] = mfma16(-ai, sb[t].y, accR[t]);
+                    accI[t] = mfma16(ar, sb[t].y, accI[t]);
+                    accI[t] = mfma16(ai, sb[t].x, accI[t]);
                 }
             }
             if (kk + 4 < s_pad) store_rows(nxt);
@@ -373,9 +378,9 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
         // epilogue: multiplier update and R staging
 #pragma unroll
         for (int t = 0; t < MAXT; ++t) {
-            const int tile = wave + t * LR_WAVES;
-            if (tile < ntile) {
-                const int It = tile / nt, Jt = tile - It * nt;
+            const int Jt = kw + nwi * t;
+            if (Jt < nt) {
+                const int It = It_w;
                 const int col = Jt * 16 + li;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -791,8 +796,8 @@ hipError_t launch_reproj(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cpl
     // rows of S staged through LDS where the space allows
     const int stage = reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC, true) <= LDS_LIMIT ? 1 : 0;
     if (stage) lds = reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC, true);
-    const int tiles = (KC / 16) * nt;
-    const int need = (tiles + LR_WAVES - 1) / LR_WAVES;
+    // column tiles per wave: the fewest waves that share a row tile take ceil(nt / that) each
+    const int need = (nt + LR_WAVES / (KC / 16) - 1) / (LR_WAVES / (KC / 16));
     dim3 grid(count);
     const R ib = (R)(1.0 / beta), tt = (R)tau;
     if (need <= 2)
