@@ -412,7 +412,8 @@ __device__ __attribute__((always_inline)) void backtransform_wy(double2* __restr
 // the complex off-diagonal and h_i as 4 s doubles at the start of the scratch.
 // ---------------------------------------------------------------------------
 constexpr int RR_MAXS = 208;
-constexpr int RR_THREADS = 512;
+constexpr int RR_THREADS = 768;
+constexpr int RR_WAVES = RR_THREADS / 64;
 
 __device__ inline int rr_bidx(int I, int J, int nb) { return J * nb - (J * (J - 1)) / 2 + (I - J); }
 
@@ -431,7 +432,7 @@ __device__ inline double2 rank2_sub(double2 a, double2 ur, double2 qr, double2 u
 
 
 template <int MAXB>
-__global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __restrict__ descs, int m0,
+__global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restrict__ descs, int m0,
                                                               double2* __restrict__ Gs, int64_t g_stride,
                                                               double* __restrict__ scr, int64_t scr_stride) {
     // separate LDS objects, so that the stores of partial sums do not order the vector loads
@@ -464,7 +465,7 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
     int bI[MAXB], bJ[MAXB];
 #pragma unroll
     for (int t = 0; t < MAXB; ++t) {
-        int b = wave + 8 * t, J = 0;
+        int b = wave + RR_WAVES * t, J = 0;
         while (J < nb && b >= nb - J) {
             b -= nb - J;
             ++J;
@@ -479,7 +480,7 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
         const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
         for (int t = 0; t < MAXB; ++t) {
-            const bool has = wave + 8 * t < nblk;
+            const bool has = wave + RR_WAVES * t < nblk;
             const int c = bJ[t] * 16 + lr;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -504,7 +505,7 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
         // column 0 into xraw
 #pragma unroll
         for (int t = 0; t < MAXB; ++t) {
-            if (wave + 8 * t < nblk && bJ[t] == 0 && lr == 0) {
+            if (wave + RR_WAVES * t < nblk && bJ[t] == 0 && lr == 0) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int r = bI[t] * 16 + lk + 4 * q;
@@ -518,8 +519,16 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
     // Thread t works on row j + t of the current column j (every row count here is below 512).
     // finish_and_reflect: column j (rows >= j, raw in xraw) minus the update (u, q) of step j-1
     // (in uc / qp, none for j = 0), its diagonal entry, and the reflector of column j into uc.
+    // the thread index, recomputed where it is used (the wave index is a scalar), so that no
+    // vector register keeps it across the step loop
+    auto tid_now = [&]() {
+        int ln;
+        asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+        return wave * 64 + ln;
+    };
     auto finish_and_reflect = [&](int j, bool pending, double2 q_j) {
-        const int r = j + tid;
+        const int tl = tid_now();
+        const int r = j + tl;
         double tail = 0;
         if (r < s) {
             double2 v = xraw[r];
@@ -535,7 +544,7 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
             if (r > j + 1) tail = cabs2(v);
         }
         tail = wave_sum_to63(tail);
-        if (lane == 63) red[RR_THREADS / 64 + wave] = tail;
+        if ((tl & 63) == 63) red[RR_THREADS / 64 + wave] = tail;
         __syncthreads();
         if (j + 1 >= s) return;
         tail = 0;
@@ -550,12 +559,18 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
             if (aabs > 0) ph = make_double2(al.x / aabs, al.y / aabs);
             hh = xn * xn + aabs * xn;
         }
-        if (tid == 0) {
+        if (tl == 0) {
             ter[j] = refl ? -ph.x * xn : al.x;
             tei[j] = refl ? -ph.y * xn : al.y;
             thv[j] = refl ? hh : 0.0;
         }
-        if (r == j) uc[j] = make_double2(0.0, 0.0);   // entries at and above the column stay zero
+        if (r == j) {
+            // entries at and above the column stay zero (the zero is made here rather than kept
+            // in registers across the loop)
+            double zx, zy;
+            asm volatile("v_mov_b64 %0, 0\n\tv_mov_b64 %1, 0" : "=v"(zx), "=v"(zy));
+            uc[j] = make_double2(zx, zy);
+        }
         if (r > j && r < s) {
             double2 u = make_double2(0.0, 0.0);
             if (refl) {
@@ -564,7 +579,7 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
             }
             uc[r] = u;
         }
-        if (tid == 0) {
+        if (tl == 0) {
             rh[0] = hh;
             rh[1] = 1.0 / hh;
             rrefl = refl;
@@ -582,7 +597,7 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
         // so the stale values there never reach a live product.
 #pragma unroll
         for (int t = 0; t < MAXB; ++t) {
-            int b = wave + 8 * t;
+            int b = wave + RR_WAVES * t;
             if (b >= nblk || bJ[t] < jlo) continue;   // uniform over the wave
             int I = bI[t], J = bJ[t];
             // keep the block's index arithmetic inside the step (it would otherwise be hoisted
@@ -641,7 +656,8 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
         // (b) p = A u_i / h and u^H p over all threads, then q_i, column i+1 and the next reflector
         {
             const int j = i + 1;
-            const int r = j + tid;
+            const int tl = tid_now();
+            const int r = j + tl;
             const bool refl = rrefl != 0;
             const double hh = rh[0], ihh = rh[1];
             double2 pv = make_double2(0.0, 0.0);
@@ -668,7 +684,7 @@ __global__ __launch_bounds__(RR_THREADS, 2) void k_tridiag_rr(const LRDesc* __re
                 if (r == j) salpha[1] = pv;
             }
             uhp = wave_sum_to63(uhp);
-            if (lane == 63) red[wave] = uhp;
+            if ((tl & 63) == 63) red[wave] = uhp;
             __syncthreads();
             uhp = 0;
             for (int w = 0; w < RR_THREADS / 64; ++w) uhp += red[w];
@@ -1539,11 +1555,12 @@ hipError_t launch_tridiag_rr(hipStream_t st, const LRDesc* descs, int m0, int co
                              double* scr, int64_t scr_stride, int smax) {
     if (!tridiag_rr_supported(smax)) return hipErrorInvalidValue;
     const int nb = (smax + 15) / 16, nblk = nb * (nb + 1) / 2;
-    const void* fn = nb <= 6 ? (const void*)k_tridiag_rr<3>
-                   : nb <= 8 ? (const void*)k_tridiag_rr<5>
-                   : nb <= 10 ? (const void*)k_tridiag_rr<7>
-                   : nb <= 12 ? (const void*)k_tridiag_rr<10>
-                              : (const void*)k_tridiag_rr<12>;
+    // blocks per wave: ceil(nblk / RR_WAVES)
+    const void* fn = nb <= 6 ? (const void*)k_tridiag_rr<2>
+                   : nb <= 8 ? (const void*)k_tridiag_rr<3>
+                   : nb <= 10 ? (const void*)k_tridiag_rr<5>
+                   : nb <= 12 ? (const void*)k_tridiag_rr<7>
+                              : (const void*)k_tridiag_rr<8>;
     void* args[] = {(void*)&descs, (void*)&m0, (void*)&Gs, (void*)&g_stride, (void*)&scr, (void*)&scr_stride};
     hipError_t e = hipLaunchKernel(fn, dim3(count), dim3(RR_THREADS), args, 0, st);
     if (e != hipSuccess) return e;
