@@ -425,6 +425,55 @@ __global__ __launch_bounds__(SPC_THREADS) void k_spirit_cols(const cplx_t<R>* __
     }
 }
 
+// PCG direction update fused with the first (inverse, row) pass of the SPIRiT operator:
+// rz_new = sum of the previous update's partials (fixed order), beta = rz_new / rz_prev,
+// p = z + beta p (written back), t = F_n^-1 p along rows.  Block 0 stores rz_new for the next
+// step length.  Rows of length N, J*M of them, contiguous.
+template <typename R>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_dir(cplx_t<R>* __restrict__ p, const cplx_t<R>* __restrict__ z,
+                                                              cplx_t<R>* __restrict__ t, int n_lines, int N,
+                                                              FftPlan pl, int NL, const double* __restrict__ upart,
+                                                              int n_upart, const double* __restrict__ rz_prev,
+                                                              double* __restrict__ rz_out) {
+    using C = cplx_t<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[FFT_THREADS];
+    const int tid = threadIdx.x, ls = pl.f, c = N / 2;
+    double a = 0;
+    for (int i = tid; i < n_upart; i += FFT_THREADS) a += upart[i];
+    red[tid] = a;
+    __syncthreads();
+    for (int h = FFT_THREADS / 2; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    const double rz_new = red[0], rz0 = *rz_prev;
+    if (blockIdx.x == 0 && tid == 0) *rz_out = rz_new;
+    const R bc = (R)(rz0 != 0.0 ? rz_new / rz0 : 0.0);
+    const FftLds<C> L = fft_setup<C>(smem_raw, pl, NL, tid, FFT_THREADS);
+    const int g0 = blockIdx.x * NL;
+    const int nl = min(NL, n_lines - g0);
+    for (int e = tid; e < nl * N; e += FFT_THREADS) {
+        const int line = e / N, i = e - line * N;
+        int q = i - c;
+        if (q < 0) q += N;
+        const int64_t ge = (int64_t)(g0 + line) * N + i;
+        const C pv = p[ge], zv = z[ge];
+        const C np = cmk<C>(zv.x + bc * pv.x, zv.y + bc * pv.y);
+        p[ge] = np;
+        L.b0[line * ls + q] = np;
+    }
+    __syncthreads();
+    C* res = dft_run(L, nl, pl, true, tid, FFT_THREADS);
+    const R sc = (R)(1.0 / sqrt((double)N));
+    for (int e = tid; e < nl * N; e += FFT_THREADS) {
+        const int line = e / N, i = e - line * N;
+        int q = i - c;
+        if (q < 0) q += N;
+        t[(int64_t)(g0 + line) * N + i] = cscale(res[line * ls + q], sc);
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_apply(cplx_t<R>* __restrict__ io,
                                                                 const cplx_t<R>* __restrict__ p, int J, int M, int N,
@@ -701,6 +750,21 @@ hipError_t launch_spirit_cols(hipStream_t st, const cplx_t<R>* t, cplx_t<R>* y, 
 }
 
 template <typename R>
+hipError_t launch_fft_rows_dir(hipStream_t st, cplx_t<R>* p, const cplx_t<R>* z, cplx_t<R>* t, int n_lines, int N,
+                               const double* upart, int n_upart, const double* rz_prev, double* rz_out) {
+    const FftPlan pl = make_fft_plan(N);
+    const int NL = fft_lines_per_block<R>(pl, false);
+    const size_t lds = fft_lds_bytes<R>(pl, NL);
+    hipError_t e = hipFuncSetAttribute((const void*)k_fft_rows_dir<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    const int blocks = (n_lines + NL - 1) / NL;
+    hipLaunchKernelGGL((k_fft_rows_dir<R>), dim3(blocks), dim3(FFT_THREADS), lds, st, p, z, t, n_lines, N, pl, NL,
+                       upart, n_upart, rz_prev, rz_out);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_fft_rows_apply(hipStream_t st, cplx_t<R>* io, const cplx_t<R>* p, int J, int M, int N,
                                  const uint8_t* mask, const R* rtab, int64_t rr_off, int64_t rc_off, double lam,
                                  double beta, double lam1, double* partials) {
@@ -731,6 +795,8 @@ hipError_t launch_fft_rows_apply(hipStream_t st, cplx_t<R>* io, const cplx_t<R>*
     template hipError_t launch_fill_hash<R>(hipStream_t, cplx_t<R>*, int64_t, uint64_t, double);                     \
     template hipError_t launch_maxabs<R>(hipStream_t, const cplx_t<R>*, int64_t, unsigned long long*, uint32_t*);   \
     template int spirit_fused_blocks<R>(int, int, int);                                                              \
+    template hipError_t launch_fft_rows_dir<R>(hipStream_t, cplx_t<R>*, const cplx_t<R>*, cplx_t<R>*, int, int,        \
+                                               const double*, int, const double*, double*);                          \
     template hipError_t launch_spirit_cols<R>(hipStream_t, const cplx_t<R>*, cplx_t<R>*, const cplx_t<R>*, int, int, \
                                               int);                                                                  \
     template hipError_t launch_fft_rows_apply<R>(hipStream_t, cplx_t<R>*, const cplx_t<R>*, int, int, int,           \

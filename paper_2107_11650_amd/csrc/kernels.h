@@ -60,6 +60,9 @@ template <typename R>
 hipError_t launch_spirit_cols(hipStream_t st, const cplx_t<R>* t, cplx_t<R>* y, const cplx_t<R>* A, int J, int M,
                               int N);
 template <typename R>
+hipError_t launch_fft_rows_dir(hipStream_t st, cplx_t<R>* p, const cplx_t<R>* z, cplx_t<R>* t, int n_lines, int N,
+                               const double* upart, int n_upart, const double* rz_prev, double* rz_out);
+template <typename R>
 hipError_t launch_fft_rows_apply(hipStream_t st, cplx_t<R>* io, const cplx_t<R>* p, int J, int M, int N,
                                  const uint8_t* mask, const R* rtab, int64_t rr_off, int64_t rc_off, double lam,
                                  double beta, double lam1, double* partials);
