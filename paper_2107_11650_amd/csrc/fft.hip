@@ -385,7 +385,12 @@ __global__ __launch_bounds__(SPC_THREADS) void k_spirit_cols(const cplx_t<R>* __
                                                              FftPlan pl) {
     using C = cplx_t<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int tid = threadIdx.x, n = blockIdx.x, ls = pl.f, c = M / 2;
+    // blocks are dealt to the 8 XCDs in turn: give each XCD a contiguous range of columns, so that a
+    // cache line of 16 neighbouring columns is fetched into (and written back from) one L2 only
+    const int per = (N + 7) / 8;
+    const int n = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (n >= N) return;   // uniform over the block
+    const int tid = threadIdx.x, ls = pl.f, c = M / 2;
     const int64_t MN = (int64_t)M * N;
     const FftLds<C> L = fft_setup<C>(smem_raw, pl, J, tid, SPC_THREADS);
     for (int e = tid; e < J * M; e += SPC_THREADS) {
@@ -745,7 +750,8 @@ hipError_t launch_spirit_cols(hipStream_t st, const cplx_t<R>* t, cplx_t<R>* y, 
     hipError_t e = hipFuncSetAttribute((const void*)k_spirit_cols<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_spirit_cols<R>), dim3(N), dim3(SPC_THREADS), lds, st, t, y, A, J, M, N, pl);
+    hipLaunchKernelGGL((k_spirit_cols<R>), dim3(8 * ((N + 7) / 8)), dim3(SPC_THREADS), lds, st, t, y, A, J, M, N,
+                       pl);
     return hipGetLastError();
 }
 
