@@ -205,18 +205,44 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
             const R a1r = Ar[row + I1 * 16], a1i = Ai[row + I1 * 16];
             R a2r = 0, a2i = 0;
             if (I2 >= 0) { a2r = Ar[row + I2 * 16]; a2i = Ai[row + I2 * 16]; }
+            if constexpr (sizeof(R) == 4 && MAXT <= 16) {
+                // every B operand of the step is read before the products (one wait per
+                // step); wider tiles or FP64 operands would not fit in registers beside them
+                R br[MAXT], bi[MAXT];
 #pragma unroll
-            for (int t = 0; t < MAXT; ++t) {
-                if (t < count) {
-                    const bool first = t < cnt1;
-                    const int Jb = first ? I1 + t : I2 + (t - cnt1);
-                    const R ar = first ? a1r : a2r;
-                    const R ai = first ? a1i : a2i;
-                    const R br = Ar[row + Jb * 16], bi = Ai[row + Jb * 16];
-                    accR[t] = mfma16(ar, br, accR[t]);
-                    accR[t] = mfma16(ai, bi, accR[t]);
-                    accI[t] = mfma16(ar, bi, accI[t]);
-                    accI[t] = mfma16(-ai, br, accI[t]);
+                for (int t = 0; t < MAXT; ++t) {
+                    if (t < count) {
+                        const int Jb = t < cnt1 ? I1 + t : I2 + (t - cnt1);
+                        br[t] = Ar[row + Jb * 16];
+                        bi[t] = Ai[row + Jb * 16];
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < MAXT; ++t) {
+                    if (t < count) {
+                        const bool first = t < cnt1;
+                        const R ar = first ? a1r : a2r;
+                        const R ai = first ? a1i : a2i;
+                        accR[t] = mfma16(ar, br[t], accR[t]);
+                        accR[t] = mfma16(ai, bi[t], accR[t]);
+                        accI[t] = mfma16(ar, bi[t], accI[t]);
+                        accI[t] = mfma16(-ai, br[t], accI[t]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < MAXT; ++t) {
+                    if (t < count) {
+                        const bool first = t < cnt1;
+                        const int Jb = first ? I1 + t : I2 + (t - cnt1);
+                        const R ar = first ? a1r : a2r;
+                        const R ai = first ? a1i : a2i;
+                        const R br = Ar[row + Jb * 16], bi = Ai[row + Jb * 16];
+                        accR[t] = mfma16(ar, br, accR[t]);
+                        accR[t] = mfma16(ai, bi, accR[t]);
+                        accI[t] = mfma16(ar, bi, accI[t]);
+                        accI[t] = mfma16(-ai, br, accI[t]);
+                    }
                 }
             }
         }
