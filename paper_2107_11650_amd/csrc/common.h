@@ -91,58 +91,36 @@ __device__ inline double row16_sum_to15(double v) {
     v += dpp_shift_d(v, 8);
     return v;
 }
-// a double moved between lanes by a DPP control (all lanes of the row valid)
+// a double moved between lanes by a DPP control that reads a valid lane for every lane
 template <int CTRL>
 __device__ inline double dpp_move_d(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
     return __hiloint2double(hi, lo);
 }
-template <int CTRL>
-__device__ inline double2 dpp_move_z(double2 v) {
-    return make_double2(dpp_move_d<CTRL>(v.x), dpp_move_d<CTRL>(v.y));
+// the sum of a complex value over each quad of lanes, in every lane of the quad
+__device__ inline double2 quad_sum_z(double2 v) {
+    v.x += dpp_move_d<0xB1>(v.x);   // quad_perm [1,0,3,2]
+    v.y += dpp_move_d<0xB1>(v.y);
+    v.x += dpp_move_d<0x4E>(v.x);   // quad_perm [2,3,0,1]
+    v.y += dpp_move_d<0x4E>(v.y);
+    return v;
 }
-// Sums of four complex values v[0..3] over each row of 16 lanes (reduce-scatter: row rotate
-// by 8, half mirror, then quad butterflies).  On return lane l of a row holds the total of
-// v[k] with k = 2 (l & 8 ? 1 : 0) + ((l & 7) >= 4 ? 1 : 0), and all four lanes of a quad agree.
-__device__ inline double2 row16_reduce4_z(const double2 v[4], int lr) {
-    const bool hi8 = (lr & 8) != 0, hi4 = (lr & 7) >= 4;
-    const double2 sA = hi8 ? v[0] : v[2], sB = hi8 ? v[1] : v[3];
-    double2 kA = hi8 ? v[2] : v[0], kB = hi8 ? v[3] : v[1];
-    const double2 rA = dpp_move_z<0x128>(sA), rB = dpp_move_z<0x128>(sB);   // row_ror:8
-    kA.x += rA.x;
-    kA.y += rA.y;
-    kB.x += rB.x;
-    kB.y += rB.y;
-    const double2 s2 = hi4 ? kA : kB;
-    double2 k2 = hi4 ? kB : kA;
-    const double2 r2 = dpp_move_z<0x141>(s2);                                 // row_half_mirror
-    k2.x += r2.x;
-    k2.y += r2.y;
-    double2 t = dpp_move_z<0xB1>(k2);                                         // quad_perm [1,0,3,2]
-    k2.x += t.x;
-    k2.y += t.y;
-    t = dpp_move_z<0x4E>(k2);                                                 // quad_perm [2,3,0,1]
-    k2.x += t.x;
-    k2.y += t.y;
-    return k2;
-}
-// v + v[lane ^ 32] and v + v[lane ^ 16] in every lane, with the gfx950 lane-swap
-// instructions (VALU only).  permlane32_swap(a, b) exchanges the upper half of a
-// with the lower half of b; permlane16_swap(a, b) the odd rows of a with the even
-// rows of b.  With a = b = v the two results hold v and its partner lane in
-// opposite order, so their sum is the butterfly sum in every lane.
-__device__ inline double xor32_sum(double v) {
-    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
-    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
-}
-__device__ inline double xor16_sum(double v) {
-    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
-    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+// Sums of x and of y over the four rows of 16 lanes (lanes l, l ^ 16, l ^ 32, l ^ 48), with
+// the gfx950 lane-swap instructions.  permlane16_swap(a, b) exchanges the odd rows of a with
+// the even rows of b, so swapping x with y leaves rows (x0, y0, x2, y2) and (x1, y1, x3, y3),
+// whose sum pairs the rows; permlane32_swap(c, c) exchanges the halves of c.  On return lanes
+// of rows 0 and 2 hold the sum of x, lanes of rows 1 and 3 the sum of y.
+__device__ inline double colsum4_pair(double x, double y) {
+    const auto l = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y),
+                                                    false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y),
+                                                    false, false);
+    const double c = __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+    const unsigned clo = (unsigned)__double2loint(c), chi = (unsigned)__double2hiint(c);
+    const auto l2 = __builtin_amdgcn_permlane32_swap(clo, clo, false, false);
+    const auto h2 = __builtin_amdgcn_permlane32_swap(chi, chi, false, false);
+    return __hiloint2double((int)h2[0], (int)l2[0]) + __hiloint2double((int)h2[1], (int)l2[1]);
 }
 // the maximum over the 64 lanes, in every lane
 __device__ inline double wave_max_all(double v) {

@@ -414,6 +414,7 @@ __device__ __attribute__((always_inline)) void backtransform_wy(double2* __restr
 constexpr int RR_MAXS = 208;
 constexpr int RR_THREADS = 768;
 constexpr int RR_WAVES = RR_THREADS / 64;
+constexpr int RR_TILE = 16 * 17;
 
 __device__ inline int rr_bidx(int I, int J, int nb) { return J * nb - (J * (J - 1)) / 2 + (I - J); }
 
@@ -444,6 +445,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
     __shared__ double2 xraw[RR_SP];               // captured column i+1
     __shared__ double2 yrow[RR_NBLK * 16];        // [block][16] row partials
     __shared__ double2 ycol[RR_NBLK * 16];        // [block][16] column partials
+    __shared__ double2 rtile[RR_WAVES * RR_TILE];  // per wave: products of a block, 16 rows of 17
     __shared__ double2 salpha[2];                 // [0] alpha of the reflector, [1] p_j
     __shared__ double red[2 * (RR_THREADS / 64)];  // per-wave partial sums: u^H p, then tails
     __shared__ double rh[2];                      // h of the current reflector and 1 / h
@@ -624,32 +626,40 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
                     if (r > i && r < s) xraw[r] = make_double2(ar_[t][q], ai_[t][q]);
                 }
             }
-            // column partials conj(A)^T u over the block's rows: in-lane, then across the four rows of lanes
+            // column partials conj(A)^T u over the block's rows: in-lane, then across the four rows
+            // of lanes; lanes of row 0 end with the real part, lanes of row 1 the imaginary part
             const double2 uC = uc[J * 16 + lr];
-            double2 ycl = make_double2(0.0, 0.0);
+            double ycx = 0.0, ycy = 0.0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const double2 uR = uc[I * 16 + lk + 4 * q];
-                const double2 av = make_double2(ar_[t][q], ai_[t][q]);
-                ycl.x = fma(av.x, uR.x, fma(av.y, uR.y, ycl.x));
-                ycl.y = fma(av.x, uR.y, fma(-av.y, uR.x, ycl.y));
+                ycx = fma(ar_[t][q], uR.x, fma(ai_[t][q], uR.y, ycx));
+                ycy = fma(ar_[t][q], uR.y, fma(-ai_[t][q], uR.x, ycy));
             }
-            ycl.x = xor32_sum(xor16_sum(ycl.x));
-            ycl.y = xor32_sum(xor16_sum(ycl.y));
-            if (I == J) {
-                // a diagonal block is held in full and Hermitian: its column sums are its row sums
-                if (lk == 0) yrow[b * 16 + lr] = ycl;
-            } else {
-                if (lk == 0) ycol[b * 16 + lr] = ycl;
-                // row partials A u_C: one per row held by the lane, summed over the 16 columns
-                double2 yq[4];
+            const double ycs = colsum4_pair(ycx, ycy);
+            // a diagonal block is held in full and Hermitian: its column sums are its row sums
+            double2* ydst = I == J ? yrow : ycol;
+            if (lk < 2) reinterpret_cast<double*>(ydst + b * 16 + lr)[lk] = ycs;
+            if (I != J) {
+                // row partials A u_C: the lane's products go through a per-wave LDS tile (rows of
+                // 17 entries, so that neither pass conflicts on banks); a quad of lanes then sums
+                // one row, four columns per lane
+                double2* tile = rtile + wave * RR_TILE;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) yq[q] = cmul(make_double2(ar_[t][q], ai_[t][q]), uC);
-                const double2 rs = row16_reduce4_z(yq, lr);
-                if ((lr & 3) == 0) {
-                    const int kk = 2 * ((lr >> 3) & 1) + (((lr & 7) >= 4) ? 1 : 0);
-                    yrow[b * 16 + lk + 4 * kk] = rs;
+                for (int q = 0; q < 4; ++q)
+                    tile[(lk + 4 * q) * 17 + lr] = cmul(make_double2(ar_[t][q], ai_[t][q]), uC);
+                __builtin_amdgcn_wave_barrier();
+                const int rho = ln >> 2, c0 = (ln & 3) * 4;
+                double2 rs = tile[rho * 17 + c0];
+#pragma unroll
+                for (int m = 1; m < 4; ++m) {
+                    const double2 v = tile[rho * 17 + c0 + m];
+                    rs.x += v.x;
+                    rs.y += v.y;
                 }
+                __builtin_amdgcn_wave_barrier();
+                rs = quad_sum_z(rs);
+                if ((ln & 3) == 0) yrow[b * 16 + rho] = rs;
             }
         }
         __syncthreads();
