@@ -439,7 +439,10 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
     // separate LDS objects, so that the stores of partial sums do not order the vector loads
     constexpr int RR_SP = ((RR_MAXS + 15) / 16) * 16;
     constexpr int RR_NB = RR_SP / 16, RR_NBLK = RR_NB * (RR_NB + 1) / 2;
-    __shared__ double2 up[RR_SP];                 // pending update u_{i-1}, by absolute row
+    // operands of the pending update in the lane order of the matrix cores (negated):
+    // opA[I][lane] = (a, a') of row I*16 + lane%16, opB[J][lane] = b of column J*16 + lane%16
+    __shared__ double2 opA[RR_NB * 64];
+    __shared__ double opB[RR_NB * 64];
     __shared__ double2 qp[RR_SP];                 // pending q_{i-1}
     __shared__ double2 uc[RR_SP];                 // current reflector u_i
     __shared__ double2 xraw[RR_SP];               // captured column i+1
@@ -500,9 +503,12 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
             }
         }
         for (int e = tid; e < sp; e += RR_THREADS) {
-            up[e] = make_double2(0.0, 0.0);
             qp[e] = make_double2(0.0, 0.0);
             uc[e] = make_double2(0.0, 0.0);
+        }
+        for (int e = tid; e < nb * 64; e += RR_THREADS) {
+            opA[e] = make_double2(0.0, 0.0);
+            opB[e] = 0.0;
         }
         // column 0 into xraw
 #pragma unroll
@@ -609,14 +615,11 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
             asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
             const int lr = ln & 15, lk = ln >> 4;
             if (pend) {
-                // D -= [u_r q_r] [q_c u_c]^H: A = (u_r.x, u_r.y, q_r.x, q_r.y) by row, B = (q_c.x, q_c.y,
-                // u_c.x, u_c.y) by column; the imaginary part takes A' = (u_r.y, -u_r.x, q_r.y, -q_r.x)
-                const double2 va = (lk < 2 ? up : qp)[I * 16 + lr];
-                const double2 vb = (lk < 2 ? qp : up)[J * 16 + lr];
-                const bool odd = (lk & 1) != 0;
-                const double a1 = odd ? va.y : va.x, a2 = odd ? -va.x : va.y, b1 = odd ? vb.y : vb.x;
-                ar_[t] = mfma16(-a1, b1, ar_[t]);
-                ai_[t] = mfma16(-a2, b1, ai_[t]);
+                // D -= [u_r q_r] [q_c u_c]^H on the matrix cores, operands as stored in (b)
+                const double2 a = opA[I * 64 + ln];
+                const double bq = opB[J * 64 + ln];
+                ar_[t] = mfma16(a.x, bq, ar_[t]);
+                ai_[t] = mfma16(a.y, bq, ai_[t]);
             }
             const int cc = i + 1 - J * 16;
             if (cc >= 0 && cc < 16 && lr == cc) {
@@ -645,15 +648,17 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
                 // 17 entries, so that neither pass conflicts on banks); a quad of lanes then sums
                 // one row, four columns per lane
                 double2* tile = rtile + wave * RR_TILE;
+                const int wr = (int)__umul24(lk, 17) + lr;        // row lk, column lr (rows of 17)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    tile[(lk + 4 * q) * 17 + lr] = cmul(make_double2(ar_[t][q], ai_[t][q]), uC);
+                    tile[wr + 68 * q] = cmul(make_double2(ar_[t][q], ai_[t][q]), uC);
                 __builtin_amdgcn_wave_barrier();
-                const int rho = ln >> 2, c0 = (ln & 3) * 4;
-                double2 rs = tile[rho * 17 + c0];
+                const int rho = ln >> 2;
+                const int rd = (int)__umul24(rho, 17) + ((ln & 3) << 2);   // row rho, columns 4 (ln % 4) ..
+                double2 rs = tile[rd];
 #pragma unroll
                 for (int m = 1; m < 4; ++m) {
-                    const double2 v = tile[rho * 17 + c0 + m];
+                    const double2 v = tile[rd + m];
                     rs.x += v.x;
                     rs.y += v.y;
                 }
@@ -706,8 +711,20 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
             }
             if (r < s) {
                 const double2 u = refl ? uc[r] : make_double2(0.0, 0.0);
-                up[r] = u;
-                qp[r] = make_double2(pv.x - Kc * u.x, pv.y - Kc * u.y);   // read back by this thread only
+                const double2 q = make_double2(pv.x - Kc * u.x, pv.y - Kc * u.y);
+                qp[r] = q;   // read back by this thread only
+                // the update D -= [u_r q_r] [q_c u_c]^H as 16x16x4 products: lane (k, c) supplies
+                // A[c][k] = (u.x, u.y, q.x, q.y)[k] of row c (and A'[c][k] = (u.y, -u.x, q.y, -q.x)[k]
+                // for the imaginary part) and B[k][c] = (q.x, q.y, u.x, u.y)[k] of column c
+                const int o = (r >> 4) * 64 + (r & 15);
+                opA[o] = make_double2(-u.x, -u.y);
+                opA[o + 16] = make_double2(-u.y, u.x);
+                opA[o + 32] = make_double2(-q.x, -q.y);
+                opA[o + 48] = make_double2(-q.y, q.x);
+                opB[o] = q.x;
+                opB[o + 16] = q.y;
+                opB[o + 32] = u.x;
+                opB[o + 48] = u.y;
             }
             finish_and_reflect(j, refl, qj);
         }
