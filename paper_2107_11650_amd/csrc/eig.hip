@@ -732,6 +732,317 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same reduction with the matrix held in FP32 (the mixed form's forward
+// iterations, whose Gram matrices come from FP32 products).  Half the registers
+// per matrix let two workgroups of 384 threads share a compute unit, so that the
+// serial part of one matrix's step (the gather, the two reductions over all
+// threads and the reflector) overlaps the block products of the other's.  Blocks
+// sit in the accumulator layout of the FP32 matrix cores (lane l holds column
+// J*16 + l%16, rows I*16 + 4(l/16) + r, r = 0..3); the update is two 16x16x4
+// FP32 MFMAs per block with the operands of the FP64 form.  Scalars (norms, h,
+// u^H p, q, the finished column) are formed in FP64 from the FP32 sums; the
+// reflector is rounded to FP32 once, and the rounded vector is both the one the
+// matrix is updated with and the one written out.  Outputs as k_tridiag_rr.
+// ---------------------------------------------------------------------------
+constexpr int RR32_THREADS = 512;
+constexpr int RR32_WAVES = RR32_THREADS / 64;
+
+template <int CTRL>
+__device__ inline float dpp_move_f(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+// colsum4_pair for single precision: lanes of rows 0 and 2 end with the sum of x over the
+// four rows of 16 lanes, lanes of rows 1 and 3 with the sum of y
+__device__ inline float colsum4_pair_f(float x, float y) {
+    const auto a = __builtin_amdgcn_permlane16_swap((unsigned)__float_as_int(x), (unsigned)__float_as_int(y),
+                                                    false, false);
+    const float c = __int_as_float((int)a[0]) + __int_as_float((int)a[1]);
+    const auto b = __builtin_amdgcn_permlane32_swap((unsigned)__float_as_int(c), (unsigned)__float_as_int(c),
+                                                    false, false);
+    return __int_as_float((int)b[0]) + __int_as_float((int)b[1]);
+}
+
+template <int MAXB>
+__global__ __launch_bounds__(RR32_THREADS, 4) void k_tridiag_rr32(const LRDesc* __restrict__ descs, int m0,
+                                                                  double2* __restrict__ Gs, int64_t g_stride,
+                                                                  double* __restrict__ scr, int64_t scr_stride) {
+    constexpr int RR_SP = ((RR_MAXS + 15) / 16) * 16;
+    constexpr int RR_NB = RR_SP / 16, RR_NBLK = RR_NB * (RR_NB + 1) / 2;
+    __shared__ float2 opA[RR_NB * 64];              // update operands in lane order (negated), as above
+    __shared__ float opB[RR_NB * 64];
+    __shared__ double2 qp[RR_SP];                   // pending q, read back by the thread that wrote it
+    __shared__ float2 uc[RR_SP];                    // current reflector (FP32-rounded)
+    __shared__ double2 xraw[RR_SP];                 // captured column i+1
+    __shared__ float2 yrow[RR_NBLK * 16];           // [block][16] row partials
+    __shared__ float2 ycol[RR_NBLK * 16];           // [block][16] column partials
+    __shared__ double2 salpha[2];
+    __shared__ double red[2 * RR32_WAVES];
+    __shared__ double rh[2];
+    __shared__ int rrefl;
+    const LRDesc dsc = descs[m0 + blockIdx.x];
+    const int s = lr_s(dsc);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nb = (s + 15) >> 4, sp = nb * 16;
+    const int nblk = nb * (nb + 1) / 2;
+    double2* A = Gs + (int64_t)blockIdx.x * g_stride;
+    double* tri = scr + (int64_t)blockIdx.x * scr_stride;   // diag | off re | off im | h
+    double* tdd = tri;
+    double* ter = tri + s;
+    double* tei = tri + 2 * s;
+    double* thv = tri + 3 * s;
+
+    int bI[MAXB], bJ[MAXB];
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+        int b = wave + RR32_WAVES * t, J = 0;
+        while (J < nb && b >= nb - J) {
+            b -= nb - J;
+            ++J;
+        }
+        bJ[t] = J;
+        bI[t] = J + b;
+    }
+    floatx4 ar_[MAXB], ai_[MAXB];
+    {
+        const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+        for (int t = 0; t < MAXB; ++t) {
+            const bool has = wave + RR32_WAVES * t < nblk;
+            const int c = bJ[t] * 16 + lr;
+            // branch-free: every lane loads a valid entry (the upper triangle as the conjugate of
+            // the lower one), and entries outside the matrix are zeroed after the load
+            double2 v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = bI[t] * 16 + 4 * lg + q;
+                const bool ok = has && r < s && c < s;
+                v[q] = A[ok ? pk(max(r, c), min(r, c), s) : 0];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = bI[t] * 16 + 4 * lg + q;
+                const bool ok = has && r < s && c < s;
+                ar_[t][q] = ok ? (float)v[q].x : 0.f;
+                ai_[t][q] = ok ? (r >= c ? (float)v[q].y : -(float)v[q].y) : 0.f;
+            }
+            // one block of FP64 loads in flight at a time, so that the load results fit in registers
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int e = tid; e < sp; e += RR32_THREADS) {
+            qp[e] = make_double2(0.0, 0.0);
+            uc[e] = make_float2(0.f, 0.f);
+        }
+        for (int e = tid; e < nb * 64; e += RR32_THREADS) {
+            opA[e] = make_float2(0.f, 0.f);
+            opB[e] = 0.f;
+        }
+#pragma unroll
+        for (int t = 0; t < MAXB; ++t) {
+            if (wave + RR32_WAVES * t < nblk && bJ[t] == 0 && lr == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = bI[t] * 16 + 4 * lg + q;
+                    if (r < s) xraw[r] = make_double2(ar_[t][q], ai_[t][q]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    auto tid_now = [&]() {
+        int ln;
+        asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+        return wave * 64 + ln;
+    };
+    // column j minus the update of step j-1, its diagonal entry, and the reflector of column j
+    auto finish_and_reflect = [&](int j, bool pending, double2 q_j) {
+        const int tl = tid_now();
+        const int r = j + tl;
+        double tail = 0;
+        if (r < s) {
+            double2 v = xraw[r];
+            if (pending) {
+                const float2 u0f = uc[j], urf = uc[r];
+                const double2 u0 = make_double2(u0f.x, u0f.y), ur = make_double2(urf.x, urf.y);
+                const double2 qr = qp[r];
+                v.x -= qr.x * u0.x + qr.y * u0.y + ur.x * q_j.x + ur.y * q_j.y;
+                v.y -= qr.y * u0.x - qr.x * u0.y + ur.y * q_j.x - ur.x * q_j.y;
+            }
+            xraw[r] = v;
+            if (r == j) tdd[j] = v.x;
+            if (r == j + 1) salpha[0] = v;
+            if (r > j + 1) tail = cabs2(v);
+        }
+        tail = wave_sum_to63(tail);
+        if ((tl & 63) == 63) red[RR32_WAVES + wave] = tail;
+        __syncthreads();
+        if (j + 1 >= s) return;
+        tail = 0;
+        for (int w = 0; w < RR32_WAVES; ++w) tail += red[RR32_WAVES + w];
+        const double2 al = salpha[0];
+        const bool refl = tail > 0.0;
+        double hh = 1.0, xn = 0.0;
+        double2 ph = make_double2(1.0, 0.0);
+        if (refl) {
+            const double aabs = sqrt(al.x * al.x + al.y * al.y);
+            xn = sqrt(aabs * aabs + tail);
+            if (aabs > 0) ph = make_double2(al.x / aabs, al.y / aabs);
+            hh = xn * xn + aabs * xn;
+        }
+        if (tl == 0) {
+            ter[j] = refl ? -ph.x * xn : al.x;
+            tei[j] = refl ? -ph.y * xn : al.y;
+            thv[j] = refl ? hh : 0.0;
+        }
+        if (r == j) uc[j] = make_float2(0.f, 0.f);
+        if (r > j && r < s) {
+            float2 u = make_float2(0.f, 0.f);
+            if (refl) {
+                const double2 ud = (r == j + 1) ? make_double2(al.x + ph.x * xn, al.y + ph.y * xn) : xraw[r];
+                u = make_float2((float)ud.x, (float)ud.y);
+                A[pk(r, j, s)] = make_double2(u.x, u.y);
+            }
+            uc[r] = u;
+        }
+        if (tl == 0) {
+            rh[0] = hh;
+            rh[1] = 1.0 / hh;
+            rrefl = refl;
+        }
+    };
+
+    finish_and_reflect(0, false, make_double2(0.0, 0.0));
+    __syncthreads();
+
+    for (int i = 0; i + 1 < s; ++i) {
+        const int jlo = (i + 1) >> 4;
+        const bool pend = i > 0;
+#pragma unroll
+        for (int t = 0; t < MAXB; ++t) {
+            int b = wave + RR32_WAVES * t;
+            if (b >= nblk || bJ[t] < jlo) continue;   // uniform over the wave
+            int I = bI[t], J = bJ[t];
+            asm volatile("" : "+s"(I), "+s"(J), "+s"(b));
+            int ln;
+            asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+            const int lr = ln & 15, lg = ln >> 4;
+            if (pend) {
+                const float2 a = opA[I * 64 + ln];
+                const float bq = opB[J * 64 + ln];
+                ar_[t] = mfma16(a.x, bq, ar_[t]);
+                ai_[t] = mfma16(a.y, bq, ai_[t]);
+            }
+            const int cc = i + 1 - J * 16;
+            if (cc >= 0 && cc < 16 && lr == cc) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = I * 16 + 4 * lg + q;
+                    if (r > i && r < s) xraw[r] = make_double2(ar_[t][q], ai_[t][q]);
+                }
+            }
+            // column partials conj(A)^T u: in-lane over the lane's four rows, then across the
+            // four rows of lanes (real part to row 0 of lanes, imaginary part to row 1)
+            const float2 uC = uc[J * 16 + lr];
+            float ycx = 0.f, ycy = 0.f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float2 uR = uc[I * 16 + 4 * lg + q];
+                ycx = fmaf(ar_[t][q], uR.x, fmaf(ai_[t][q], uR.y, ycx));
+                ycy = fmaf(ar_[t][q], uR.y, fmaf(-ai_[t][q], uR.x, ycy));
+            }
+            const float ycs = colsum4_pair_f(ycx, ycy);
+            float2* ydst = I == J ? yrow : ycol;
+            if (lg < 2) reinterpret_cast<float*>(ydst + b * 16 + lr)[lg] = ycs;
+            if (I != J) {
+                // row partials A u_C over the 16 lanes of each row of lanes, reduce-scatter: lanes
+                // exchange with lane ^ 8 (rotate by 8), then with the mirror lane in each half,
+                // then within quads; lane l ends with row 4(l/16) + (l%16)/4
+                float2 y[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) y[q] = cmul(make_float2(ar_[t][q], ai_[t][q]), uC);
+                const bool hi8 = (lr & 8) != 0, hi4 = (lr & 4) != 0;
+                const float2 sA = hi8 ? y[0] : y[2], sB = hi8 ? y[1] : y[3];
+                float2 kA = hi8 ? y[2] : y[0], kB = hi8 ? y[3] : y[1];
+                kA.x += dpp_move_f<0x128>(sA.x);
+                kA.y += dpp_move_f<0x128>(sA.y);
+                kB.x += dpp_move_f<0x128>(sB.x);
+                kB.y += dpp_move_f<0x128>(sB.y);
+                const float2 s2 = hi4 ? kA : kB;
+                float2 k2 = hi4 ? kB : kA;
+                k2.x += dpp_move_f<0x141>(s2.x);
+                k2.y += dpp_move_f<0x141>(s2.y);
+                k2.x += dpp_move_f<0xB1>(k2.x);
+                k2.y += dpp_move_f<0xB1>(k2.y);
+                k2.x += dpp_move_f<0x4E>(k2.x);
+                k2.y += dpp_move_f<0x4E>(k2.y);
+                if ((lr & 3) == 0) yrow[b * 16 + 4 * lg + (lr >> 2)] = k2;
+            }
+        }
+        __syncthreads();
+        {
+            const int j = i + 1;
+            const int tl = tid_now();
+            const int r = j + tl;
+            const bool refl = rrefl != 0;
+            const double hh = rh[0], ihh = rh[1];
+            double2 pv = make_double2(0.0, 0.0);
+            double uhp = 0;
+            if (r < s && refl) {
+                const int I = r >> 4, rr = r & 15;
+                float2 acc = make_float2(0.f, 0.f);
+#pragma unroll 4
+                for (int J = jlo; J <= I; ++J) {
+                    const float2 v = yrow[rr_bidx(I, J, nb) * 16 + rr];
+                    acc.x += v.x;
+                    acc.y += v.y;
+                }
+#pragma unroll 4
+                for (int I2 = I + 1; I2 < nb; ++I2) {
+                    const float2 v = ycol[rr_bidx(I2, I, nb) * 16 + rr];
+                    acc.x += v.x;
+                    acc.y += v.y;
+                }
+                pv = make_double2(acc.x * ihh, acc.y * ihh);
+                const float2 u = uc[r];
+                uhp = u.x * pv.x + u.y * pv.y;
+                if (r == j) salpha[1] = pv;
+            }
+            uhp = wave_sum_to63(uhp);
+            if ((tl & 63) == 63) red[wave] = uhp;
+            __syncthreads();
+            uhp = 0;
+            for (int w = 0; w < RR32_WAVES; ++w) uhp += red[w];
+            const double Kc = 0.5 * uhp * ihh;
+            double2 qj = make_double2(0.0, 0.0);
+            if (refl) {
+                const double2 pj = salpha[1];
+                const float2 uj = uc[j];
+                qj = make_double2(pj.x - Kc * uj.x, pj.y - Kc * uj.y);
+            }
+            if (r < s) {
+                const float2 uf = refl ? uc[r] : make_float2(0.f, 0.f);
+                const double2 u = make_double2(uf.x, uf.y);
+                const double2 q = make_double2(pv.x - Kc * u.x, pv.y - Kc * u.y);
+                qp[r] = q;
+                const float qx = (float)q.x, qy = (float)q.y;
+                const int o = (r >> 4) * 64 + (r & 15);
+                opA[o] = make_float2(-uf.x, -uf.y);
+                opA[o + 16] = make_float2(-uf.y, uf.x);
+                opA[o + 32] = make_float2(-qx, -qy);
+                opA[o + 48] = make_float2(-qy, qx);
+                opB[o] = qx;
+                opB[o + 16] = qy;
+                opB[o + 32] = uf.x;
+                opB[o + 48] = uf.y;
+            }
+            finish_and_reflect(j, refl, qj);
+        }
+        __syncthreads();
+    }
+}
+
 template <typename OC, int SL>
 __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const LRDesc* __restrict__ descs, int m0,
                                                              double2* __restrict__ Gs, int64_t g_stride,
@@ -1579,17 +1890,25 @@ static size_t heig_lds_bytes(int smax) {
 bool tridiag_rr_supported(int smax) { return smax >= 2 && smax <= RR_MAXS; }
 
 hipError_t launch_tridiag_rr(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
-                             double* scr, int64_t scr_stride, int smax) {
+                             double* scr, int64_t scr_stride, int smax, bool fp32) {
     if (!tridiag_rr_supported(smax)) return hipErrorInvalidValue;
-    const int nb = (smax + 15) / 16, nblk = nb * (nb + 1) / 2;
-    // blocks per wave: ceil(nblk / RR_WAVES)
-    const void* fn = nb <= 6 ? (const void*)k_tridiag_rr<2>
-                   : nb <= 8 ? (const void*)k_tridiag_rr<3>
-                   : nb <= 10 ? (const void*)k_tridiag_rr<5>
-                   : nb <= 12 ? (const void*)k_tridiag_rr<7>
-                              : (const void*)k_tridiag_rr<8>;
+    const int nb = (smax + 15) / 16;
+    // blocks per wave: ceil(nb (nb + 1) / 2 / waves)
+    const void* fn;
+    if (fp32)
+        fn = nb <= 6 ? (const void*)k_tridiag_rr32<3>
+           : nb <= 8 ? (const void*)k_tridiag_rr32<5>
+           : nb <= 10 ? (const void*)k_tridiag_rr32<7>
+           : nb <= 12 ? (const void*)k_tridiag_rr32<10>
+                      : (const void*)k_tridiag_rr32<12>;
+    else
+        fn = nb <= 6 ? (const void*)k_tridiag_rr<2>
+           : nb <= 8 ? (const void*)k_tridiag_rr<3>
+           : nb <= 10 ? (const void*)k_tridiag_rr<5>
+           : nb <= 12 ? (const void*)k_tridiag_rr<7>
+                      : (const void*)k_tridiag_rr<8>;
     void* args[] = {(void*)&descs, (void*)&m0, (void*)&Gs, (void*)&g_stride, (void*)&scr, (void*)&scr_stride};
-    hipError_t e = hipLaunchKernel(fn, dim3(count), dim3(RR_THREADS), args, 0, st);
+    hipError_t e = hipLaunchKernel(fn, dim3(count), dim3(fp32 ? RR32_THREADS : RR_THREADS), args, 0, st);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }

@@ -696,7 +696,7 @@ static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_
             if (rr) {
                 STCHK(phase_begin(P, &e0));
                 HIPCHK(launch_tridiag_rr(P->stream, desc_dev, c0, c1 - c0, G, run.g_stride, scr, run.scr_stride,
-                                         run.smax));
+                                         run.smax, sizeof(R) == 4));
                 STCHK(phase_end(P, 5, e0));
             }
             STCHK(phase_begin(P, &e0));
