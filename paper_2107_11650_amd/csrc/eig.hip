@@ -393,16 +393,16 @@ __device__ __attribute__((always_inline)) void backtransform_wy(double2* __restr
 
 // ---------------------------------------------------------------------------
 // Register-resident Householder tridiagonalisation (orders s <= RR_MAXS).
-// One workgroup of 512 threads holds the Hermitian matrix in registers as the
+// One workgroup of 768 threads holds the Hermitian matrix in registers as the
 // 16 x 16 blocks (I, J), I >= J, of its lower triangle (diagonal blocks held
-// in full): wave w owns blocks w, w + 8, ... in column-major block order, in
+// in full): wave w owns blocks w, w + 12, ... in column-major block order, in
 // the accumulator layout of the FP64 matrix cores (lane l holds column
 // J*16 + l%16, rows I*16 + l/16 + 4q, q = 0..3).  Step i:
 //  (a) every wave applies the pending rank-2 update of step i-1 to its live
 //      blocks as two 16x16x4 MFMAs per block ([u q] times [q u]^H), captures
 //      column i+1, and forms the products with u_i: column partials (in-lane,
 //      then across the four rows of lanes) and, in off-diagonal blocks, row
-//      partials (reduced over 16 lanes);
+//      partials (transposed through a per-wave LDS tile, summed by quads);
 //  (b) one thread per row gathers p = A u_i / h_i in a fixed block order;
 //      then q = p - (u^H p / 2h) u, column i+1 finished with the update of
 //      step i, and the reflector of step i+1.
@@ -735,7 +735,8 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
 // ---------------------------------------------------------------------------
 // The same reduction with the matrix held in FP32 (the mixed form's forward
 // iterations, whose Gram matrices come from FP32 products).  Half the registers
-// per matrix let two workgroups of 384 threads share a compute unit, so that the
+// per matrix let two workgroups of 512 threads share a compute unit (at most 128
+// registers per thread: four waves per SIMD, two of each workgroup), so that the
 // serial part of one matrix's step (the gather, the two reductions over all
 // threads and the reflector) overlaps the block products of the other's.  Blocks
 // sit in the accumulator layout of the FP32 matrix cores (lane l holds column
@@ -811,21 +812,28 @@ __global__ __launch_bounds__(RR32_THREADS, 4) void k_tridiag_rr32(const LRDesc* 
         for (int t = 0; t < MAXB; ++t) {
             const bool has = wave + RR32_WAVES * t < nblk;
             const int c = bJ[t] * 16 + lr;
-            // branch-free: every lane loads a valid entry (the upper triangle as the conjugate of
-            // the lower one), and entries outside the matrix are zeroed after the load
+            // branch-free with 32-bit packed indices (orders up to RR_MAXS): every lane loads a
+            // valid entry (the upper triangle as the conjugate of the lower one), and entries
+            // outside the matrix are zeroed after the load
             double2 v[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int r = bI[t] * 16 + 4 * lg + q;
-                const bool ok = has && r < s && c < s;
-                v[q] = A[ok ? pk(max(r, c), min(r, c), s) : 0];
+                const int hi = max(r, c), lo = min(r, c);
+                const bool ok = has && hi < s;
+                const int e = (int)((unsigned)(lo * (2 * s - lo - 1)) >> 1) + hi;
+                v[q] = A[ok ? e : 0];
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int r = bI[t] * 16 + 4 * lg + q;
                 const bool ok = has && r < s && c < s;
-                ar_[t][q] = ok ? (float)v[q].x : 0.f;
-                ai_[t][q] = ok ? (r >= c ? (float)v[q].y : -(float)v[q].y) : 0.f;
+                float xr = ok ? (float)v[q].x : 0.f;
+                float xi = ok ? (r >= c ? (float)v[q].y : -(float)v[q].y) : 0.f;
+                // converted here, so that no FP64 load result stays live until the step loop
+                asm volatile("" : "+v"(xr), "+v"(xi));
+                ar_[t][q] = xr;
+                ai_[t][q] = xi;
             }
             // one block of FP64 loads in flight at a time, so that the load results fit in registers
             __builtin_amdgcn_sched_barrier(0);
