@@ -73,6 +73,9 @@ LR_CASES = [
     (6, 2, 23, 23, False, True),      # 1 x 46: single-row lifts
     (5, 3, 16, 1, False, True),       # k = 1: the coil matrix
     (4, 8, 256, 25, False, True),     # 232 x 200: the 8-coil 256 x 256 row lifts
+    (3, 4, 128, 32, False, True),     # 97 x 128: order 97 (register-resident reduction, 7 block rows)
+    (3, 5, 200, 30, False, True),     # 171 x 150: order 150 (10 block rows)
+    (3, 6, 240, 30, False, True),     # 211 x 180: order 180 (12 block rows)
     (3, 12, 256, 25, True, True),     # 232 x 600: 12-coil virtual-coil PE lifts
     (3, 6, 320, 45, False, True),     # 276 x 270: order above 256 (five 64-row slabs, in-memory reduction)
 ]
