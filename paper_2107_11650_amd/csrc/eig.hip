@@ -1421,17 +1421,59 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
     // gamma_i = D+_i + D-_i - (d_i - lk) is smallest at the twist r, and
     // z_r = 1, z_i = -L_i z_{i+1} (i < r), z_{i+1} = -U_i z_i (i >= r) solves
     // (T - lk I) z = gamma_r e_r, with L_i = e_i / D+_i and U_i = e_i / D-_{i+1}.
-    // Eigenvalues closer than ortol form a cluster handled by one thread: each
-    // later member is refined by two steps of inverse iteration with the
-    // L D+ L^T factors, each followed by modified Gram-Schmidt against the
-    // earlier members.  D+ and U of each thread of a batch live in LDS region A
-    // (2 s + 1 doubles, odd stride against bank conflicts); z is formed in place
-    // in its column of W.
+    // Eigenvalues closer than ortol form a cluster.  The first member of every
+    // cluster and every single eigenvalue get their vector in parallel, one
+    // thread each; D+ and U of each thread of a batch live in LDS region A
+    // (2 s + 1 doubles, odd stride against bank conflicts), and z is formed in
+    // place in its column of W.  The later members of a cluster follow one at a
+    // time, with the whole block: thread 0 forms the twisted vector (at an
+    // eigenvalue moved at least a few ulps above the previous member's) and the
+    // two inverse-iteration solves with the L D+ L^T factors, in LDS; all threads
+    // share the scaling and, after each solve, a classical Gram-Schmidt pass
+    // repeated twice against the earlier members of the cluster (columns of W).
     const double ortol = ortol_rel * tnorm;
     {
         double* wsd = reinterpret_cast<double*>(stage);
         const int wstride = 2 * s + 1;
         const int cap = max(1, (EIG_STAGE * smax * 2) / wstride);
+        // the twisted-factorisation vector of eigenvalue lk into z (factors in Dp, Uf)
+        auto twisted = [&](double lk, double* z, double* Dp, double* Uf) {
+            double dp = sdd[0] - lk;
+            for (int i = 0; i + 1 < s; ++i) {
+                if (fabs(dp) < pivmin) dp = -pivmin;
+                Dp[i] = dp;
+                const double e = see[i];
+                dp = sdd[i + 1] - lk - e * e * rcp_nr(dp);
+            }
+            if (fabs(dp) < pivmin) dp = -pivmin;
+            Dp[s - 1] = dp;
+            double dm = sdd[s - 1] - lk;
+            int twist = s - 1;
+            double gbest = fabs(Dp[s - 1]);
+            for (int i = s - 2; i >= 0; --i) {
+                if (fabs(dm) < pivmin) dm = -pivmin;
+                const double e = see[i];
+                const double u = e * rcp_nr(dm);
+                Uf[i] = u;
+                dm = sdd[i] - lk - u * e;
+                const double g = fabs(Dp[i] + dm - (sdd[i] - lk));
+                if (g < gbest) {
+                    gbest = g;
+                    twist = i;
+                }
+            }
+            double zc = 1.0;
+            z[twist] = 1.0;
+            for (int i = twist - 1; i >= 0; --i) {
+                zc = -see[i] * rcp_nr(Dp[i]) * zc;
+                z[i] = zc;
+            }
+            zc = 1.0;
+            for (int i = twist; i + 1 < s; ++i) {
+                zc = -Uf[i] * zc;
+                z[i + 1] = zc;
+            }
+        };
         int nlead = 0;
         for (int k = 0; k < nabove; ++k) nlead += (k == 0 || slam[k] - slam[k - 1] > ortol);
         const bool leader = tid < nabove && (tid == 0 || slam[tid] - slam[tid - 1] > ortol);
@@ -1441,97 +1483,94 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
         for (int r0 = 0; r0 < nlead; r0 += cap) {
             if (leader && rank >= r0 && rank < r0 + cap) {
                 double* Dp = wsd + (int64_t)(rank - r0) * wstride;
-                double* Uf = Dp + s;
-                int kend = tid + 1;
-                while (kend < nabove && slam[kend] - slam[kend - 1] <= ortol) ++kend;
-                double prev = 0;
-                for (int k = tid; k < kend; ++k) {
-                    double* z = W + (int64_t)k * s;   // column k of W (column-major)
-                    double lk = slam[k];
-                    if (k > tid) {
-                        const double pertol = 10.0 * DBL_EPSILON * fmax(fabs(lk), tnorm * 1e-3);
-                        if (lk - prev < pertol) lk = prev + pertol;
-                    }
-                    prev = lk;
-                    // forward: D+
-                    double dp = sdd[0] - lk;
-                    for (int i = 0; i + 1 < s; ++i) {
-                        if (fabs(dp) < pivmin) dp = -pivmin;
-                        Dp[i] = dp;
-                        const double e = see[i];
-                        dp = sdd[i + 1] - lk - e * e * rcp_nr(dp);
-                    }
-                    if (fabs(dp) < pivmin) dp = -pivmin;
-                    Dp[s - 1] = dp;
-                    // backward: D-, U and the twist
-                    double dm = sdd[s - 1] - lk;
-                    int twist = s - 1;
-                    double gbest = fabs(Dp[s - 1]);
-                    for (int i = s - 2; i >= 0; --i) {
-                        if (fabs(dm) < pivmin) dm = -pivmin;
-                        const double e = see[i];
-                        const double u = e * rcp_nr(dm);
-                        Uf[i] = u;
-                        dm = sdd[i] - lk - u * e;
-                        const double g = fabs(Dp[i] + dm - (sdd[i] - lk));
-                        if (g < gbest) {
-                            gbest = g;
-                            twist = i;
-                        }
-                    }
-                    double zc = 1.0;
-                    z[twist] = 1.0;
-                    for (int i = twist - 1; i >= 0; --i) {
-                        zc = -see[i] * rcp_nr(Dp[i]) * zc;
-                        z[i] = zc;
-                    }
-                    zc = 1.0;
-                    for (int i = twist; i + 1 < s; ++i) {
-                        zc = -Uf[i] * zc;
-                        z[i + 1] = zc;
-                    }
-                    // a single eigenvector is normalised by the whole block below; in a cluster
-                    // every member is normalised here before the next one is orthogonalised
-                    if (kend == tid + 1) break;
-                    const int nref = k > tid ? 2 : 0;
-                    for (int it = 0; it <= nref; ++it) {
-                        if (it > 0) {
-                            // z <- (L D+ L^T)^{-1} z
-                            double zp = z[0];
-                            for (int i = 0; i + 1 < s; ++i) {
-                                const double zn = z[i + 1] - see[i] * rcp_nr(Dp[i]) * zp;
-                                z[i + 1] = zn;
-                                zp = zn;
-                            }
-                            for (int i = 0; i < s; ++i) z[i] /= Dp[i];
-                            zp = z[s - 1];
-                            for (int i = s - 2; i >= 0; --i) {
-                                const double zn = z[i] - see[i] * rcp_nr(Dp[i]) * zp;
-                                z[i] = zn;
-                                zp = zn;
-                            }
-                        }
-                        double amax = 0;
-                        for (int i = 0; i < s; ++i) amax = fmax(amax, fabs(z[i]));
-                        if (!(amax > 0) || !(amax < DBL_MAX)) {
-                            for (int i = 0; i < s; ++i) z[i] = start_entry(i, k + it + 1);
-                            amax = 1.0;
-                        }
-                        const double ia = 1.0 / amax;
-                        for (int i = 0; i < s; ++i) z[i] *= ia;
-                        for (int k2 = tid; k2 < k; ++k2) {
-                            double dot = 0;
-                            for (int i = 0; i < s; ++i) dot += W[(int64_t)k2 * s + i] * z[i];
-                            for (int i = 0; i < s; ++i) z[i] -= dot * W[(int64_t)k2 * s + i];
-                        }
-                        double nrm = 0;
-                        for (int i = 0; i < s; ++i) nrm += z[i] * z[i];
-                        nrm = nrm > 0 ? 1.0 / sqrt(nrm) : 0.0;
-                        for (int i = 0; i < s; ++i) z[i] *= nrm;
-                    }
-                }
+                twisted(slam[tid], W + (int64_t)tid * s, Dp, Dp + s);
             }
             __syncthreads();
+        }
+        if (nlead < nabove) {   // uniform: some eigenvalues are clustered
+            double* Dp = wsd;
+            double* Uf = Dp + s;
+            double* zb = Uf + s + 1;   // the member being formed
+            double* dts = zb + s;      // its projections on the earlier members
+            // z <- z / max|z| (a zero or non-finite z is replaced by a start vector), then
+            // z <- z / ||z||, over the block; every thread calls these
+            auto scale_max = [&](double* z, int seed) {
+                double m = block_max(tid < s ? fabs(z[tid]) : 0.0, red);
+                if (!(m > 0) || !(m < DBL_MAX)) {
+                    if (tid < s) z[tid] = start_entry(tid, seed);
+                    m = block_max(tid < s ? fabs(z[tid]) : 0.0, red);
+                }
+                if (tid < s) z[tid] *= 1.0 / m;
+                __syncthreads();
+            };
+            auto scale_unit = [&](double* z) {
+                const double n2 = block_sum(tid < s ? z[tid] * z[tid] : 0.0, red);
+                if (tid < s) z[tid] *= n2 > 0 ? 1.0 / sqrt(n2) : 0.0;
+                __syncthreads();
+            };
+            int lead = 0;
+            double prev = 0;
+            for (int k = 1; k < nabove; ++k) {   // uniform
+                if (slam[k] - slam[k - 1] > ortol) {
+                    lead = k;
+                    continue;
+                }
+                if (k - 1 == lead) {
+                    // the cluster's first member, formed above, is made a unit vector first
+                    double* zl = W + (int64_t)lead * s;
+                    scale_max(zl, lead + 1);
+                    scale_unit(zl);
+                    prev = slam[lead];
+                }
+                double lk = slam[k];
+                const double pertol = 10.0 * DBL_EPSILON * fmax(fabs(lk), tnorm * 1e-3);
+                if (lk - prev < pertol) lk = prev + pertol;
+                prev = lk;
+                if (tid == 0) twisted(lk, zb, Dp, Uf);
+                __syncthreads();
+                for (int it = 0; it <= 2; ++it) {
+                    if (it > 0) {
+                        if (tid == 0) {
+                            // z <- (L D+ L^T)^{-1} z
+                            double zp = zb[0];
+                            for (int i = 0; i + 1 < s; ++i) {
+                                const double zn = zb[i + 1] - see[i] * rcp_nr(Dp[i]) * zp;
+                                zb[i + 1] = zn;
+                                zp = zn;
+                            }
+                            for (int i = 0; i < s; ++i) zb[i] /= Dp[i];
+                            zp = zb[s - 1];
+                            for (int i = s - 2; i >= 0; --i) {
+                                const double zn = zb[i] - see[i] * rcp_nr(Dp[i]) * zp;
+                                zb[i] = zn;
+                                zp = zn;
+                            }
+                        }
+                        __syncthreads();
+                    }
+                    scale_max(zb, k + it + 1);
+                    for (int pass = 0; pass < 2; ++pass) {
+                        // projections on columns lead .. k-1: one wave per column, lanes over rows
+                        for (int j = lead + wave; j < k; j += nw) {
+                            const double* wj = W + (int64_t)j * s;
+                            double d = 0;
+                            for (int i = lane; i < s; i += 64) d += wj[i] * zb[i];
+                            d = wave_sum_all(d);
+                            if (lane == 0) dts[j - lead] = d;
+                        }
+                        __syncthreads();
+                        if (tid < s) {
+                            double z = zb[tid];
+                            for (int j = lead; j < k; ++j) z -= dts[j - lead] * W[(int64_t)j * s + tid];
+                            zb[tid] = z;
+                        }
+                        __syncthreads();
+                    }
+                    scale_unit(zb);
+                }
+                if (tid < s) W[(int64_t)k * s + tid] = zb[tid];
+                __syncthreads();
+            }
         }
     }
     // unit scale of every column of W, one wave per column with lanes over rows: 1 / (amax ||z / amax||);

@@ -113,6 +113,37 @@ def test_lowrank_step(case, prec):
     assert e_d < tol and e_b < tol
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lowrank_step_clustered(prec):
+    """Lifted matrices with repeated and nearly repeated singular values above the threshold: the
+    eigenvectors of such clusters are formed member by member and orthogonalised."""
+    shlr = _lib()
+    B, J, n, k, beta, tau = 3, 4, 64, 8, 3.0, 2.0
+    lift = O.LineLift(n, k, True, False)
+    p, q = lift.p, lift.q(J)
+    h = inputs.random_complex((B, J, n), seed=31, scale=0.1)
+    base = np.array([8.0, 8.0 * (1 + 1e-13), 8.0 * (1 + 3e-13), 8.0 * (1 + 1e-9), 6.0, 4.0, 4.0 * (1 + 1e-14),
+                     4.0, 4.0 * (1 - 2e-12), 3.0, 2.5, 2.0])
+    sig = np.concatenate([base, np.linspace(1.2, 0.05, min(p, q) - len(base))])
+    T = np.empty((B, p, q), dtype=np.complex128)
+    for m in range(B):
+        U, _ = np.linalg.qr(inputs.random_complex((p, p), seed=40 + m))
+        V, _ = np.linalg.qr(inputs.random_complex((q, q), seed=50 + m))
+        T[m] = (U[:, :len(sig)] * sig) @ V[:, :len(sig)].conj().T
+    D = beta * (T - lift.forward(h))
+    thr = 1.5   # twelve singular values above it, with clusters of four at 8 and at 4
+    Dn_ref, b_ref = O.lowrank_step(lift, h, D, beta, tau, thr)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    Dd = dev(D, dt)
+    b, ranks = shlr.lowrank_lines(dev(h, dt), Dd, k, beta, tau, thr, ranks=True)
+    torch.cuda.synchronize()
+    e_d, e_b = nmse(host(Dd), Dn_ref), nmse(host(b), b_ref)
+    print(f"lowrank clustered {prec}: nmse D={e_d:.3e} b={e_b:.3e} ranks={ranks.cpu().numpy().tolist()}", flush=True)
+    assert ranks.cpu().numpy().tolist() == [int((sig > thr).sum())] * B
+    tol = 1e-20 if prec == "fp64" else 1e-5
+    assert e_d < tol and e_b < tol
+
+
 def test_lowrank_step_zero_and_full_threshold():
     shlr = _lib()
     B, J, n, k = 4, 4, 64, 8
