@@ -26,10 +26,17 @@ constexpr int EIG_MAXS = 320;                    // largest supported order
 constexpr int EIG_STAGE = 6 + EIG_THREADS / 64;  // smax-sized double2 rows of LDS region A (staging)
 
 // double2 entries of LDS region A: the staging rows, and at least one 16 x 16 tile per wave plus
-// one more for the blocked back-transform
+// one more for the blocked back-transform.  Beyond that it grows, up to 19 rows, while the
+// kernel's LDS stays within half a compute unit's (two workgroups per CU): the eigenvector step
+// keeps the factors of one eigenvalue per 2 s + 1 doubles of it, and more of them at once means
+// fewer sequential batches.
 __host__ __device__ inline int heig_region_a(int smax) {
     const int a = EIG_STAGE * smax, b = (EIG_THREADS / 64 + 1) * 256;
-    return a > b ? a : b;
+    const int rest = 9 * smax * 8 + (2 * (EIG_THREADS / 64) + 8) * 8;      // bytes after region A
+    const int half = (80 * 1024 - rest) / 16;                               // double2 entries
+    const int c = 19 * smax < half ? 19 * smax : half;
+    const int ab = a > b ? a : b;
+    return ab > c ? ab : c;
 }
 
 __device__ inline double block_sum(double v, double* red) {
@@ -1435,7 +1442,7 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
     {
         double* wsd = reinterpret_cast<double*>(stage);
         const int wstride = 2 * s + 1;
-        const int cap = max(1, (EIG_STAGE * smax * 2) / wstride);
+        const int cap = max(1, (heig_region_a(smax) * 2) / wstride);
         // the twisted-factorisation vector of eigenvalue lk into z (factors in Dp, Uf)
         auto twisted = [&](double lk, double* z, double* Dp, double* Uf) {
             double dp = sdd[0] - lk;
