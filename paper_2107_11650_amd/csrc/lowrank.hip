@@ -146,6 +146,81 @@ __device__ inline void stage_A_chunk(R* Ar, R* Ai, int ldA, const cplx_t<R>* U, 
     }
 }
 
+// Multiplier entries per thread that the Gram kernel keeps in flight for the next chunk, and
+// whether a launch does (FP32, tiles up to 16 per wave: the registers allow it there).
+constexpr int GRAM_NPF = 4;
+__host__ __device__ inline bool gram_prefetches(int rsize, int maxt, int KC, int s_pad) {
+    return rsize == 4 && maxt <= 16 && KC * s_pad <= GRAM_NPF * LR_THREADS;
+}
+
+// The same staging in two halves, so that the multiplier reads of the next chunk are in flight
+// while the current one is multiplied: prefetch_D_chunk loads this thread's D entries of a chunk
+// (at most NPF of them) into registers, stage_A_prefetched forms A from them.  Callers check
+// KC * s_pad <= NPF * nth.
+template <typename R, int NPF>
+__device__ inline void prefetch_D_chunk(cplx_t<R> (&dv)[NPF], const cplx_t<R>* Dm, const LRDesc& d, int r0, int KC,
+                                        int s_pad, int tid, int nth) {
+    const int p = lr_p(d), q = lr_q(d), side = lr_side(d);
+    const int s = side == 0 ? q : p;
+    const int l = side == 0 ? p : q;
+    const int total = KC * s_pad;
+#pragma unroll
+    for (int j = 0; j < NPF; ++j) {
+        const int e = tid + j * nth;
+        dv[j] = cplx_t<R>{0, 0};
+        if (e < total) {
+            if (side == 0) {
+                const int r = e / s_pad, cidx = e - r * s_pad, a = r0 + r;
+                if (a < l && cidx < s) dv[j] = Dm[(int64_t)a * q + cidx];
+            } else {
+                const int cidx = e / KC, r = e - cidx * KC, col = r0 + r;
+                if (col < l && cidx < s) dv[j] = Dm[(int64_t)cidx * q + col];
+            }
+        }
+    }
+}
+
+template <typename R, int NPF>
+__device__ inline void stage_A_prefetched(R* Ar, R* Ai, int ldA, const cplx_t<R>* U, const cplx_t<R> (&dv)[NPF],
+                                          const LRDesc& d, R inv_beta, int r0, int KC, int s_pad, int tid,
+                                          int nth) {
+    using C = cplx_t<R>;
+    const int p = lr_p(d), q = lr_q(d), side = lr_side(d);
+    const int s = side == 0 ? q : p;
+    const int l = side == 0 ? p : q;
+    const int total = KC * s_pad;
+    // the element indices are recomputed here rather than kept from the prefetch (registers)
+    int t0 = tid;
+    asm volatile("" : "+v"(t0));
+#pragma unroll
+    for (int j = 0; j < NPF; ++j) {
+        const int e = t0 + j * nth;
+        if (e < total) {
+            R re = 0, im = 0;
+            int r, cidx;
+            if (side == 0) {
+                r = e / s_pad;
+                cidx = e - r * s_pad;
+                if (r0 + r < l && cidx < s) {
+                    const C lv = lift_val(U, d.n, d.k, r0 + r, cidx);
+                    re = lv.x + dv[j].x * inv_beta;
+                    im = lv.y + dv[j].y * inv_beta;
+                }
+            } else {
+                cidx = e / KC;
+                r = e - cidx * KC;
+                if (r0 + r < l && cidx < s) {
+                    const C lv = lift_val(U, d.n, d.k, cidx, r0 + r);
+                    re = lv.x + dv[j].x * inv_beta;
+                    im = -(lv.y + dv[j].y * inv_beta);
+                }
+            }
+            Ar[r * ldA + cidx] = re;
+            Ai[r * ldA + cidx] = im;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_lift_gram
 //   grid.x: matrices of the chunk; grid.y: groups of 8 "units".
@@ -195,10 +270,21 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
     const C* Dm = db + d.d_off;
     const int li = lane & 15, lk = lane >> 4;
 
+    // the multiplier entries of the next chunk are loaded while the current one is multiplied
+    constexpr int NPF = GRAM_NPF;
+    const bool pf = gram_prefetches(sizeof(R), MAXT, KC, s_pad);   // uniform
+    C dv[NPF];
+    if (pf) prefetch_D_chunk<R, NPF>(dv, Dm, d, 0, KC, s_pad, tid, LR_THREADS);
     for (int r0 = 0; r0 < l; r0 += KC) {
         __syncthreads();
-        stage_A_chunk<R>(Ar, Ai, ldA, U, Dm, d, inv_beta, r0, KC, s_pad, tid, LR_THREADS);
-        __syncthreads();
+        if (pf) {
+            stage_A_prefetched<R, NPF>(Ar, Ai, ldA, U, dv, d, inv_beta, r0, KC, s_pad, tid, LR_THREADS);
+            __syncthreads();
+            if (r0 + KC < l) prefetch_D_chunk<R, NPF>(dv, Dm, d, r0 + KC, KC, s_pad, tid, LR_THREADS);
+        } else {
+            stage_A_chunk<R>(Ar, Ai, ldA, U, Dm, d, inv_beta, r0, KC, s_pad, tid, LR_THREADS);
+            __syncthreads();
+        }
         if (!active) continue;
         for (int kk = 0; kk < KC; kk += 4) {
             const int row = (kk + lk) * ldA + li;
@@ -781,7 +867,11 @@ hipError_t launch_lift_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>
     const int nt = (s + 15) / 16;
     const int n_units = (nt + 1) / 2;
     const int groups = (n_units + LR_WAVES - 1) / LR_WAVES;
-    int KC = (kc == 4 || kc == 8 || kc == 16 || kc == 32) ? kc : 16;   // rows of A staged per chunk
+    // rows of A staged per chunk; by default 16, or 8 where that lets the kernel prefetch
+    const int s_pad = nt * 16;
+    int KC = 16;
+    if (!gram_prefetches(sizeof(R), nt + 1, 16, s_pad) && gram_prefetches(sizeof(R), nt + 1, 8, s_pad)) KC = 8;
+    if (kc == 4 || kc == 8 || kc == 16 || kc == 32) KC = kc;
     while (KC > 4 && gram_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT) KC /= 2;
     if (gram_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT) return hipErrorInvalidValue;
     const size_t lds = gram_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC);
