@@ -106,7 +106,10 @@ __device__ inline void stage_chunk(R* Ar, R* Ai, int ldA, const cplx_t<R>* U, R 
     }
 }
 
-template <typename R>
+// UB entries per thread at a time: their multiplier reads are all issued before the first is
+// used, so that a chunk waits for HBM once per UB entries rather than once per entry (UB = 1
+// where the registers are needed elsewhere)
+template <typename R, int UB = 1>
 __device__ inline void stage_A_chunk(R* Ar, R* Ai, int ldA, const cplx_t<R>* U, const cplx_t<R>* Dm,
                                      const LRDesc& d, R inv_beta, int r0, int KC, int s_pad, int tid, int nth) {
     using C = cplx_t<R>;
@@ -114,34 +117,49 @@ __device__ inline void stage_A_chunk(R* Ar, R* Ai, int ldA, const cplx_t<R>* U, 
     const int s = side == 0 ? q : p;
     const int l = side == 0 ? p : q;
     const int total = KC * s_pad;
-    if (side == 0) {
-        for (int e = tid; e < total; e += nth) {
-            int r = e / s_pad, cidx = e - r * s_pad;
-            int a = r0 + r;
-            R re = 0, im = 0;
-            if (a < l && cidx < s) {
-                C dv = Dm[(int64_t)a * q + cidx];
-                C lv = lift_val(U, d.n, d.k, a, cidx);
-                re = lv.x + dv.x * inv_beta;
-                im = lv.y + dv.y * inv_beta;
+    for (int e0 = tid; e0 < total; e0 += UB * nth) {
+        C dv[UB];
+#pragma unroll
+        for (int j = 0; j < UB; ++j) {
+            const int e = e0 + j * nth;
+            dv[j] = C{0, 0};
+            if (e < total) {
+                if (side == 0) {
+                    const int r = e / s_pad, cidx = e - r * s_pad, a = r0 + r;
+                    if (a < l && cidx < s) dv[j] = Dm[(int64_t)a * q + cidx];
+                } else {
+                    // A[r][c] = conj(T[c][r]): rows of A are columns of T; read D with r fastest
+                    const int cidx = e / KC, r = e - cidx * KC, col = r0 + r;
+                    if (col < l && cidx < s) dv[j] = Dm[(int64_t)cidx * q + col];
+                }
             }
-            Ar[r * ldA + cidx] = re;
-            Ai[r * ldA + cidx] = im;
         }
-    } else {
-        // A[r][c] = conj(T[c][r]): rows of A are columns of T; read D with r fastest.
-        for (int e = tid; e < total; e += nth) {
-            int cidx = e / KC, r = e - cidx * KC;
-            int col = r0 + r;
-            R re = 0, im = 0;
-            if (col < l && cidx < s) {
-                C dv = Dm[(int64_t)cidx * q + col];
-                C lv = lift_val(U, d.n, d.k, cidx, col);
-                re = lv.x + dv.x * inv_beta;
-                im = -(lv.y + dv.y * inv_beta);
+#pragma unroll
+        for (int j = 0; j < UB; ++j) {
+            const int e = e0 + j * nth;
+            if (e < total) {
+                R re = 0, im = 0;
+                int r, cidx;
+                if (side == 0) {
+                    r = e / s_pad;
+                    cidx = e - r * s_pad;
+                    if (r0 + r < l && cidx < s) {
+                        const C lv = lift_val(U, d.n, d.k, r0 + r, cidx);
+                        re = lv.x + dv[j].x * inv_beta;
+                        im = lv.y + dv[j].y * inv_beta;
+                    }
+                } else {
+                    cidx = e / KC;
+                    r = e - cidx * KC;
+                    if (r0 + r < l && cidx < s) {
+                        const C lv = lift_val(U, d.n, d.k, cidx, r0 + r);
+                        re = lv.x + dv[j].x * inv_beta;
+                        im = -(lv.y + dv[j].y * inv_beta);
+                    }
+                }
+                Ar[r * ldA + cidx] = re;
+                Ai[r * ldA + cidx] = im;
             }
-            Ar[r * ldA + cidx] = re;
-            Ai[r * ldA + cidx] = im;
         }
     }
 }
@@ -405,7 +423,7 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
 
     for (int r0 = 0; r0 < l; r0 += KC) {
         __syncthreads();
-        stage_A_chunk<R>(Ar, Ai, ldA, U, Dm, d, inv_beta, r0, KC, s_pad, tid, LR_THREADS);
+        stage_A_chunk<R, 8>(Ar, Ai, ldA, U, Dm, d, inv_beta, r0, KC, s_pad, tid, LR_THREADS);
         __syncthreads();
         A4 accR[MAXT], accI[MAXT];
 #pragma unroll
