@@ -512,6 +512,19 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
             if (Jt < nt) {
                 const int It = It_w;
                 const int col = Jt * 16 + li;
+                // FP32 with up to 8 tiles per wave: the tile's four multiplier reads are issued
+                // before any of its writes (the registers allow it there); otherwise one at a time
+                constexpr bool BATCH = sizeof(R) == 4 && MAXT <= 8;
+                C dv[4];
+                if constexpr (BATCH) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = r0 + It * 16 + acc_row<R>(lk, r);
+                        dv[r] = cmk<C>(0, 0);
+                        if (row < l && col < s)
+                            dv[r] = side == 0 ? Dm[(int64_t)row * q + col] : Dm[(int64_t)col * q + row];
+                    }
+                }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int rloc = It * 16 + acc_row<R>(lk, r);
@@ -524,10 +537,10 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
                         else { a = col; c = row; z = cmk<C>(accR[t][r], -accI[t][r]); }
                         const C lv = lift_val(U, n, k, a, c);
                         const int64_t di = (int64_t)a * q + c;
-                        const C dv = Dm[di];
+                        if constexpr (!BATCH) dv[r] = Dm[di];
                         C dn;
-                        dn.x = dv.x + tau * (lv.x - z.x);
-                        dn.y = dv.y + tau * (lv.y - z.y);
+                        dn.x = dv[r].x + tau * (lv.x - z.x);
+                        dn.y = dv[r].y + tau * (lv.y - z.y);
                         Dm[di] = dn;
                         rv.x = z.x - dn.x * inv_beta;
                         rv.y = z.y - dn.y * inv_beta;
