@@ -7,12 +7,15 @@
 //
 // One workgroup per matrix, all arithmetic in FP64:
 //  1. Householder reduction to tridiagonal form with Hermitian reflectors
-//     P = I - u u^H / h (the matrix lives in the per-slot scratch in HBM/L2);
+//     P = I - u u^H / h (the matrix lives in the per-slot scratch in HBM/L2),
+//     unless a register-resident reduction (k_tridiag_rr in FP64,
+//     k_tridiag_rr32 in FP32 for the mixed form) already ran;
 //  2. a diagonal unitary makes the off-diagonal real and non-negative;
 //  3. Sturm-sequence bisection for every eigenvalue above thr^2, in parallel;
 //  4. eigenvectors from a twisted factorisation of T - lambda I per eigenvalue;
-//     eigenvalues closer than ortol are grouped, refined by inverse iteration
-//     and re-orthogonalised (MGS);
+//     eigenvalues closer than ortol are grouped, and the later members of a
+//     group are refined by inverse iteration and re-orthogonalised by the
+//     whole workgroup (classical Gram-Schmidt, twice);
 //  5. back-transformation through the reflectors, scaling by sqrt(f), and
 //     S = X X^H written in the working precision (row-major, ld = s).
 #include <float.h>
