@@ -756,8 +756,9 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
 // reflector is rounded to FP32 once, and the rounded vector is both the one the
 // matrix is updated with and the one written out.  Outputs as k_tridiag_rr.
 // ---------------------------------------------------------------------------
-constexpr int RR32_THREADS = 512;
-constexpr int RR32_WAVES = RR32_THREADS / 64;
+// two shapes: 512 threads for orders up to 208 (two workgroups per CU), and 1024 threads for
+// orders 209 .. 256 (one workgroup per CU, still at most 128 registers per thread)
+constexpr int RR32_MAXS_WIDE = 256;
 
 template <int CTRL>
 __device__ inline float dpp_move_f(float v) {
@@ -774,11 +775,12 @@ __device__ inline float colsum4_pair_f(float x, float y) {
     return __int_as_float((int)b[0]) + __int_as_float((int)b[1]);
 }
 
-template <int MAXB>
-__global__ __launch_bounds__(RR32_THREADS, 4) void k_tridiag_rr32(const LRDesc* __restrict__ descs, int m0,
+template <int MAXB, int NTHR, int MAXS>
+__global__ __launch_bounds__(NTHR, 4) void k_tridiag_rr32(const LRDesc* __restrict__ descs, int m0,
                                                                   double2* __restrict__ Gs, int64_t g_stride,
                                                                   double* __restrict__ scr, int64_t scr_stride) {
-    constexpr int RR_SP = ((RR_MAXS + 15) / 16) * 16;
+    constexpr int RR32_THREADS = NTHR, RR32_WAVES = NTHR / 64;
+    constexpr int RR_SP = ((MAXS + 15) / 16) * 16;
     constexpr int RR_NB = RR_SP / 16, RR_NBLK = RR_NB * (RR_NB + 1) / 2;
     __shared__ float2 opA[RR_NB * 64];              // update operands in lane order (negated), as above
     __shared__ float opB[RR_NB * 64];
@@ -822,7 +824,7 @@ __global__ __launch_bounds__(RR32_THREADS, 4) void k_tridiag_rr32(const LRDesc* 
         for (int t = 0; t < MAXB; ++t) {
             const bool has = wave + RR32_WAVES * t < nblk;
             const int c = bJ[t] * 16 + lr;
-            // branch-free with 32-bit packed indices (orders up to RR_MAXS): every lane loads a
+            // branch-free with 32-bit packed indices (orders up to MAXS): every lane loads a
             // valid entry (the upper triangle as the conjugate of the lower one), and entries
             // outside the matrix are zeroed after the load
             double2 v[4];
@@ -1944,28 +1946,35 @@ static size_t heig_lds_bytes(int smax) {
            (2 * nw + 8) * sizeof(double);
 }
 
-bool tridiag_rr_supported(int smax) { return smax >= 2 && smax <= RR_MAXS; }
+bool tridiag_rr_supported(int smax, bool fp32) { return smax >= 2 && smax <= (fp32 ? RR32_MAXS_WIDE : RR_MAXS); }
 
 hipError_t launch_tridiag_rr(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
                              double* scr, int64_t scr_stride, int smax, bool fp32) {
-    if (!tridiag_rr_supported(smax)) return hipErrorInvalidValue;
+    if (!tridiag_rr_supported(smax, fp32)) return hipErrorInvalidValue;
     const int nb = (smax + 15) / 16;
     // blocks per wave: ceil(nb (nb + 1) / 2 / waves)
     const void* fn;
-    if (fp32)
-        fn = nb <= 6 ? (const void*)k_tridiag_rr32<3>
-           : nb <= 8 ? (const void*)k_tridiag_rr32<5>
-           : nb <= 10 ? (const void*)k_tridiag_rr32<7>
-           : nb <= 12 ? (const void*)k_tridiag_rr32<10>
-                      : (const void*)k_tridiag_rr32<12>;
-    else
+    int nthr = RR_THREADS;
+    if (fp32 && smax <= RR_MAXS) {
+        nthr = 512;
+        fn = nb <= 6 ? (const void*)k_tridiag_rr32<3, 512, RR_MAXS>
+           : nb <= 8 ? (const void*)k_tridiag_rr32<5, 512, RR_MAXS>
+           : nb <= 10 ? (const void*)k_tridiag_rr32<7, 512, RR_MAXS>
+           : nb <= 12 ? (const void*)k_tridiag_rr32<10, 512, RR_MAXS>
+                      : (const void*)k_tridiag_rr32<12, 512, RR_MAXS>;
+    } else if (fp32) {
+        nthr = 1024;
+        fn = nb <= 14 ? (const void*)k_tridiag_rr32<7, 1024, RR32_MAXS_WIDE>
+           : nb <= 15 ? (const void*)k_tridiag_rr32<8, 1024, RR32_MAXS_WIDE>
+                      : (const void*)k_tridiag_rr32<9, 1024, RR32_MAXS_WIDE>;
+    } else
         fn = nb <= 6 ? (const void*)k_tridiag_rr<2>
            : nb <= 8 ? (const void*)k_tridiag_rr<3>
            : nb <= 10 ? (const void*)k_tridiag_rr<5>
            : nb <= 12 ? (const void*)k_tridiag_rr<7>
                       : (const void*)k_tridiag_rr<8>;
     void* args[] = {(void*)&descs, (void*)&m0, (void*)&Gs, (void*)&g_stride, (void*)&scr, (void*)&scr_stride};
-    hipError_t e = hipLaunchKernel(fn, dim3(count), dim3(fp32 ? RR32_THREADS : RR_THREADS), args, 0, st);
+    hipError_t e = hipLaunchKernel(fn, dim3(count), dim3(nthr), args, 0, st);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }

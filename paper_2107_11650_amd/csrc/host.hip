@@ -126,7 +126,9 @@ struct LRRun {
     int rr = -1;           // Householder reduction: 1 registers, 0 memory, -1 registers when supported
 };
 
-static int run_uses_rr(const LRRun& r) { return r.rr >= 0 ? r.rr : (tridiag_rr_supported(r.smax) ? 1 : 0); }
+static int run_uses_rr(const LRRun& r, bool fp32) {
+    return r.rr >= 0 ? r.rr : (tridiag_rr_supported(r.smax, fp32) ? 1 : 0);
+}
 
 struct SliceLayout {
     int M, N;
@@ -302,17 +304,19 @@ static LRDesc make_desc(int64_t h_off, int h_cs, int h_es, int64_t b_off, int b_
 
 static const size_t SLOT_BUDGET = (size_t)3 << 30;   // eigen-solver scratch for one chunk
 
-// Eigen-solver class of a matrix order: register-resident reductions (order <= 208) apart
-// from in-memory ones, then by the number of 64-row tiles the eigen kernel is built for.
-static int order_class(int s) { return (tridiag_rr_supported(s) ? 0 : 16) + (s + 63) / 64; }
+// Eigen-solver class of a matrix order: register-resident reductions (order <= 208, or <= 256
+// in FP32) apart from in-memory ones, then by the number of 64-row tiles the eigen kernel is
+// built for.
+static int order_class(int s, bool fp32) { return (tridiag_rr_supported(s, fp32) ? 0 : 16) + (s + 63) / 64; }
 
 // Groups sorted by class (stable), the descriptors laid out again in that order, so that the
 // runs formed below hold matrices of one class.
 static void order_groups(shlr_plan* P) {
+    const bool fp32 = P->p.precision == SHLR_PREC_MIXED;
     std::vector<int> idx(P->groups.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-        return order_class(lr_s(P->groups[a].proto)) < order_class(lr_s(P->groups[b].proto));
+        return order_class(lr_s(P->groups[a].proto), fp32) < order_class(lr_s(P->groups[b].proto), fp32);
     });
     std::vector<LRDesc> d;
     std::vector<LRGroup> g;
@@ -329,6 +333,7 @@ static void order_groups(shlr_plan* P) {
 }
 
 static void layout_slots(shlr_plan* P) {
+    const bool fp32 = P->p.precision == SHLR_PREC_MIXED;
     P->runs.clear();
     P->bytes_g = P->bytes_s = P->bytes_scr = 0;
     for (int gi = 0; gi < (int)P->groups.size(); ++gi) {
@@ -341,7 +346,7 @@ static void layout_slots(shlr_plan* P) {
                 lo = std::min(lo, lr_s(P->groups[gj].proto));
                 hi = std::max(hi, lr_s(P->groups[gj].proto));
             }
-            if (hi <= 2 * lo && order_class(sg) == order_class(r.smax)) {
+            if (hi <= 2 * lo && order_class(sg, fp32) == order_class(r.smax, fp32)) {
                 r.g1 = gi + 1;
                 r.count += g.count;
                 r.smax = hi;
@@ -692,7 +697,7 @@ static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_
                                            g.gram_kc));
             }
             STCHK(phase_end(P, 1, e0));
-            const int rr = run_uses_rr(run);
+            const int rr = run_uses_rr(run, sizeof(R) == 4);
             if (rr) {
                 STCHK(phase_begin(P, &e0));
                 HIPCHK(launch_tridiag_rr(P->stream, desc_dev, c0, c1 - c0, G, run.g_stride, scr, run.scr_stride,

@@ -117,8 +117,8 @@ hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int coun
                            int tri_in = 0);
 // Register-resident Householder reduction of the packed Gram matrices (orders 2..208): reflectors in
 // place, diagonal / off-diagonal / h in the first 4 s doubles of each slot's scratch (then tri_in = 1).
-// fp32: the matrix held in FP32 (two workgroups per compute unit; the mixed form's forward iterations).
-bool tridiag_rr_supported(int smax);
+// fp32: the matrix held in FP32 (the mixed form's forward iterations), orders up to 256; FP64 up to 208.
+bool tridiag_rr_supported(int smax, bool fp32);
 hipError_t launch_tridiag_rr(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
                              double* scr, int64_t scr_stride, int smax, bool fp32);
 

@@ -76,6 +76,9 @@ LR_CASES = [
     (3, 4, 128, 32, False, True),     # 97 x 128: order 97 (register-resident reduction, 7 block rows)
     (3, 5, 200, 30, False, True),     # 171 x 150: order 150 (10 block rows)
     (3, 6, 240, 30, False, True),     # 211 x 180: order 180 (12 block rows)
+    (3, 12, 240, 25, False, True),    # 216 x 300: order 216 (FP32 reduction in registers, 14 block rows)
+    (3, 12, 256, 25, False, True),    # 232 x 300: order 232 (15 block rows)
+    (2, 10, 285, 30, False, True),    # 256 x 300: order 256 (16 block rows, the widest in registers)
     (3, 12, 256, 25, True, True),     # 232 x 600: 12-coil virtual-coil PE lifts
     (3, 6, 320, 45, False, True),     # 276 x 270: order above 256 (five 64-row slabs, in-memory reduction)
 ]
