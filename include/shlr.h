@@ -163,6 +163,12 @@ shlr_status shlr_reconstruct(shlr_plan* plan, const void* y_dev, const uint8_t* 
 #define SHLR_TIMING_PHASES 6
 shlr_status shlr_timing_enable(shlr_plan* plan, int32_t enable);
 
+/* As shlr_timing_enable, for the phases whose bits are set in phase_mask (bit p: phase p
+ * of shlr_timing_read); the other phases record no events, so their launches run as
+ * untimed.  phase_mask == 0 stops the accumulation; bits at or above SHLR_TIMING_PHASES
+ * are rejected with SHLR_E_INVALID_ARG. */
+shlr_status shlr_timing_enable_phases(shlr_plan* plan, uint32_t phase_mask);
+
 /* Read the accumulated times (synchronises the stream).  Phase index:
  * 0 transforms and X-update (Eq. 15 / S7), 1 lift + Gram, 2 eigen-solve and
  * threshold (Eq. 16), 3 reprojection + multiplier update (Eq. 13) + adjoint

@@ -183,6 +183,7 @@ struct shlr_plan {
     // per-phase HIP-event timing (phase: 0 transforms + X-update, 1 Gram, 2 eigen-SVT, 3 reprojection, 4 SPIRiT,
     // 5 register-resident Householder reduction)
     bool timing = false;
+    uint32_t timing_mask = 0x3f;   // phases timed while timing is on
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, std::pair<size_t, size_t>>> ev_marks;  // (phase, (start, stop))
@@ -200,14 +201,15 @@ static shlr_status ev_get(shlr_plan* P, size_t* idx) {
     *idx = P->ev_used++;
     return SHLR_OK;
 }
-static shlr_status phase_begin(shlr_plan* P, size_t* start) {
-    if (!P->timing) return SHLR_OK;
+static bool phase_timed(const shlr_plan* P, int phase) { return P->timing && ((P->timing_mask >> phase) & 1u); }
+static shlr_status phase_begin(shlr_plan* P, int phase, size_t* start) {
+    if (!phase_timed(P, phase)) return SHLR_OK;
     STCHK(ev_get(P, start));
     HIPCHK(hipEventRecord(P->ev_pool[*start], P->stream));
     return SHLR_OK;
 }
 static shlr_status phase_end(shlr_plan* P, int phase, size_t start) {
-    if (!P->timing) return SHLR_OK;
+    if (!phase_timed(P, phase)) return SHLR_OK;
     size_t stop;
     STCHK(ev_get(P, &stop));
     HIPCHK(hipEventRecord(P->ev_pool[stop], P->stream));
@@ -687,7 +689,7 @@ static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_
         for (int c0 = run.first; c0 < run.first + run.count; c0 += run.slots) {
             const int c1 = std::min(run.first + run.count, c0 + run.slots);
             size_t e0 = 0;
-            STCHK(phase_begin(P, &e0));
+            STCHK(phase_begin(P, 1, &e0));
             for (int gi = run.g0; gi < run.g1; ++gi) {
                 const LRGroup& g = P->groups[gi];
                 const int s0 = std::max(c0, g.first), s1 = std::min(c1, g.first + g.count);
@@ -699,17 +701,17 @@ static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_
             STCHK(phase_end(P, 1, e0));
             const int rr = run_uses_rr(run, sizeof(R) == 4);
             if (rr) {
-                STCHK(phase_begin(P, &e0));
+                STCHK(phase_begin(P, 5, &e0));
                 HIPCHK(launch_tridiag_rr(P->stream, desc_dev, c0, c1 - c0, G, run.g_stride, scr, run.scr_stride,
                                          run.smax, sizeof(R) == 4));
                 STCHK(phase_end(P, 5, e0));
             }
-            STCHK(phase_begin(P, &e0));
+            STCHK(phase_begin(P, 2, &e0));
             HIPCHK(launch_heig_svt<cplx_t<R>>(P->stream, desc_dev, c0, c1 - c0, G, run.g_stride, S, run.s_stride, scr,
                                               run.scr_stride, ranks, ortol, flags, run.smax, VjpArgs<cplx_t<R>>(),
                                               rr));
             STCHK(phase_end(P, 2, e0));
-            STCHK(phase_begin(P, &e0));
+            STCHK(phase_begin(P, 3, &e0));
             for (int gi = run.g0; gi < run.g1; ++gi) {
                 const LRGroup& g = P->groups[gi];
                 const int s0 = std::max(c0, g.first), s1 = std::min(c1, g.first + g.count);
@@ -731,7 +733,7 @@ static shlr_status x_update_phase(shlr_plan* P, bool track_change) {
     const int J = p.J;
     if (track_change) HIPCHK(launch_zero_doubles(P->stream, Q.change, 2 * p.n_slices));
     size_t e0 = 0;
-    STCHK(phase_begin(P, &e0));
+    STCHK(phase_begin(P, 0, &e0));
     if (p.model == SHLR_MODEL_PI) {
         for (int si = 0; si < p.n_slices; ++si) {
             const SliceLayout& L = P->sl[si];
@@ -941,10 +943,25 @@ static shlr_status iterate_impl(shlr_plan* P, int n, shlr_info* info) {
     return SHLR_OK;
 }
 
+extern "C" shlr_status shlr_timing_enable_phases(shlr_plan* plan, uint32_t phase_mask) {
+    if (!plan) return fail(SHLR_E_INVALID_ARG, "plan is NULL");
+    if (phase_mask >> SHLR_TIMING_PHASES) return fail(SHLR_E_INVALID_ARG, "phase mask has bits above phase %d",
+                                                       SHLR_TIMING_PHASES - 1);
+    STCHK(timing_collect(plan));
+    plan->timing = phase_mask != 0;
+    plan->timing_mask = phase_mask;
+    for (int i = 0; i < 8; ++i) {
+        plan->t_ms[i] = 0;
+        plan->t_cnt[i] = 0;
+    }
+    return SHLR_OK;
+}
+
 extern "C" shlr_status shlr_timing_enable(shlr_plan* plan, int32_t enable) {
     if (!plan) return fail(SHLR_E_INVALID_ARG, "plan is NULL");
     STCHK(timing_collect(plan));
     plan->timing = enable != 0;
+    plan->timing_mask = (1u << SHLR_TIMING_PHASES) - 1;
     for (int i = 0; i < 8; ++i) {
         plan->t_ms[i] = 0;
         plan->t_cnt[i] = 0;

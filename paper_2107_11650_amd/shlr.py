@@ -35,7 +35,7 @@ EXPORTED = [
     "shlr_plan_create", "shlr_plan_destroy", "shlr_workspace_size", "shlr_bind", "shlr_set_spirit_kernel",
     "shlr_calibrate_spirit", "shlr_init", "shlr_iterate", "shlr_iterate_graph", "shlr_get_kspace",
     "shlr_reconstruct", "shlr_fft_lines", "shlr_lowrank_workspace_size", "shlr_lowrank_lines",
-    "shlr_last_error", "shlr_version", "shlr_timing_enable", "shlr_timing_read",
+    "shlr_last_error", "shlr_version", "shlr_timing_enable", "shlr_timing_enable_phases", "shlr_timing_read",
     "shlr_unrolled_sizes", "shlr_unrolled_forward", "shlr_unrolled_backward", "shlr_autotune",
 ]
 TIMING_PHASES = ("xupdate", "gram", "eig", "reproj", "spirit", "tridiag")
@@ -89,6 +89,7 @@ _lib.shlr_unrolled_backward.argtypes = [_vp, _i32, _vp, _vp, ctypes.c_size_t, _v
                                         ctypes.POINTER(ctypes.c_double)]
 _lib.shlr_autotune.argtypes = [_vp, _i32, ctypes.c_char_p, ctypes.c_size_t]
 _lib.shlr_timing_enable.argtypes = [_vp, _i32]
+_lib.shlr_timing_enable_phases.argtypes = [_vp, ctypes.c_uint32]
 _lib.shlr_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
 _lib.shlr_last_error.restype = ctypes.c_char_p
 _lib.shlr_version.restype = ctypes.c_char_p
@@ -219,6 +220,13 @@ class Plan:
 
     def timing_enable(self, on=True):
         _check(_lib.shlr_timing_enable(self._h, int(on)))
+
+    def timing_enable_phases(self, phases):
+        """Time only the named phases (names of TIMING_PHASES); an empty list stops timing."""
+        mask = 0
+        for p in phases:
+            mask |= 1 << TIMING_PHASES.index(p)
+        _check(_lib.shlr_timing_enable_phases(self._h, ctypes.c_uint32(mask)))
 
     def timing_read(self):
         """Accumulated per-phase device time: {phase: (ms, launches)}."""

@@ -201,6 +201,40 @@ def run_pi_gpu(Y, mask, prm: O.PIParams, precision, graph=False, slices=None):
     return out
 
 
+def test_phase_timing_mask():
+    """Timing restricted to some phases records only those; the iterate itself is unchanged."""
+    shlr = _lib()
+    Y, mask = pi_problem(4, 64, 64, seed=5)
+    p = shlr.Params(model=shlr.MODEL_PI, precision=shlr.PREC_MIXED, M=(64,), N=(64,), J=4, k_row=8, k_col=8,
+                    lam=1e3, beta=10.0, tau=10.0, max_iter=3)
+    outs, ran = [], None
+    for phases in (None, ["tridiag", "reproj"]):
+        plan = shlr.Plan(p)
+        plan.init(dev(Y, plan.cdtype), dev(mask.astype(np.uint8), torch.uint8))
+        if phases is None:
+            plan.timing_enable(True)
+        else:
+            plan.timing_enable_phases(phases)
+        plan.iterate(3)
+        t = plan.timing_read()
+        plan.timing_enable(False)
+        outs.append(host(plan.kspace()))
+        plan.close()
+        if phases is None:
+            ran = {name for name, (ms, n) in t.items() if n > 0}
+            assert {"tridiag", "reproj", "gram", "eig", "xupdate"} <= ran
+        else:
+            for name, (ms, n) in t.items():
+                assert (n > 0) == (name in phases and name in ran), (name, n)
+    assert np.array_equal(outs[0], outs[1])
+    plan = shlr.Plan(p)
+    try:
+        with pytest.raises(shlr.ShlrError):
+            shlr._check(shlr._lib.shlr_timing_enable_phases(plan._h, 1 << len(shlr.TIMING_PHASES)))
+    finally:
+        plan.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-18), ("mixed", 1e-5)])
 def test_pi_config1_20_iterations(prec, tol):
     # 4 coils, 64 x 64, 1D variable-density Cartesian R=3 with 8 centre lines, window 8, 20 iterations
