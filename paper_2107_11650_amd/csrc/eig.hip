@@ -1492,12 +1492,69 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
         int rank = 0;
         if (leader)
             for (int k = 1; k <= tid; ++k) rank += (slam[k] - slam[k - 1] > ortol);
-        for (int r0 = 0; r0 < nlead; r0 += cap) {
-            if (leader && rank >= r0 && rank < r0 + cap) {
-                double* Dp = wsd + (int64_t)(rank - r0) * wstride;
+        if (nlead <= cap) {   // uniform
+            if (leader) {
+                double* Dp = wsd + (int64_t)rank * wstride;
                 twisted(slam[tid], W + (int64_t)tid * s, Dp, Dp + s);
             }
             __syncthreads();
+        } else {
+            // more vectors than slots of 2 s + 1: D+ and U share one array of s (+ 1, odd stride),
+            // which holds twice as many at once.  Only D+ below the twist and U from it onwards
+            // are read when z is formed, so U is recomputed, from the bottom up to the twist, over
+            // the D+ entries that are no longer needed.
+            const int cstride = s + 1;
+            const int cap1 = max(1, (heig_region_a(smax) * 2) / cstride);
+            for (int r0 = 0; r0 < nlead; r0 += cap1) {
+                if (leader && rank >= r0 && rank < r0 + cap1) {
+                    const double lk = slam[tid];
+                    double* F = wsd + (int64_t)(rank - r0) * cstride;
+                    double* z = W + (int64_t)tid * s;
+                    double dp = sdd[0] - lk;
+                    for (int i = 0; i + 1 < s; ++i) {
+                        if (fabs(dp) < pivmin) dp = -pivmin;
+                        F[i] = dp;
+                        const double e = see[i];
+                        dp = sdd[i + 1] - lk - e * e * rcp_nr(dp);
+                    }
+                    if (fabs(dp) < pivmin) dp = -pivmin;
+                    F[s - 1] = dp;
+                    double dm = sdd[s - 1] - lk;
+                    int twist = s - 1;
+                    double gbest = fabs(F[s - 1]);
+                    for (int i = s - 2; i >= 0; --i) {
+                        if (fabs(dm) < pivmin) dm = -pivmin;
+                        const double e = see[i];
+                        const double u = e * rcp_nr(dm);
+                        dm = sdd[i] - lk - u * e;
+                        const double g = fabs(F[i] + dm - (sdd[i] - lk));
+                        if (g < gbest) {
+                            gbest = g;
+                            twist = i;
+                        }
+                    }
+                    dm = sdd[s - 1] - lk;
+                    for (int i = s - 2; i >= twist; --i) {
+                        if (fabs(dm) < pivmin) dm = -pivmin;
+                        const double e = see[i];
+                        const double u = e * rcp_nr(dm);
+                        F[i] = u;
+                        dm = sdd[i] - lk - u * e;
+                    }
+                    double zc = 1.0;
+                    z[twist] = 1.0;
+                    for (int i = twist - 1; i >= 0; --i) {
+                        zc = -see[i] * rcp_nr(F[i]) * zc;
+                        z[i] = zc;
+                    }
+                    zc = 1.0;
+                    for (int i = twist; i + 1 < s; ++i) {
+                        zc = -F[i] * zc;
+                        z[i + 1] = zc;
+                    }
+                }
+                __syncthreads();
+            }
         }
         if (nlead < nabove) {   // uniform: some eigenvalues are clustered
             double* Dp = wsd;
