@@ -1388,8 +1388,10 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
     int nabove = 0;
     if (!bad) nabove = s - sturm_count(sdd, se2, s, t2, pivmin);
     {
+        // at most 256 lanes count at once: with two workgroups per CU, half the block's lanes and
+        // two more rounds take less time than every lane (the counts are issue-bound)
         int G = 64;
-        while (G > 1 && G * nabove > EIG_THREADS) G >>= 1;
+        while (G > 1 && G * nabove > EIG_THREADS / 2) G >>= 1;
         const int ngroups = EIG_THREADS / G;
         const int grp = tid / G, gl_ = tid % G;
         const double slack = 2.0 * DBL_EPSILON * tnorm + pivmin;
