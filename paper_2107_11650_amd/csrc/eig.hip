@@ -906,9 +906,14 @@ __global__ __launch_bounds__(NTHR, 4) void k_tridiag_rr32(const LRDesc* __restri
         double hh = 1.0, xn = 0.0;
         double2 ph = make_double2(1.0, 0.0);
         if (refl) {
-            const double aabs = sqrt(al.x * al.x + al.y * al.y);
-            xn = sqrt(aabs * aabs + tail);
-            if (aabs > 0) ph = make_double2(al.x / aabs, al.y / aabs);
+            // reciprocals by the hardware estimate and a Newton step (FP32-accurate data)
+            const double a2 = al.x * al.x + al.y * al.y;
+            const double aabs = sqrt(a2);
+            xn = sqrt(a2 + tail);
+            if (aabs > 0) {
+                const double ia = rcp_nr(aabs);
+                ph = make_double2(al.x * ia, al.y * ia);
+            }
             hh = xn * xn + aabs * xn;
         }
         if (tl == 0) {
@@ -928,7 +933,7 @@ __global__ __launch_bounds__(NTHR, 4) void k_tridiag_rr32(const LRDesc* __restri
         }
         if (tl == 0) {
             rh[0] = hh;
-            rh[1] = 1.0 / hh;
+            rh[1] = rcp_nr(hh);
             rrefl = refl;
         }
     };
