@@ -403,19 +403,44 @@ __global__ __launch_bounds__(SPC_THREADS) void k_spirit_cols(const cplx_t<R>* __
     C* res = dft_run(L, J, pl, true, tid, SPC_THREADS);
     C* oth = (res == L.b0) ? L.b1 : L.b0;
     const R sc = (R)(1.0 / sqrt((double)M));
-    // one (pixel, output coil) pair per thread: the J threads of a pixel read its J x J block coalesced
-    for (int e = tid; e < M * J; e += SPC_THREADS) {
-        const int m = e / J, a = e - m * J;
-        int q = m - c;
-        if (q < 0) q += M;
-        const C* Ar = A + (((int64_t)m * N + n) * J + a) * J;
-        R sr = 0, si = 0;
-        for (int b = 0; b < J; ++b) {
-            const C mv = Ar[b], v = res[b * ls + q];
-            sr += mv.x * v.x - mv.y * v.y;
-            si += mv.x * v.y + mv.y * v.x;
+    // one (pixel, output coil) pair per thread: the J threads of a pixel read its J x J block
+    // coalesced.  Two pairs per thread at a time, their operator rows read in groups of 8 entries
+    // before the products, so that a group waits for memory once rather than once per entry.
+    constexpr int GB = 8;
+    for (int e0 = tid; e0 < M * J; e0 += 2 * SPC_THREADS) {
+        R sr[2] = {0, 0}, si[2] = {0, 0};
+        int qq[2], aa[2];
+        const C* Ar[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = min(e0 + h * SPC_THREADS, M * J - 1);
+            const int m = e / J, a = e - m * J;
+            int q = m - c;
+            if (q < 0) q += M;
+            qq[h] = q;
+            aa[h] = a;
+            Ar[h] = A + (((int64_t)m * N + n) * J + a) * J;
         }
-        oth[a * ls + q] = cmk<C>(sr * sc, si * sc);
+        for (int b0 = 0; b0 < J; b0 += GB) {
+            C mv[2][GB];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int u = 0; u < GB; ++u) mv[h][u] = b0 + u < J ? Ar[h][b0 + u] : cmk<C>(0, 0);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int u = 0; u < GB; ++u) {
+                    if (b0 + u < J) {
+                        const C v = res[(b0 + u) * ls + qq[h]];
+                        sr[h] += mv[h][u].x * v.x - mv[h][u].y * v.y;
+                        si[h] += mv[h][u].x * v.y + mv[h][u].y * v.x;
+                    }
+                }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (e0 + h * SPC_THREADS < M * J) oth[aa[h] * ls + qq[h]] = cmk<C>(sr[h] * sc, si[h] * sc);
     }
     __syncthreads();
     FftLds<C> L2 = L;   // the product is staged in oth
