@@ -175,6 +175,7 @@ __device__ inline void load_lines_centred(C* dst, const C* src, const LineAddr& 
                                           int tid, int nth) {
     const int c = n / 2;
     if (a.es == 1) {
+#pragma unroll 4
         for (int e = tid; e < nl * n; e += nth) {
             const int line = e / n, i = e - line * n;
             int t = i - c;
@@ -182,6 +183,7 @@ __device__ inline void load_lines_centred(C* dst, const C* src, const LineAddr& 
             dst[line * ls + t] = src[line_off(a, g0 + line) + i];
         }
     } else {
+#pragma unroll 4
         for (int e = tid; e < nl * n; e += nth) {
             const int line = e % nl, i = e / nl;
             int t = i - c;
@@ -196,6 +198,7 @@ __device__ inline void store_lines_centred(C* dstg, const C* res, const LineAddr
                                            R scale, int tid, int nth) {
     const int c = n / 2;
     if (a.es == 1) {
+#pragma unroll 4
         for (int e = tid; e < nl * n; e += nth) {
             const int line = e / n, i = e - line * n;
             int f = i - c;
@@ -203,6 +206,7 @@ __device__ inline void store_lines_centred(C* dstg, const C* res, const LineAddr
             dstg[line_off(a, g0 + line) + i] = cscale(res[line * ls + f], scale);
         }
     } else {
+#pragma unroll 4
         for (int e = tid; e < nl * n; e += nth) {
             const int line = e % nl, i = e / nl;
             int f = i - c;
@@ -269,6 +273,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
     const R sc = (R)(1.0 / sqrt((double)n));
     // 1. load the other-direction adjoint rows (centred)
     if (x.bo.es == 1) {
+#pragma unroll 4
         for (int e = tid; e < nl * n; e += FFT_THREADS) {
             const int line = e / n, i = e - line * n;
             int d2, d1, d0;
@@ -278,6 +283,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
             b0[line * ls + t] = base_bo[row_off(x.bo, d2, d1, d0) + i];
         }
     } else {
+#pragma unroll 4
         for (int e = tid; e < nl * n; e += FFT_THREADS) {
             const int line = e % nl, i = e / nl;
             int d2, d1, d0;
@@ -292,6 +298,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
     C* oth = (res == L.b0) ? L.b1 : L.b0;
     // 2. combine; write K and stage K (centred) for the inverse transform
     double dsum = 0, osum = 0;
+#pragma unroll 4
     for (int e = tid; e < nl * n; e += FFT_THREADS) {
         const int line = e / n, i = e - line * n;
         int d2, d1, d0;
@@ -347,6 +354,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
     L2.b1 = res;
     C* res2 = dft_run(L2, nl, pl, true, tid, FFT_THREADS);
     if (x.out.es == 1) {
+#pragma unroll 4
         for (int e = tid; e < nl * n; e += FFT_THREADS) {
             const int line = e / n, i = e - line * n;
             int d2, d1, d0;
@@ -356,6 +364,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
             base_out[row_off(x.out, d2, d1, d0) + i] = cscale(res2[line * ls + f], sc);
         }
     } else {
+#pragma unroll 4
         for (int e = tid; e < nl * n; e += FFT_THREADS) {
             const int line = e % nl, i = e / nl;
             int d2, d1, d0;
@@ -393,6 +402,7 @@ __global__ __launch_bounds__(SPC_THREADS) void k_spirit_cols(const cplx_t<R>* __
     const int tid = threadIdx.x, ls = pl.f, c = M / 2;
     const int64_t MN = (int64_t)M * N;
     const FftLds<C> L = fft_setup<C>(smem_raw, pl, J, tid, SPC_THREADS);
+#pragma unroll 4
     for (int e = tid; e < J * M; e += SPC_THREADS) {
         const int j = e / M, m = e - j * M;
         int q = m - c;
@@ -447,6 +457,7 @@ __global__ __launch_bounds__(SPC_THREADS) void k_spirit_cols(const cplx_t<R>* __
     L2.b0 = oth;
     L2.b1 = res;
     C* r2 = dft_run(L2, J, pl, false, tid, SPC_THREADS);
+#pragma unroll 4
     for (int e = tid; e < J * M; e += SPC_THREADS) {
         const int j = e / M, m = e - j * M;
         int q = m - c;
@@ -483,6 +494,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_dir(cplx_t<R>* __restr
     const FftLds<C> L = fft_setup<C>(smem_raw, pl, NL, tid, FFT_THREADS);
     const int g0 = blockIdx.x * NL;
     const int nl = min(NL, n_lines - g0);
+#pragma unroll 4
     for (int e = tid; e < nl * N; e += FFT_THREADS) {
         const int line = e / N, i = e - line * N;
         int q = i - c;
@@ -496,6 +508,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_dir(cplx_t<R>* __restr
     __syncthreads();
     C* res = dft_run(L, nl, pl, true, tid, FFT_THREADS);
     const R sc = (R)(1.0 / sqrt((double)N));
+#pragma unroll 4
     for (int e = tid; e < nl * N; e += FFT_THREADS) {
         const int line = e / N, i = e - line * N;
         int q = i - c;
@@ -518,6 +531,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_apply(cplx_t<R>* __res
     const FftLds<C> L = fft_setup<C>(smem_raw, pl, NL, tid, FFT_THREADS);
     const int g0 = blockIdx.x * NL;
     const int nl = min(NL, J * M - g0);
+#pragma unroll 4
     for (int e = tid; e < nl * N; e += FFT_THREADS) {
         const int line = e / N, i = e - line * N;
         int q = i - c;
@@ -528,6 +542,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_apply(cplx_t<R>* __res
     C* res = dft_run(L, nl, pl, false, tid, FFT_THREADS);
     const R sc = (R)(1.0 / sqrt((double)N));
     double acc = 0;
+#pragma unroll 4
     for (int e = tid; e < nl * N; e += FFT_THREADS) {
         const int line = e / N, i = e - line * N;
         int q = i - c;

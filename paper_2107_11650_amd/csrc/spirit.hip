@@ -178,6 +178,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_update(cplx_t<R>* __restric
                                                             double* partials) {
     const R alpha = (R)scal[2];
     double acc = 0;
+#pragma unroll 4
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
         const R d = den_at(e, M, N, mask, rtab, rr_off, rc_off, lam, beta);
         const cplx_t<R> pv = p[e], av = Ap[e];
@@ -225,6 +226,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_update_a(cplx_t<R>* __restr
     const double rz0 = *rz;
     const R alpha = (R)((pap != 0.0 && rz0 != 0.0) ? rz0 / pap : 0.0);
     double acc = 0;
+#pragma unroll 4
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
         const R d = den_at(e, M, N, mask, rtab, rr_off, rc_off, lam, beta);
         const cplx_t<R> pv = p[e], av = Ap[e];
