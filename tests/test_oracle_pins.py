@@ -251,7 +251,7 @@ def test_soft_dc_tends_to_hard_dc():
 
 
 # --------------------------------------------------------------------------
-# whole iterations against the dense brute force (spec: 8x8 brute force)
+# whole iterations on 8x8 k-space against the dense brute force
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("vc", [False, True])
