@@ -1006,6 +1006,9 @@ __global__ __launch_bounds__(NTHR, 4) void k_tridiag_rr32(const LRDesc* __restri
             }
         }
         __syncthreads();
+        // the serial part of the step (gather, the two reductions, the reflector) runs at raised
+        // wave priority, ahead of the block products of the other matrix on the compute unit
+        __builtin_amdgcn_s_setprio(2);
         {
             const int j = i + 1;
             const int tl = tid_now();
@@ -1064,6 +1067,7 @@ __global__ __launch_bounds__(NTHR, 4) void k_tridiag_rr32(const LRDesc* __restri
             }
             finish_and_reflect(j, refl, qj);
         }
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
     }
 }
