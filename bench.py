@@ -300,6 +300,31 @@ def main():
         "roofline": roof,
     }
 
+    # the low-rank step per iteration, from the phase times of the warm-up: the contraction kernels
+    # against max(bytes / HBM, flops / MFMA), and the whole step (Gram, reduction, eigen-solve,
+    # reprojection) against flops / MFMA + eigen flops / FP64 (13.3 s^3 per matrix), or bytes / HBM.
+    # Bytes: D read by the Gram kernel, read and written by the reprojection.
+    mfma_peak = PEAK_TFLOPS_FP32_MFMA if prec == shlr.PREC_MIXED else PEAK_TFLOPS_FP64
+    ms = {k: warm[k][0] / n_warm if k in warm else 0.0 for k in ("gram", "tridiag", "eig", "reproj")}
+    d_bytes = sum(c * 3.0 * p * q * csize for p, q, c in shapes)
+    t_hbm = d_bytes / (PEAK_HBM_GBS * 1e9) * 1e3
+    t_mfma = (work["gram"] + work["reproj"]) / (mfma_peak * 1e12) * 1e3
+    t_eig = work["eig"] / (PEAK_TFLOPS_FP64 * 1e12) * 1e3
+    ms_contr = ms["gram"] + ms["reproj"]
+    ms_whole = ms_contr + ms["tridiag"] + ms["eig"]
+    if ms_contr > 0 and ms_whole > 0:
+        result["lowrank_step"] = {
+            "contraction": {"kernels": "gram + reproj", "ms_per_step": ms_contr, "bound_ms": max(t_hbm, t_mfma),
+                            "bound": "mfma" if t_mfma >= t_hbm else "hbm", "frac": max(t_hbm, t_mfma) / ms_contr,
+                            "tflops": (work["gram"] + work["reproj"]) / (ms_contr * 1e-3) / 1e12,
+                            "peak_tflops": mfma_peak},
+            "whole": {"kernels": "gram + tridiag + eig + reproj", "ms_per_step": ms_whole,
+                      "bound_ms": max(t_hbm, t_mfma + t_eig), "frac": max(t_hbm, t_mfma + t_eig) / ms_whole,
+                      "convention": "contractions at the MFMA peak of the data type; the eigen-solve counted as "
+                                    "13.3 s^3 FP64 flops per matrix at the FP64 peak"},
+            "d_bytes_per_step": d_bytes,
+        }
+
     if not args.no_diff and args.workload == "pi256":
         result["differentiation"] = diff_leg(args.diff_batch, args.diff_steps, kw, lam, beta)
 
