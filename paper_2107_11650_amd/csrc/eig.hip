@@ -428,6 +428,40 @@ constexpr int RR_TILE = 16 * 17;
 
 __device__ inline int rr_bidx(int I, int J, int nb) { return J * nb - (J * (J - 1)) / 2 + (I - J); }
 
+// Sum of the partials of row 16 I + rr over the blocks t = jlo .. nb-1 of the trailing matrix: row
+// partials of blocks (I, t) for t <= I, then column partials of blocks (t, I) for t > I, added in
+// that order.  The loads are issued BATCH at a time before their sums (one LDS round trip per
+// batch instead of one per block); lanes past the last block load entry 0 and skip the sum.
+template <int NBMAX, int BATCH, typename T, typename V>
+__device__ inline void gather_partials(const V* yrow, const V* ycol, int I, int rr, int jlo, int nb, T& ax, T& ay) {
+    // block indices stepped along t: rr_bidx(I, t + 1) = rr_bidx(I, t) + nb - 1 - t, and
+    // rr_bidx(t, I) = rr_bidx(I, I) + t - I
+    int bl = rr_bidx(I, jlo, nb);
+    const int bu = rr_bidx(I, I, nb) - I;
+#pragma unroll
+    for (int m0 = 0; m0 < NBMAX; m0 += BATCH) {
+        if (jlo + m0 >= nb) break;   // uniform over the block
+        V v[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            if (m0 + u < NBMAX) {
+                const int t = jlo + m0 + u;
+                const bool lower = t <= I;
+                const int b = lower ? bl : bu + t;
+                v[u] = (lower ? yrow : ycol)[(t < nb ? b : 0) * 16 + rr];
+                bl += nb - 1 - t;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            if (m0 + u < NBMAX && jlo + m0 + u < nb) {
+                ax += v[u].x;
+                ay += v[u].y;
+            }
+        }
+    }
+}
+
 // a - (u_r conj(q_c) + q_r conj(u_c)): one element of the pending Hermitian rank-2 update
 __device__ inline double2 rank2_sub(double2 a, double2 ur, double2 qr, double2 uc, double2 qc) {
     a.x = fma(-ur.x, qc.x, a.x);
@@ -690,18 +724,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
             if (r < s && refl) {
                 // row partials of blocks (I, jlo .. I), then column partials of blocks (I + 1 .. nb-1, I)
                 const int I = r >> 4, rr = r & 15;
-#pragma unroll 4
-                for (int J = jlo; J <= I; ++J) {
-                    const double2 v = yrow[rr_bidx(I, J, nb) * 16 + rr];
-                    pv.x += v.x;
-                    pv.y += v.y;
-                }
-#pragma unroll 4
-                for (int I2 = I + 1; I2 < nb; ++I2) {
-                    const double2 v = ycol[rr_bidx(I2, I, nb) * 16 + rr];
-                    pv.x += v.x;
-                    pv.y += v.y;
-                }
+                gather_partials<RR_NB, 4>(yrow, ycol, I, rr, jlo, nb, pv.x, pv.y);
                 pv.x *= ihh;
                 pv.y *= ihh;
                 const double2 u = uc[r];
@@ -921,10 +944,9 @@ __global__ __launch_bounds__(NTHR, 4) void k_tridiag_rr32(const LRDesc* __restri
             tei[j] = refl ? -ph.y * xn : al.y;
             thv[j] = refl ? hh : 0.0;
         }
-        if (r == j) uc[j] = make_float2(0.f, 0.f);
-        if (r > j && r < s) {
-            float2 u = make_float2(0.f, 0.f);
-            if (refl) {
+        if (r >= j && r < s) {
+            float2 u = make_float2(0.f, 0.f);   // entry j of the reflector is zero
+            if (refl && r > j) {
                 const double2 ud = (r == j + 1) ? make_double2(al.x + ph.x * xn, al.y + ph.y * xn) : xraw[r];
                 u = make_float2((float)ud.x, (float)ud.y);
                 A[pk(r, j, s)] = make_double2(u.x, u.y);
@@ -1019,19 +1041,9 @@ __global__ __launch_bounds__(NTHR, 4) void k_tridiag_rr32(const LRDesc* __restri
             double uhp = 0;
             if (r < s && refl) {
                 const int I = r >> 4, rr = r & 15;
-                float2 acc = make_float2(0.f, 0.f);
-#pragma unroll 4
-                for (int J = jlo; J <= I; ++J) {
-                    const float2 v = yrow[rr_bidx(I, J, nb) * 16 + rr];
-                    acc.x += v.x;
-                    acc.y += v.y;
-                }
-#pragma unroll 4
-                for (int I2 = I + 1; I2 < nb; ++I2) {
-                    const float2 v = ycol[rr_bidx(I2, I, nb) * 16 + rr];
-                    acc.x += v.x;
-                    acc.y += v.y;
-                }
+                float ax = 0.f, ay = 0.f;
+                gather_partials<RR_NB, 8>(yrow, ycol, I, rr, jlo, nb, ax, ay);
+                const float2 acc = make_float2(ax, ay);
                 pv = make_double2(acc.x * ihh, acc.y * ihh);
                 const float2 u = uc[r];
                 uhp = u.x * pv.x + u.y * pv.y;
