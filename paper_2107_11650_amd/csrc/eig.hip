@@ -785,7 +785,7 @@ constexpr int RR32_MAXS_WIDE = 256;
 
 template <int CTRL>
 __device__ inline float dpp_move_f(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
 }
 // colsum4_pair for single precision: lanes of rows 0 and 2 end with the sum of x over the
 // four rows of 16 lanes, lanes of rows 1 and 3 with the sum of y
