@@ -115,15 +115,18 @@ def build_workload(name, prec, n_cg, tune=True):
     return plan, Y, mask, shapes, elems, cfg
 
 
-def measured_traffic(phase, prec):
-    """HBM bytes per launch of a phase's kernel from the committed rocprofv3 counter runs, or None
-    when the kernel's sources changed since the counters were taken (or another precision runs)."""
+def measured_traffic(phase, prec_name):
+    """HBM bytes per launch of a phase's kernel from the committed rocprofv3 counter runs of this
+    precision form, or None when there are none or the kernel's sources changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_8coil_256_k25.json")
-    if prec != 0 or not os.path.exists(path):   # counters were taken in mixed precision
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_8coil_256_k25_{prec_name.replace('-', '_')}.json")
+    if not os.path.exists(path):
         return None
     with open(path) as f:
-        rec = json.load(f)["phases"].get(phase)
+        d = json.load(f)
+    if d.get("precision") != prec_name:
+        return None
+    rec = d["phases"].get(phase)
     if rec is None:
         return None
     for name, digest in rec["sources"].items():
@@ -178,12 +181,52 @@ def diff_leg(batch, steps, kw, lam, beta, reps=2):
     }
 
 
+def timed_run(plan, steps, warmup, check_iters):
+    """The accuracy-check iterations, the warm-up with every phase timed, then `steps` iterations timed
+    with HIP events around the dominant phase only (each timed phase adds an event pair per launch)."""
+    import numpy as np
+    import torch
+    k_check = None
+    if check_iters > 0:
+        plan.iterate(check_iters)
+        k_check = plan.kspace().cpu().numpy().astype(np.complex128)
+    names = ("gram", "eig", "reproj", "xupdate", "spirit", "tridiag")
+    warm = None
+    if warmup > 0:
+        plan.timing_enable(True)
+        plan.iterate(warmup)
+        warm = plan.timing_read()
+        plan.timing_enable(False)
+        dom = max(names, key=lambda k: warm[k][0])
+        plan.timing_enable_phases([dom])
+    else:
+        plan.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.iterate_async(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = plan.timing_read()
+    plan.timing_enable(False)
+    if warm is None:
+        dom = max(names, key=lambda k: phases[k][0])
+        warm, n_warm = phases, steps
+    else:
+        n_warm = warmup
+    return {"k_check": k_check, "warm": warm, "n_warm": n_warm, "phases": phases, "dom": dom,
+            "elapsed": t1 - t0}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--precision", choices=["mixed", "fp64", "mixed-r32"], default="mixed",
+                    help="mixed: FP32 MFMA products, FP64 eigen-solve (the default); fp64: FP64 throughout; "
+                         "mixed-r32: the opt-in form whose Householder reduction runs in FP32")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the comparison runs of the other precision forms on the same workload")
     ap.add_argument("--workload", choices=["pi256", "ragged", "t2"], default="pi256",
                     help="pi256: the headline 8-coil 256x256 SHLR-S iteration; ragged: 32 slices of 12 coils; "
                          "t2: the SHLR-VP T2 series")
@@ -217,57 +260,27 @@ def main():
     from paper_2107_11650_amd import shlr
 
     kw, lam, lam1, beta = 25, 1e4, 10.0, 30.0
-    prec = shlr.PREC_MIXED if args.precision == "mixed" else shlr.PREC_FP64
+    precs = {"mixed": shlr.PREC_MIXED, "fp64": shlr.PREC_FP64, "mixed-r32": shlr.PREC_MIXED_R32}
+    prec = precs[args.precision]
     plan, Y, mask, shapes, elems, cfg = build_workload(args.workload, prec, args.n_cg, tune=not args.no_autotune)
-
-    # accuracy check leg: K after check_iters iterations from the initial state
-    k_check = None
-    if args.workload == "pi256":
-        plan.iterate(args.check_iters)
-        k_check = plan.kspace().cpu().numpy().astype(np.complex128)
-
-    # warm-up with every phase timed: the per-phase breakdown, and which phase dominates; the
-    # timed region then records events around that phase's launches only (each timed phase
-    # adds an event pair per launch to the stream)
-    names = ("gram", "eig", "reproj", "xupdate", "spirit", "tridiag")
-    warm = None
-    if args.warmup > 0:
-        plan.timing_enable(True)
-        plan.iterate(args.warmup)
-        warm = plan.timing_read()
-        plan.timing_enable(False)
-        dom = max(names, key=lambda k: warm[k][0])
-        plan.timing_enable_phases([dom])
-    else:
-        plan.timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.iterate_async(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    phases = plan.timing_read()
-    plan.timing_enable(False)
-    elapsed = t1 - t0
+    run = timed_run(plan, args.steps, args.warmup, args.check_iters if args.workload == "pi256" else 0)
+    k_check, warm, n_warm, phases, dom = run["k_check"], run["warm"], run["n_warm"], run["phases"], run["dom"]
+    elapsed = run["elapsed"]
     value = args.steps / elapsed
-    if warm is None:
-        dom = max(names, key=lambda k: phases[k][0])
-        warm, n_warm = phases, args.steps
-    else:
-        n_warm = args.warmup
 
     # roofline of the dominant kernel: algorithmic work of one iteration / launches per iteration
-    csize = 8 if prec == shlr.PREC_MIXED else 16
+    csize = 16 if prec == shlr.PREC_FP64 else 8
     work = lowrank_work(shapes)
     ms_dom, n_dom = phases[dom]
     avg_ms = ms_dom / max(n_dom, 1)
     launches_per_step = n_dom / args.steps
     if dom in ("gram", "reproj"):
-        peak = PEAK_TFLOPS_FP32_MFMA if prec == shlr.PREC_MIXED else PEAK_TFLOPS_FP64
+        peak = PEAK_TFLOPS_FP64 if prec == shlr.PREC_FP64 else PEAK_TFLOPS_FP32_MFMA
         achieved = work[dom] / launches_per_step / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "unit": "TFLOP/s"}
     elif dom in ("eig", "tridiag"):
-        # the mixed form reduces to tridiagonal form in FP32; the eigen-solve proper is FP64
-        peak = PEAK_TFLOPS_FP32_VECTOR if (dom == "tridiag" and prec == shlr.PREC_MIXED) else PEAK_TFLOPS_FP64
+        # only the opt-in FP32-reduction form reduces in FP32; every other eigen-solve runs in FP64
+        peak = PEAK_TFLOPS_FP32_VECTOR if (dom == "tridiag" and prec == shlr.PREC_MIXED_R32) else PEAK_TFLOPS_FP64
         achieved = work[dom] / launches_per_step / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "unit": "TFLOP/s"}
     else:
@@ -276,7 +289,7 @@ def main():
         bytes_launch = 6 * elems * csize / launches_per_step
         achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "unit": "GB/s"}
-    traffic = measured_traffic(dom, prec) if args.workload == "pi256" else None
+    traffic = measured_traffic(dom, args.precision) if args.workload == "pi256" else None
     roof.update({"kernel": dom, "achieved": achieved, "peak": peak, "frac": achieved / peak,
                  "traffic": traffic, "avg_launch_ms": avg_ms, "launches": n_dom})
 
@@ -291,9 +304,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == shlr.PREC_MIXED else "f64",
+        "dtype": "f64" if prec == shlr.PREC_FP64 else "f32",
         "data": "synthetic",
-        "config": {**cfg, "tridiag_dtype": "f32" if prec == shlr.PREC_MIXED else "f64", "eig_dtype": "f64"},
+        "config": {**cfg, "precision": args.precision,
+                   "tridiag_dtype": "f32" if prec == shlr.PREC_MIXED_R32 else "f64", "eig_dtype": "f64"},
         "phases_ms_per_step": {k: v[0] / n_warm for k, v in warm.items()},
         "phases_timed_over": "warm-up iterations, every phase timed" if n_warm == args.warmup and args.warmup > 0
                              else "timed iterations",
@@ -304,7 +318,7 @@ def main():
     # against max(bytes / HBM, flops / MFMA), and the whole step (Gram, reduction, eigen-solve,
     # reprojection) against flops / MFMA + eigen flops / FP64 (13.3 s^3 per matrix), or bytes / HBM.
     # Bytes: D read by the Gram kernel, read and written by the reprojection.
-    mfma_peak = PEAK_TFLOPS_FP32_MFMA if prec == shlr.PREC_MIXED else PEAK_TFLOPS_FP64
+    mfma_peak = PEAK_TFLOPS_FP64 if prec == shlr.PREC_FP64 else PEAK_TFLOPS_FP32_MFMA
     ms = {k: warm[k][0] / n_warm if k in warm else 0.0 for k in ("gram", "tridiag", "eig", "reproj")}
     d_bytes = sum(c * 3.0 * p * q * csize for p, q, c in shapes)
     t_hbm = d_bytes / (PEAK_HBM_GBS * 1e9) * 1e3
@@ -346,6 +360,20 @@ def main():
         }
         result["nmse_vs_oracle"] = O.nmse(k_check, k_ref)
         result["nmse_iters"] = args.check_iters
+        if not args.no_forms:
+            # the other precision forms on the same workload, same step counts: throughput and error
+            forms = {}
+            for name, pv in precs.items():
+                if pv == prec:
+                    continue
+                p2, *_ = build_workload(args.workload, pv, args.n_cg, tune=not args.no_autotune)
+                r2 = timed_run(p2, args.steps, args.warmup, args.check_iters)
+                p2.close()
+                forms[name] = {"value": args.steps / r2["elapsed"], "ms_per_step": 1e3 * r2["elapsed"] / args.steps,
+                               "nmse_vs_oracle": O.nmse(r2["k_check"], k_ref),
+                               "tridiag_ms_per_step": r2["warm"]["tridiag"][0] / r2["n_warm"],
+                               "eig_ms_per_step": r2["warm"]["eig"][0] / r2["n_warm"]}
+            result["other_forms"] = forms
     plan.close()
     print(json.dumps(result))
 

@@ -16,8 +16,8 @@
  *
  * Conventions shared by every entry point
  *   - Complex data are interleaved (re, im): float pairs (complex64) when
- *     precision == SHLR_PREC_MIXED, double pairs (complex128) when
- *     precision == SHLR_PREC_FP64.
+ *     precision is SHLR_PREC_MIXED or SHLR_PREC_MIXED_R32, double pairs
+ *     (complex128) when precision == SHLR_PREC_FP64.
  *   - k-space is centred: the DC sample of an axis of length n sits at index
  *     n / 2 (integer division).  Every DFT is unitary.
  *   - "dev" pointers are device (HBM) pointers owned by the caller; "host"
@@ -43,8 +43,19 @@ extern "C" {
 #define SHLR_MODEL_PI 0     /* parallel imaging: SHLR(-S/-V/-SV)          */
 #define SHLR_MODEL_PARAM 1  /* parameter imaging: SHLR-P / SHLR-VP         */
 
-#define SHLR_PREC_MIXED 0   /* complex64 data; FP32 MFMA Gram and reprojection; FP64 eigensolves */
-#define SHLR_PREC_FP64 1    /* complex128 data; FP64 everywhere */
+/* Precision forms.  In every form the Gram matrices are accumulated to FP64 and the
+ * eigenvalue count above the threshold (the decision of Eq. 16) is a Sturm count in FP64
+ * arithmetic on the tridiagonal form; the forms differ in the data type and in the
+ * arithmetic of the Householder reduction that produces that tridiagonal form. */
+#define SHLR_PREC_MIXED 0     /* complex64 data; FP32 MFMA Gram and reprojection products with FP32
+                                 accumulation; the whole Hermitian eigen-solve (Householder reduction,
+                                 eigenvalues, threshold decision, eigenvectors, S) in FP64          */
+#define SHLR_PREC_FP64 1      /* complex128 data; FP64 everywhere                                    */
+#define SHLR_PREC_MIXED_R32 2 /* opt-in: as SHLR_PREC_MIXED but the Householder reduction to
+                                 tridiagonal form runs in FP32 (FP64 scalars), so the tridiagonal
+                                 whose eigenvalues are counted carries FP32 rounding (backward error
+                                 about 1e-7 of the Gram norm); faster, not the default.  Not
+                                 accepted by the reverse-mode calls.                                 */
 
 #define SHLR_MAX_SLICES 4096
 
@@ -78,7 +89,7 @@ typedef enum {
  */
 typedef struct {
     int32_t model;          /* SHLR_MODEL_PI or SHLR_MODEL_PARAM                        */
-    int32_t precision;      /* SHLR_PREC_MIXED or SHLR_PREC_FP64                          */
+    int32_t precision;      /* SHLR_PREC_MIXED, SHLR_PREC_FP64 or SHLR_PREC_MIXED_R32     */
     int32_t n_slices;       /* PI: 1..SHLR_MAX_SLICES; PARAM: 1                           */
     const int32_t* M;       /* host [n_slices]: rows (PARAM: FE positions)                */
     const int32_t* N;       /* host [n_slices]: columns (PARAM: PE positions)             */
@@ -98,19 +109,30 @@ typedef struct {
     double lambda2;         /* parameter-direction weight (Eq. 7), > 0 for PARAM           */
     double beta;            /* ADMM penalty (Eq. 9), > 0                                   */
     double tau;             /* multiplier step (Eqs. 13-14), > 0                           */
-    double tol;             /* relative-change stop of Algorithm S1/S2; <= 0: fixed count  */
+    double tol;             /* relative-change stop of Algorithm S1/S2; <= 0: fixed count;  */
+                            /* checked per unit (slice of PI, FE position of PARAM)         */
     double d0;              /* initial multiplier value (Algorithms S1/S2 use 1)           */
 } shlr_params;
 
 typedef struct {
-    int32_t iters_done;     /* iterations run by the last shlr_iterate / shlr_reconstruct  */
-    int32_t converged;      /* 1 if the tol test stopped it                                */
-    double rel_change;      /* last ||K^{k+1}-K^k||^2 / ||K^k||^2 (max over slices)         */
+    int32_t iters_done;     /* iterations run by the last call (with tol > 0: the most any  */
+                            /* unit ran in that call)                                       */
+    int32_t converged;      /* 1 if the tol test has stopped every unit                     */
+    double rel_change;      /* with tol > 0: the largest over units of the last             */
+                            /* ||K^{k+1}-K^k||^2 / ||K^k||^2 of each unit; else 0           */
     double scale;           /* max|Y| used for normalisation (1 if off)                     */
     uint32_t device_flags;  /* bit0: non-finite value met                                   */
 } shlr_info;
 
 typedef struct shlr_plan shlr_plan;
+
+/* Fill *p with the paper's settings for a model (Algorithms S1 / S2): iteration cap 50
+ * (SHLR_MODEL_PI) or 100 (SHLR_MODEL_PARAM), relative-change tolerance 1e-6, initial
+ * multipliers D = 1 (Z = 0), weighting W on, virtual coils off, no SPIRiT term, soft data
+ * consistency, normalisation on, precision SHLR_PREC_MIXED, one slice.  Sizes (M, N, J, L,
+ * windows) and the weights lambda, lambda1, lambda2, beta, tau, which the paper sets per
+ * experiment, are left 0 / NULL for the caller to fill. */
+shlr_status shlr_params_default(int32_t model, shlr_params* p);
 
 /* Validate p and build the plan (host only, no device call).  *out is NULL on error. */
 shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out);
@@ -140,14 +162,27 @@ shlr_status shlr_calibrate_spirit(shlr_plan* plan, int32_t acs, double reg);
  * initialisation). */
 shlr_status shlr_init(shlr_plan* plan, const void* y_dev, const uint8_t* mask_dev);
 
-/* Run n ADMM iterations (X-update Eq. 15 / S7, Z-updates Eqs. 16-17 / S8-S9,
- * multiplier updates Eqs. 13-14 / S5-S6).  With tol > 0 the relative change is
- * read back every iteration and the loop stops early; with tol <= 0 nothing is
- * read back and info (if not NULL) is filled after a stream synchronisation. */
+/* Run up to n ADMM iterations (X-update Eq. 15 / S7, Z-updates Eqs. 16-17 / S8-S9,
+ * multiplier updates Eqs. 13-14 / S5-S6).  With tol > 0 the stop test of Algorithms S1 / S2
+ * runs on the device after every iteration, per unit (each slice of SHLR_MODEL_PI, each FE
+ * position of SHLR_MODEL_PARAM): a unit whose relative change ||K^{k+1}-K^k||^2 / ||K^k||^2
+ * falls below tol keeps its K from then on, as if its own loop had ended.  The host reads
+ * only the number of active units, every 8 iterations, and returns once it is 0.  With
+ * tol <= 0 nothing is read back.  info (may be NULL) is filled after a stream
+ * synchronisation. */
 shlr_status shlr_iterate(shlr_plan* plan, int32_t n, shlr_info* info);
 
-/* Same iterations through a captured HIP graph of one iteration (tol ignored). */
+/* The same n iterations as replays of a HIP graph of one iteration, captured at the first
+ * call (stop test included when tol > 0; no early return to the host). */
 shlr_status shlr_iterate_graph(shlr_plan* plan, int32_t n, shlr_info* info);
+
+/* Per-unit state of the stop test since shlr_init: units are the slices (SHLR_MODEL_PI)
+ * or the FE positions (SHLR_MODEL_PARAM); n_units must equal that count.  iters_host
+ * [n_units] receives the iterations each unit ran (counted only when tol > 0),
+ * rel_host [n_units] its last relative change, active_host [n_units] 1 while it still
+ * iterates.  Any output pointer may be NULL.  Synchronises the stream. */
+shlr_status shlr_unit_status(const shlr_plan* plan, int32_t n_units, int32_t* iters_host, double* rel_host,
+                             int32_t* active_host);
 
 /* Write the current k-space estimate (scaled back) to k_out_dev (layout of Y). */
 shlr_status shlr_get_kspace(const shlr_plan* plan, void* k_out_dev);

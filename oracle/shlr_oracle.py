@@ -401,6 +401,8 @@ class ParamState:
     De: np.ndarray
     active: np.ndarray
     it: int = 0
+    it_fe: np.ndarray | None = None      # iterations run by each FE position
+    rel_change: list = field(default_factory=list)   # per iteration: relative change of each FE position
 
 
 def param_lifts(L, N, prm: ParamParams):
@@ -445,7 +447,7 @@ def shlr_param(Yk, mask, prm: ParamParams, return_state=False, fe_positions=None
     Zp = np.zeros((M, L, Lp.p, Lp.q(J)), dtype=np.complex128)
     Ze = np.zeros((M, N, Le.p, Le.q(J)), dtype=np.complex128)
     st = ParamState(K=Ym.copy(), Zp=Zp, Dp=np.full_like(Zp, prm.d0), Ze=Ze,
-                    De=np.full_like(Ze, prm.d0), active=np.ones(M, dtype=bool))
+                    De=np.full_like(Ze, prm.d0), active=np.ones(M, dtype=bool), it_fe=np.zeros(M, dtype=np.int64))
     lr = 0.0 if prm.hard_dc else prm.lam
     for _ in range(prm.iters):
         act = st.active
@@ -472,9 +474,14 @@ def shlr_param(Yk, mask, prm: ParamParams, return_state=False, fe_positions=None
         st.Dp[act] = st.Dp[act] + prm.t() * (LXp - Zp_)
         st.De[act] = st.De[act] + prm.t() * (LXe - Ze_)
         st.it += 1
+        st.it_fe[act] += 1
+        # relative change of each FE position (Algorithm S2's test, evaluated after the update)
+        num = np.sum(np.abs(Kn - K_prev) ** 2, axis=(1, 2, 3))
+        dd = np.sum(np.abs(K_prev) ** 2, axis=(1, 2, 3))
+        rel = np.full(M, np.nan)
+        rel[act] = np.where(dd > 0, num / np.where(dd > 0, dd, 1.0), np.inf)
+        st.rel_change.append(rel)
         if prm.tol > 0:
-            num = np.sum(np.abs(Kn - K_prev) ** 2, axis=(1, 2, 3))
-            dd = np.sum(np.abs(K_prev) ** 2, axis=(1, 2, 3))
             idx = np.nonzero(act)[0]
             st.active[idx[num < prm.tol * dd]] = False
     if fe_positions is not None:

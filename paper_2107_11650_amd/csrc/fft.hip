@@ -260,7 +260,8 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
                                                            const uint8_t* __restrict__ base_m,
                                                            const R* __restrict__ rtab, XupdRows x, FftPlan pl,
                                                            int NL, R lam, R beta, int hard_dc,
-                                                           double* __restrict__ change_acc, int rhs_only) {
+                                                           double* __restrict__ change_acc,
+                                                           const int32_t* __restrict__ active, int rhs_only) {
     using C = cplx_t<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = x.n, ls = pl.f;
@@ -296,8 +297,12 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
     __syncthreads();
     C* res = dft_run(L, nl, pl, false, tid, FFT_THREADS);
     C* oth = (res == L.b0) ? L.b1 : L.b0;
-    // 2. combine; write K and stage K (centred) for the inverse transform
+    // 2. combine; write K and stage K (centred) for the inverse transform.  Rows of a unit that
+    // the stop test has retired keep K (their staged line is the old K); the change sums are
+    // kept per unit and flushed when a thread's unit changes.
     double dsum = 0, osum = 0;
+    int cur_u = -1;
+    bool cur_act = true;
 #pragma unroll 4
     for (int e = tid; e < nl * n; e += FFT_THREADS) {
         const int line = e / n, i = e - line * n;
@@ -305,6 +310,16 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
         row_digits(x, g0 + line, d2, d1, d0);
         int f = i - c;
         if (f < 0) f += n;
+        const int u = x.unit_digit == 2 ? d2 : 0;
+        if (u != cur_u) {
+            if (change_acc && cur_u >= 0 && (dsum != 0 || osum != 0)) {
+                atomicAdd(change_acc + 2 * cur_u, dsum);
+                atomicAdd(change_acc + 2 * cur_u + 1, osum);
+            }
+            dsum = osum = 0;
+            cur_u = u;
+            cur_act = !active || active[u] != 0;
+        }
         const C cv = cscale(res[line * ls + f], sc);
         const C av = base_a[row_off(x.a, d2, d1, d0) + (int64_t)i * x.a.es];
         const int64_t yo = row_off(x.y, d2, d1, d0) + (int64_t)i * x.y.es;
@@ -317,6 +332,10 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
             const C yv = base_y[yo];
             const R lm = mk ? lam : (R)0;
             base_k[ko] = cmk<C>(lm * yv.x + beta * (av.x + cv.x), lm * yv.y + beta * (av.y + cv.y));
+            continue;
+        }
+        if (!cur_act) {
+            oth[line * ls + f] = base_k[ko];
             continue;
         }
         if (hard_dc) {
@@ -338,13 +357,21 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
     }
     if (rhs_only) return;   // uniform: the right-hand side of Eq. 15 only
     if (change_acc) {
-        for (int off = 32; off > 0; off >>= 1) {
-            dsum += __shfl_down(dsum, off, 64);
-            osum += __shfl_down(osum, off, 64);
-        }
-        if ((tid & 63) == 0) {
-            atomicAdd(change_acc, dsum);
-            atomicAdd(change_acc + 1, osum);
+        // one atomic pair per wave when its lanes end on one unit (lanes without rows hold -1)
+        int umax = cur_u;
+        for (int off = 32; off > 0; off >>= 1) umax = max(umax, __shfl_xor(umax, off, 64));
+        if (__all(cur_u == umax || cur_u < 0)) {
+            for (int off = 32; off > 0; off >>= 1) {
+                dsum += __shfl_down(dsum, off, 64);
+                osum += __shfl_down(osum, off, 64);
+            }
+            if ((tid & 63) == 0 && umax >= 0) {
+                atomicAdd(change_acc + 2 * umax, dsum);
+                atomicAdd(change_acc + 2 * umax + 1, osum);
+            }
+        } else if (cur_u >= 0 && (dsum != 0 || osum != 0)) {
+            atomicAdd(change_acc + 2 * cur_u, dsum);
+            atomicAdd(change_acc + 2 * cur_u + 1, osum);
         }
     }
     __syncthreads();
@@ -627,6 +654,54 @@ __global__ void k_zero_doubles(double* p, int count) {
     for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0.0;
 }
 
+// change[0] += sum |a - b|^2, change[1] += sum |b|^2 (the relative change of an iterate a against b);
+// with commit != null also commit[i] = a[i] (commit may be b)
+template <typename R>
+__global__ void k_change_pair(const cplx_t<R>* a, const cplx_t<R>* b, int64_t count, double* __restrict__ change,
+                              const int32_t* __restrict__ gate, cplx_t<R>* commit) {
+    if (gate && *gate == 0) return;
+    double ds = 0, os = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        const cplx_t<R> u = a[i], v = b[i];
+        if (commit) commit[i] = u;
+        const double dx = (double)u.x - v.x, dy = (double)u.y - v.y;
+        ds += dx * dx + dy * dy;
+        os += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        ds += __shfl_down(ds, off, 64);
+        os += __shfl_down(os, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(change, ds);
+        atomicAdd(change + 1, os);
+    }
+}
+
+// the stop test of Algorithms S1 / S2, one thread per unit; one block
+__global__ void k_stop_test(const double* __restrict__ change, int32_t* __restrict__ active,
+                            int32_t* __restrict__ iters, double* __restrict__ rel, int n_units, double tol,
+                            int32_t* __restrict__ n_active) {
+    __shared__ int cnt[256];
+    int c = 0;
+    for (int u = threadIdx.x; u < n_units; u += blockDim.x) {
+        if (!active[u]) continue;
+        iters[u] += 1;
+        const double num = change[2 * u], den = change[2 * u + 1];
+        const double r = den > 0 ? num / den : (num > 0 ? INFINITY : 0.0);
+        rel[u] = r;
+        if (tol > 0 && r < tol) active[u] = 0;
+        else ++c;
+    }
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) cnt[threadIdx.x] += cnt[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *n_active = cnt[0];
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -698,7 +773,7 @@ hipError_t launch_fft_lines(hipStream_t st, const cplx_t<R>* in, cplx_t<R>* out,
 template <typename R>
 hipError_t launch_xupd_rows(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>* a, const cplx_t<R>* y,
                             cplx_t<R>* k, cplx_t<R>* out, const uint8_t* m, const R* rtab, const XupdRows& x,
-                            double lam, double beta, int hard_dc, double* change_acc) {
+                            double lam, double beta, int hard_dc, double* change_acc, const int32_t* active) {
     if (x.n_rows <= 0) return hipSuccess;
     FftPlan pl = make_fft_plan(x.n);
     const int NL = fft_lines_per_block<R>(pl, x.bo.es != 1 || x.out.es != 1);
@@ -708,7 +783,7 @@ hipError_t launch_xupd_rows(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>
     if (e != hipSuccess) return e;
     const int blocks = (x.n_rows + NL - 1) / NL;
     hipLaunchKernelGGL((k_xupd_rows<R>), dim3(blocks), dim3(FFT_THREADS), lds, st, bo, a, y, k, out, m, rtab, x, pl,
-                       NL, (R)lam, (R)beta, hard_dc, change_acc, 0);
+                       NL, (R)lam, (R)beta, hard_dc, change_acc, active, 0);
     return hipGetLastError();
 }
 
@@ -725,7 +800,7 @@ hipError_t launch_xupd_rows_rhs(hipStream_t st, const cplx_t<R>* bo, const cplx_
     if (e != hipSuccess) return e;
     const int blocks = (x.n_rows + NL - 1) / NL;
     hipLaunchKernelGGL((k_xupd_rows<R>), dim3(blocks), dim3(FFT_THREADS), lds, st, bo, a, y, rhs, (cplx_t<R>*)nullptr,
-                       m, rtab, x, pl, NL, (R)lam, (R)beta, 0, (double*)nullptr, 1);
+                       m, rtab, x, pl, NL, (R)lam, (R)beta, 0, (double*)nullptr, (const int32_t*)nullptr, 1);
     return hipGetLastError();
 }
 
@@ -771,6 +846,19 @@ hipError_t launch_maxabs(hipStream_t st, const cplx_t<R>* in, int64_t count, uns
 }
 hipError_t launch_zero_doubles(hipStream_t st, double* p, int count) {
     hipLaunchKernelGGL(k_zero_doubles, dim3(1), dim3(256), 0, st, p, count);
+    return hipGetLastError();
+}
+template <typename R>
+hipError_t launch_change_pair(hipStream_t st, const cplx_t<R>* a, const cplx_t<R>* b, int64_t count, double* change,
+                              const int32_t* gate, cplx_t<R>* commit) {
+    if (count <= 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>(1024, (count + 255) / 256);
+    hipLaunchKernelGGL((k_change_pair<R>), dim3(blocks), dim3(256), 0, st, a, b, count, change, gate, commit);
+    return hipGetLastError();
+}
+hipError_t launch_stop_test(hipStream_t st, const double* change, int32_t* active, int32_t* iters, double* rel,
+                            int n_units, double tol, int32_t* n_active) {
+    hipLaunchKernelGGL(k_stop_test, dim3(1), dim3(256), 0, st, change, active, iters, rel, n_units, tol, n_active);
     return hipGetLastError();
 }
 
@@ -831,7 +919,7 @@ hipError_t launch_fft_rows_apply(hipStream_t st, cplx_t<R>* io, const cplx_t<R>*
                                             const LineAddr&, int, int, int, double);                                 \
     template hipError_t launch_xupd_rows<R>(hipStream_t, const cplx_t<R>*, const cplx_t<R>*, const cplx_t<R>*,       \
                                             cplx_t<R>*, cplx_t<R>*, const uint8_t*, const R*, const XupdRows&,       \
-                                            double, double, int, double*);                                           \
+                                            double, double, int, double*, const int32_t*);                           \
     template hipError_t launch_xupd_rows_rhs<R>(hipStream_t, const cplx_t<R>*, const cplx_t<R>*, const cplx_t<R>*,   \
                                                 cplx_t<R>*, const uint8_t*, const R*, const XupdRows&, double,        \
                                                 double);                                                              \
@@ -841,6 +929,8 @@ hipError_t launch_fft_rows_apply(hipStream_t st, cplx_t<R>* io, const cplx_t<R>*
     template hipError_t launch_fill_hash<R>(hipStream_t, cplx_t<R>*, int64_t, uint64_t, double);                     \
     template hipError_t launch_maxabs<R>(hipStream_t, const cplx_t<R>*, int64_t, unsigned long long*, uint32_t*);   \
     template int spirit_fused_blocks<R>(int, int, int);                                                              \
+    template hipError_t launch_change_pair<R>(hipStream_t, const cplx_t<R>*, const cplx_t<R>*, int64_t, double*,     \
+                                              const int32_t*, cplx_t<R>*);                                           \
     template hipError_t launch_fft_rows_dir<R>(hipStream_t, cplx_t<R>*, const cplx_t<R>*, cplx_t<R>*, int, int,        \
                                                const double*, int, const double*, double*);                          \
     template hipError_t launch_spirit_cols<R>(hipStream_t, const cplx_t<R>*, cplx_t<R>*, const cplx_t<R>*, int, int, \

@@ -126,6 +126,12 @@ struct LRRun {
     int rr = -1;           // Householder reduction: 1 registers, 0 memory, -1 registers when supported
 };
 
+// complex64 data (the two mixed forms) or complex128 (the FP64 form)
+static bool prec_c64(int prec) { return prec == SHLR_PREC_MIXED || prec == SHLR_PREC_MIXED_R32; }
+static bool prec_valid(int prec) { return prec == SHLR_PREC_MIXED || prec == SHLR_PREC_FP64 || prec == SHLR_PREC_MIXED_R32; }
+// the Householder reduction in FP32 (opt-in form only)
+static bool prec_r32(int prec) { return prec == SHLR_PREC_MIXED_R32; }
+
 static int run_uses_rr(const LRRun& r, bool fp32) {
     return r.rr >= 0 ? r.rr : (tridiag_rr_supported(r.smax, fp32) ? 1 : 0);
 }
@@ -169,6 +175,7 @@ struct shlr_plan {
     bool bound = false, initialised = false;
     std::vector<double> scales;
     int64_t total_elems = 0;  // complex elements of Y
+    int n_units = 1;          // units of the relative-change stop: slices (PI) or FE positions (PARAM)
     int64_t d_block_off = 0, d_block_elems = 0;   // PI: the multipliers of all slices (complex elements)
     // reverse mode: the forward with checkpoints that the backward may follow
     int unrolled_n = 0;
@@ -231,6 +238,7 @@ static shlr_status timing_collect(shlr_plan* P) {
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static size_t scal_bytes(int n_slices, int n_units) { return (size_t)n_slices * 16 + 64 + (size_t)n_units * 32 + 64; }
 
 static size_t spirit_bytes(const shlr_plan* P);
 
@@ -238,8 +246,8 @@ static shlr_status validate(const shlr_params* p) {
     if (!p) return fail(SHLR_E_INVALID_ARG, "params is NULL");
     if (p->model != SHLR_MODEL_PI && p->model != SHLR_MODEL_PARAM)
         return fail(SHLR_E_INVALID_ARG, "model must be SHLR_MODEL_PI or SHLR_MODEL_PARAM");
-    if (p->precision != SHLR_PREC_MIXED && p->precision != SHLR_PREC_FP64)
-        return fail(SHLR_E_INVALID_ARG, "precision must be SHLR_PREC_MIXED or SHLR_PREC_FP64");
+    if (!prec_valid(p->precision))
+        return fail(SHLR_E_INVALID_ARG, "precision must be SHLR_PREC_MIXED, SHLR_PREC_FP64 or SHLR_PREC_MIXED_R32");
     if (p->n_slices < 1 || p->n_slices > SHLR_MAX_SLICES)
         return fail(SHLR_E_INVALID_ARG, "n_slices must be in [1, %d]", SHLR_MAX_SLICES);
     if (p->model == SHLR_MODEL_PARAM && p->n_slices != 1)
@@ -276,7 +284,7 @@ static shlr_status validate(const shlr_params* p) {
             return fail(SHLR_E_UNSUPPORTED, "lifted matrices with min(p, q) > 320 are not supported");
         if (std::max(pr, qr) > 4096 || std::max(pc, qc) > 4096)
             return fail(SHLR_E_UNSUPPORTED, "lifted matrices with max(p, q) > 4096 are not supported");
-        const int cs = p->precision == SHLR_PREC_MIXED ? 8 : 16;
+        const int cs = prec_c64(p->precision) ? 8 : 16;
         if (!lowrank_lds_fits(cs, V, p->J, nr, p->k_row) || !lowrank_lds_fits(cs, Vc, p->J, nc, p->k_col))
             return fail(SHLR_E_UNSUPPORTED, "slice %d: the line table of a lifted matrix (V*J*n = %d) exceeds the "
                         "LDS staging of this precision", s, V * p->J * std::max(nr, nc));
@@ -314,7 +322,7 @@ static int order_class(int s, bool fp32) { return (tridiag_rr_supported(s, fp32)
 // Groups sorted by class (stable), the descriptors laid out again in that order, so that the
 // runs formed below hold matrices of one class.
 static void order_groups(shlr_plan* P) {
-    const bool fp32 = P->p.precision == SHLR_PREC_MIXED;
+    const bool fp32 = prec_r32(P->p.precision);
     std::vector<int> idx(P->groups.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
@@ -335,7 +343,7 @@ static void order_groups(shlr_plan* P) {
 }
 
 static void layout_slots(shlr_plan* P) {
-    const bool fp32 = P->p.precision == SHLR_PREC_MIXED;
+    const bool fp32 = prec_r32(P->p.precision);
     P->runs.clear();
     P->bytes_g = P->bytes_s = P->bytes_scr = 0;
     for (int gi = 0; gi < (int)P->groups.size(); ++gi) {
@@ -375,6 +383,23 @@ static void layout_slots(shlr_plan* P) {
     }
 }
 
+extern "C" shlr_status shlr_params_default(int32_t model, shlr_params* p) {
+    if (!p) return fail(SHLR_E_INVALID_ARG, "p is NULL");
+    if (model != SHLR_MODEL_PI && model != SHLR_MODEL_PARAM)
+        return fail(SHLR_E_INVALID_ARG, "model must be SHLR_MODEL_PI or SHLR_MODEL_PARAM");
+    memset(p, 0, sizeof(*p));
+    p->model = model;
+    p->precision = SHLR_PREC_MIXED;
+    p->n_slices = 1;
+    p->use_w = 1;
+    p->normalize = 1;
+    p->max_iter = model == SHLR_MODEL_PI ? 50 : 100;   // Algorithm S1 / Algorithm S2 caps
+    p->tol = 1e-6;                                     // their relative-change tolerance
+    p->d0 = 1.0;                                       // their initial multipliers
+    p->n_cg = 10;
+    return SHLR_OK;
+}
+
 extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
     if (!out) return fail(SHLR_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -385,8 +410,8 @@ extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
     P->Ns.assign(p->N, p->N + p->n_slices);
     P->p.M = nullptr;
     P->p.N = nullptr;
-    P->csize = p->precision == SHLR_PREC_MIXED ? 8 : 16;
-    P->rsize = p->precision == SHLR_PREC_MIXED ? 4 : 8;
+    P->csize = prec_c64(p->precision) ? 8 : 16;
+    P->rsize = prec_c64(p->precision) ? 4 : 8;
     const int J = p->J, V = p->use_vc ? 2 : 1;
     int64_t c = 0, r = 0, m = 0;
     auto cal = [&](int64_t n) { int64_t o = c; c += n; c = (c + 31) & ~(int64_t)31; return o; };
@@ -570,8 +595,12 @@ extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
     off = align256(off + P->bytes_scr);
     P->off_ranks = off;
     off = align256(off + P->descs.size() * 4);
-    P->off_scal = off;   // scale (n_slices doubles), maxabs (n_slices u64), flags (u32), change (2 doubles per slice)
-    off = align256(off + (size_t)p->n_slices * 32 + 64);
+    // scale (n_slices doubles), maxabs (n_slices u64), flags (u32, 64 bytes), then per stop unit: the change
+    // pair (2 doubles), active flag and iteration count (int32 each), last relative change (double), and the
+    // count of active units
+    P->n_units = p->model == SHLR_MODEL_PI ? p->n_slices : P->Ms[0];
+    P->off_scal = off;
+    off = align256(off + scal_bytes(p->n_slices, P->n_units));
     P->off_spirit = off;
     P->bytes_spirit = spirit_bytes(P);
     off = align256(off + P->bytes_spirit);
@@ -631,7 +660,7 @@ extern "C" shlr_status shlr_bind(shlr_plan* plan, void* ws_dev, size_t bytes, vo
         (void)hipGraphExecDestroy(plan->graph_exec);
         plan->graph_exec = nullptr;
     }
-    if (plan->p.precision == SHLR_PREC_MIXED) return upload_tables<float>(plan);
+    if (prec_c64(plan->p.precision)) return upload_tables<float>(plan);
     return upload_tables<double>(plan);
 }
 
@@ -653,7 +682,11 @@ struct Ptrs {
     double* scale;
     unsigned long long* maxabs;
     uint32_t* flags;
-    double* change;
+    double* change;     // [n_units][2]: sum |K - K_prev|^2, sum |K_prev|^2
+    int32_t* active;    // [n_units]
+    int32_t* iters;     // [n_units]
+    double* rel;        // [n_units]
+    int32_t* n_active;
     explicit Ptrs(const shlr_plan* P) {
         c = (C*)(P->ws + P->off_c);
         r = (R*)(P->ws + P->off_r);
@@ -665,17 +698,22 @@ struct Ptrs {
         ranks = (int32_t*)(P->ws + P->off_ranks);
         unsigned char* sc = P->ws + P->off_scal;
         const int S = P->p.n_slices;
+        const int U = P->n_units;
         scale = (double*)sc;
         maxabs = (unsigned long long*)(sc + 8 * S);
-        change = (double*)(sc + 16 * S);
-        flags = (uint32_t*)(sc + 32 * S);
+        flags = (uint32_t*)(sc + 16 * S);
+        change = (double*)(sc + 16 * S + 64);
+        active = (int32_t*)(change + 2 * U);
+        iters = active + U;
+        rel = (double*)(iters + U);
+        n_active = (int32_t*)(rel + U);
     }
 };
 
 template <typename R>
-static shlr_status spirit_xupdate(shlr_plan* P, int si);
+static shlr_status spirit_xupdate(shlr_plan* P, int si, bool track_change);
 
-static double ortol_for(const shlr_plan* P) { return P->p.precision == SHLR_PREC_MIXED ? 1e-5 : 1e-3; }
+static double ortol_for(const shlr_plan* P) { return prec_c64(P->p.precision) ? 1e-5 : 1e-3; }
 
 template <typename R>
 static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_t<R>* bb, const cplx_t<R>* wtab,
@@ -699,11 +737,12 @@ static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_
                                            g.gram_kc));
             }
             STCHK(phase_end(P, 1, e0));
-            const int rr = run_uses_rr(run, sizeof(R) == 4);
+            const bool r32 = prec_r32(P->p.precision);
+            const int rr = run_uses_rr(run, r32);
             if (rr) {
                 STCHK(phase_begin(P, 5, &e0));
                 HIPCHK(launch_tridiag_rr(P->stream, desc_dev, c0, c1 - c0, G, run.g_stride, scr, run.scr_stride,
-                                         run.smax, sizeof(R) == 4));
+                                         run.smax, r32));
                 STCHK(phase_end(P, 5, e0));
             }
             STCHK(phase_begin(P, 2, &e0));
@@ -731,7 +770,7 @@ static shlr_status x_update_phase(shlr_plan* P, bool track_change) {
     Ptrs<R> Q(P);
     const shlr_params& p = P->p;
     const int J = p.J;
-    if (track_change) HIPCHK(launch_zero_doubles(P->stream, Q.change, 2 * p.n_slices));
+    if (track_change) HIPCHK(launch_zero_doubles(P->stream, Q.change, 2 * P->n_units));
     size_t e0 = 0;
     STCHK(phase_begin(P, 0, &e0));
     if (p.model == SHLR_MODEL_PI) {
@@ -743,7 +782,7 @@ static shlr_status x_update_phase(shlr_plan* P, bool track_change) {
             LineAddr col{0, MN, 1, N, N};
             HIPCHK(launch_fft_lines<R>(P->stream, Q.c + L.br, Q.c + L.a, col, col, M, J * N, 0, 1.0 / sqrt((double)M)));
             if (p.spirit_ksize > 0 && p.lambda1 > 0) {
-                STCHK(spirit_xupdate<R>(P, si));
+                STCHK(spirit_xupdate<R>(P, si, track_change));
             } else {
                 XupdRows x;
                 x.n = N;
@@ -761,7 +800,8 @@ static shlr_status x_update_phase(shlr_plan* P, bool track_change) {
                 x.rc_off = L.rc;
                 HIPCHK(launch_xupd_rows<R>(P->stream, Q.c + L.bct, Q.c + L.a, Q.c + L.yn, Q.c + L.k, Q.c + L.hct,
                                            Q.m + L.mask_b, Q.r, x, p.lambda, p.beta, p.hard_dc,
-                                           track_change ? Q.change + 2 * si : nullptr));
+                                           track_change ? Q.change + 2 * si : nullptr,
+                                           track_change ? Q.active + si : nullptr));
             }
             // H_row = F_m^-1(K)
             HIPCHK(launch_fft_lines<R>(P->stream, Q.c + L.k, Q.c + L.hr, col, col, M, J * N, 1, 1.0 / sqrt((double)M)));
@@ -783,9 +823,10 @@ static shlr_status x_update_phase(shlr_plan* P, bool track_change) {
         x.msk = RowAddr{0, N, 0, 1};
         x.rr_off = L.rr;
         x.rc_off = L.rc;
+        x.unit_digit = 2;   // one stop unit per FE position (Algorithm S2)
         HIPCHK(launch_xupd_rows<R>(P->stream, Q.c + L.be, Q.c + L.bp, Q.c + L.yn, Q.c + L.k, Q.c + L.xe,
                                    Q.m + L.mask_b, Q.r, x, p.lambda, p.beta, p.hard_dc,
-                                   track_change ? Q.change : nullptr));
+                                   track_change ? Q.change : nullptr, track_change ? Q.active : nullptr));
     }
     STCHK(phase_end(P, 0, e0));
     return SHLR_OK;
@@ -797,11 +838,18 @@ static shlr_status lowrank_phase(shlr_plan* P) {
     return run_lowrank<R>(P, Q.c, Q.c, Q.c, Q.c, Q.desc, Q.g, Q.s, Q.scr, Q.ranks, Q.flags);
 }
 
-// One iteration of Algorithm S1 / S2: X-update, then the Z and multiplier updates.
+// One iteration of Algorithm S1 / S2: X-update, then the Z and multiplier updates.  With the
+// relative-change stop on, the X-update of a unit (slice or FE position) that has stopped keeps its
+// K, and the stop test after the multiplier updates retires the units whose change fell below tol.
 template <typename R>
 static shlr_status iterate_once(shlr_plan* P, bool track_change) {
     STCHK(x_update_phase<R>(P, track_change));
-    return lowrank_phase<R>(P);
+    STCHK(lowrank_phase<R>(P));
+    if (track_change) {
+        Ptrs<R> Q(P);
+        HIPCHK(launch_stop_test(P->stream, Q.change, Q.active, Q.iters, Q.rel, P->n_units, P->p.tol, Q.n_active));
+    }
+    return SHLR_OK;
 }
 
 template <typename R>
@@ -811,7 +859,13 @@ static shlr_status init_impl(shlr_plan* P, const void* y_dev, const uint8_t* mas
     const shlr_params& p = P->p;
     const int J = p.J;
     const C* Y = (const C*)y_dev;
-    HIPCHK(hipMemsetAsync(P->ws + P->off_scal, 0, (size_t)p.n_slices * 32 + 64, P->stream));
+    HIPCHK(hipMemsetAsync(P->ws + P->off_scal, 0, scal_bytes(p.n_slices, P->n_units), P->stream));
+    {
+        // every unit starts active (Algorithm S1 / S2 iterate until their own stop test)
+        std::vector<int32_t> ones(P->n_units, 1);
+        HIPCHK(hipMemcpyAsync(Q.active, ones.data(), ones.size() * 4, hipMemcpyHostToDevice, P->stream));
+        HIPCHK(hipStreamSynchronize(P->stream));
+    }
     if (p.model == SHLR_MODEL_PI) {
         int64_t yoff = 0, moff = 0;
         for (int si = 0; si < p.n_slices; ++si) {
@@ -900,46 +954,73 @@ extern "C" shlr_status shlr_init(shlr_plan* plan, const void* y_dev, const uint8
     if (!plan) return fail(SHLR_E_INVALID_ARG, "plan is NULL");
     if (!plan->bound) return fail(SHLR_E_WORKSPACE, "no workspace bound");
     if (!y_dev || !mask_dev) return fail(SHLR_E_INVALID_ARG, "NULL data pointer");
-    if (plan->p.precision == SHLR_PREC_MIXED) return init_impl<float>(plan, y_dev, mask_dev);
+    if (prec_c64(plan->p.precision)) return init_impl<float>(plan, y_dev, mask_dev);
     return init_impl<double>(plan, y_dev, mask_dev);
+}
+
+// Read the per-unit stop state back and fill info (synchronises the stream).
+template <typename R>
+static shlr_status fill_info(shlr_plan* P, bool track, const std::vector<int32_t>& iters_before, int ran,
+                             shlr_info* info) {
+    Ptrs<R> Q(P);
+    const int U = P->n_units;
+    uint32_t fl = 0;
+    std::vector<int32_t> it(U), act(U);
+    std::vector<double> rel(U);
+    HIPCHK(hipMemcpyAsync(&fl, Q.flags, 4, hipMemcpyDeviceToHost, P->stream));
+    if (track) {
+        HIPCHK(hipMemcpyAsync(it.data(), Q.iters, 4 * U, hipMemcpyDeviceToHost, P->stream));
+        HIPCHK(hipMemcpyAsync(act.data(), Q.active, 4 * U, hipMemcpyDeviceToHost, P->stream));
+        HIPCHK(hipMemcpyAsync(rel.data(), Q.rel, 8 * U, hipMemcpyDeviceToHost, P->stream));
+    }
+    HIPCHK(hipStreamSynchronize(P->stream));
+    info->iters_done = ran;
+    info->converged = 0;
+    info->rel_change = 0;
+    if (track) {
+        int most = 0, still = 0;
+        double worst = 0;
+        for (int u = 0; u < U; ++u) {
+            most = std::max(most, it[u] - (iters_before.empty() ? 0 : iters_before[u]));
+            still += act[u] != 0;
+            worst = std::max(worst, rel[u]);
+        }
+        info->iters_done = most;
+        info->converged = still == 0;
+        info->rel_change = worst;
+    }
+    info->scale = P->scales[0];
+    info->device_flags = fl;
+    if (fl & 1u) return fail(SHLR_E_NONFINITE, "a non-finite value was met during the iterations");
+    return SHLR_OK;
 }
 
 template <typename R>
 static shlr_status iterate_impl(shlr_plan* P, int n, shlr_info* info) {
     Ptrs<R> Q(P);
     const bool track = P->p.tol > 0;
+    std::vector<int32_t> before;
+    if (track && info) {
+        before.resize(P->n_units);
+        HIPCHK(hipMemcpyAsync(before.data(), Q.iters, 4 * before.size(), hipMemcpyDeviceToHost, P->stream));
+        HIPCHK(hipStreamSynchronize(P->stream));
+    }
+    // The stop decision stays on the device (units that stopped keep their K); the host looks at the
+    // count of active units only every STOP_POLL iterations, to end the loop once all have stopped.
+    constexpr int STOP_POLL = 8;
     int done = 0;
-    bool conv = false;
-    double last = 0;
     for (int it = 0; it < n; ++it) {
         STCHK(iterate_once<R>(P, track));
         ++done;
-        if (track) {
-            std::vector<double> ch(2 * P->p.n_slices);
-            HIPCHK(hipMemcpyAsync(ch.data(), Q.change, ch.size() * 8, hipMemcpyDeviceToHost, P->stream));
+        if (track && (done % STOP_POLL == 0) && done < n) {
+            int32_t na = 1;
+            HIPCHK(hipMemcpyAsync(&na, Q.n_active, 4, hipMemcpyDeviceToHost, P->stream));
             HIPCHK(hipStreamSynchronize(P->stream));
-            double worst = 0;
-            for (int s = 0; s < P->p.n_slices; ++s)
-                worst = std::max(worst, ch[2 * s + 1] > 0 ? ch[2 * s] / ch[2 * s + 1] : INFINITY);
-            last = worst;
-            if (worst < P->p.tol) {
-                conv = true;
-                break;
-            }
+            if (na == 0) break;
         }
     }
     P->iters_total += done;
-    if (info) {
-        uint32_t fl = 0;
-        HIPCHK(hipMemcpyAsync(&fl, Q.flags, 4, hipMemcpyDeviceToHost, P->stream));
-        HIPCHK(hipStreamSynchronize(P->stream));
-        info->iters_done = done;
-        info->converged = conv;
-        info->rel_change = last;
-        info->scale = P->scales[0];
-        info->device_flags = fl;
-        if (fl & 1u) return fail(SHLR_E_NONFINITE, "a non-finite value was met during the iterations");
-    }
+    if (info) STCHK(fill_info<R>(P, track, before, done, info));
     return SHLR_OK;
 }
 
@@ -985,7 +1066,7 @@ extern "C" shlr_status shlr_iterate(shlr_plan* plan, int32_t n, shlr_info* info)
     if (n < 0) return fail(SHLR_E_INVALID_ARG, "n must be >= 0");
     if (plan->p.spirit_ksize > 0 && plan->p.lambda1 > 0 && !plan->spirit_ready)
         return fail(SHLR_E_STATE, "the SPIRiT kernel is not set (shlr_set_spirit_kernel / shlr_calibrate_spirit)");
-    if (plan->p.precision == SHLR_PREC_MIXED) return iterate_impl<float>(plan, n, info);
+    if (prec_c64(plan->p.precision)) return iterate_impl<float>(plan, n, info);
     return iterate_impl<double>(plan, n, info);
 }
 
@@ -995,14 +1076,19 @@ static shlr_status build_graph(shlr_plan* P) {
     hipStream_t user = P->stream;
     P->stream = P->cap_stream;
     hipGraph_t graph = nullptr;
+    // no timing events go into the graph: captured events cannot be read back as phase times
+    const bool timing = P->timing;
+    P->timing = false;
     hipError_t e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
         P->stream = user;
+        P->timing = timing;
         return fail(SHLR_E_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
     }
-    shlr_status st = iterate_once<R>(P, false);
+    shlr_status st = iterate_once<R>(P, P->p.tol > 0);
     e = hipStreamEndCapture(P->cap_stream, &graph);
     P->stream = user;
+    P->timing = timing;
     if (st != SHLR_OK) {
         if (graph) (void)hipGraphDestroy(graph);
         return st;
@@ -1024,23 +1110,39 @@ extern "C" shlr_status shlr_iterate_graph(shlr_plan* plan, int32_t n, shlr_info*
     if (plan->p.spirit_ksize > 0 && plan->p.lambda1 > 0 && !plan->spirit_ready)
         return fail(SHLR_E_STATE, "the SPIRiT kernel is not set");
     if (!plan->graph_exec) {
-        if (plan->p.precision == SHLR_PREC_MIXED) STCHK(build_graph<float>(plan));
+        if (prec_c64(plan->p.precision)) STCHK(build_graph<float>(plan));
         else STCHK(build_graph<double>(plan));
+    }
+    const bool track = plan->p.tol > 0;
+    std::vector<int32_t> before;
+    if (track && info) {
+        before.resize(plan->n_units);
+        const size_t off = plan->off_scal + 16 * (size_t)plan->p.n_slices + 64 + 16 * (size_t)plan->n_units +
+                           4 * (size_t)plan->n_units;   // the iteration counts (layout of Ptrs)
+        HIPCHK(hipMemcpyAsync(before.data(), plan->ws + off, 4 * before.size(), hipMemcpyDeviceToHost, plan->stream));
+        HIPCHK(hipStreamSynchronize(plan->stream));
     }
     for (int i = 0; i < n; ++i) HIPCHK(hipGraphLaunch(plan->graph_exec, plan->stream));
     plan->iters_total += n;
     if (info) {
-        uint32_t fl = 0;
-        HIPCHK(hipMemcpyAsync(&fl, plan->ws + plan->off_scal + 32 * plan->p.n_slices, 4, hipMemcpyDeviceToHost,
-                              plan->stream));
-        HIPCHK(hipStreamSynchronize(plan->stream));
-        info->iters_done = n;
-        info->converged = 0;
-        info->rel_change = 0;
-        info->scale = plan->scales[0];
-        info->device_flags = fl;
-        if (fl & 1u) return fail(SHLR_E_NONFINITE, "a non-finite value was met during the iterations");
+        if (prec_c64(plan->p.precision)) STCHK(fill_info<float>(plan, track, before, n, info));
+        else STCHK(fill_info<double>(plan, track, before, n, info));
     }
+    return SHLR_OK;
+}
+
+extern "C" shlr_status shlr_unit_status(const shlr_plan* plan, int32_t n_units, int32_t* iters_host,
+                                        double* rel_host, int32_t* active_host) {
+    if (!plan) return fail(SHLR_E_INVALID_ARG, "plan is NULL");
+    if (!plan->initialised) return fail(SHLR_E_STATE, "shlr_init must come first");
+    if (n_units != plan->n_units)
+        return fail(SHLR_E_INVALID_ARG, "the plan has %d stop units, %d given", plan->n_units, n_units);
+    const size_t U = (size_t)plan->n_units;
+    const unsigned char* base = plan->ws + plan->off_scal + 16 * (size_t)plan->p.n_slices + 64 + 16 * U;
+    if (active_host) HIPCHK(hipMemcpyAsync(active_host, base, 4 * U, hipMemcpyDeviceToHost, plan->stream));
+    if (iters_host) HIPCHK(hipMemcpyAsync(iters_host, base + 4 * U, 4 * U, hipMemcpyDeviceToHost, plan->stream));
+    if (rel_host) HIPCHK(hipMemcpyAsync(rel_host, base + 8 * U, 8 * U, hipMemcpyDeviceToHost, plan->stream));
+    HIPCHK(hipStreamSynchronize(plan->stream));
     return SHLR_OK;
 }
 
@@ -1075,7 +1177,7 @@ extern "C" shlr_status shlr_get_kspace(const shlr_plan* plan, void* k_out_dev) {
     if (!plan) return fail(SHLR_E_INVALID_ARG, "plan is NULL");
     if (!plan->initialised) return fail(SHLR_E_STATE, "shlr_init must come first");
     if (!k_out_dev) return fail(SHLR_E_INVALID_ARG, "k_out is NULL");
-    if (plan->p.precision == SHLR_PREC_MIXED) return get_impl<float>(plan, k_out_dev);
+    if (prec_c64(plan->p.precision)) return get_impl<float>(plan, k_out_dev);
     return get_impl<double>(plan, k_out_dev);
 }
 
@@ -1094,14 +1196,14 @@ extern "C" shlr_status shlr_reconstruct(shlr_plan* plan, const void* y_dev, cons
 
 extern "C" shlr_status shlr_fft_lines(int32_t precision, int32_t n, int32_t n_lines, int32_t inverse,
                                       const void* in_dev, void* out_dev, void* stream) {
-    if (precision != SHLR_PREC_MIXED && precision != SHLR_PREC_FP64) return fail(SHLR_E_INVALID_ARG, "bad precision");
+    if (!prec_valid(precision)) return fail(SHLR_E_INVALID_ARG, "bad precision");
     if (n < 1 || n > 4096) return fail(SHLR_E_INVALID_ARG, "n must be in [1, 4096]");
     if (n_lines < 0) return fail(SHLR_E_INVALID_ARG, "n_lines must be >= 0");
     if (n_lines == 0) return SHLR_OK;
     if (!in_dev || !out_dev) return fail(SHLR_E_INVALID_ARG, "NULL pointer");
     LineAddr a{0, n, 0, 1, 1};
     const double sc = 1.0 / sqrt((double)n);
-    if (precision == SHLR_PREC_MIXED)
+    if (prec_c64(precision))
         HIPCHK(launch_fft_lines<float>((hipStream_t)stream, (const float2*)in_dev, (float2*)out_dev, a, a, n, n_lines,
                                        inverse, sc));
     else
@@ -1118,13 +1220,13 @@ struct LRLayout {
 
 static shlr_status lr_layout(int32_t precision, int32_t n_mat, int32_t J, int32_t n, int32_t k, int32_t use_vc,
                              LRLayout* L) {
-    if (precision != SHLR_PREC_MIXED && precision != SHLR_PREC_FP64) return fail(SHLR_E_INVALID_ARG, "bad precision");
+    if (!prec_valid(precision)) return fail(SHLR_E_INVALID_ARG, "bad precision");
     if (n_mat < 0 || J < 1 || n < 1 || k < 1 || k > n) return fail(SHLR_E_INVALID_ARG, "bad shape");
     LRDesc d = make_desc(0, 0, 0, 0, 0, 0, 0, n, k, J, use_vc ? 2 : 1, 0, 0, 0.0);
     const int s = lr_s(d);
     if (s > 320) return fail(SHLR_E_UNSUPPORTED, "min(p, q) > 320");
     if (lr_l(d) > 4096) return fail(SHLR_E_UNSUPPORTED, "max(p, q) > 4096");
-    const int cs = precision == SHLR_PREC_MIXED ? 8 : 16;
+    const int cs = prec_c64(precision) ? 8 : 16;
     if (!lowrank_lds_fits(cs, use_vc ? 2 : 1, J, n, k))
         return fail(SHLR_E_UNSUPPORTED, "the line table of a lifted matrix (V*J*n) exceeds the LDS staging");
     L->s = s;
@@ -1160,7 +1262,7 @@ extern "C" shlr_status shlr_lowrank_workspace_size(int32_t precision, int32_t n_
 }
 
 template <typename R>
-static shlr_status lowrank_impl(int32_t n_mat, int32_t J, int32_t n, int32_t k, int32_t use_vc, int32_t use_w,
+static shlr_status lowrank_impl(int32_t precision, int32_t n_mat, int32_t J, int32_t n, int32_t k, int32_t use_vc, int32_t use_w,
                                 double beta, double tau, double thr, const void* h_dev, void* d_dev, void* b_dev,
                                 int32_t* ranks_dev, unsigned char* ws, const LRLayout& L, hipStream_t st) {
     using C = cplx_t<R>;
@@ -1187,7 +1289,7 @@ static shlr_status lowrank_impl(int32_t n_mat, int32_t J, int32_t n, int32_t k, 
     shlr_plan tmp;
     tmp.p.beta = beta;
     tmp.p.tau = tau;
-    tmp.p.precision = sizeof(R) == 4 ? SHLR_PREC_MIXED : SHLR_PREC_FP64;
+    tmp.p.precision = precision;
     tmp.stream = st;
     tmp.groups = {g};
     LRRun run{};
@@ -1219,10 +1321,10 @@ extern "C" shlr_status shlr_lowrank_lines(int32_t precision, int32_t n_mat, int3
     if (!h_dev || !d_dev || !b_dev) return fail(SHLR_E_INVALID_ARG, "NULL data pointer");
     if (!ws_dev || ws_bytes < L.total) return fail(SHLR_E_WORKSPACE, "workspace too small (%zu < %zu)", ws_bytes, L.total);
     if (((uintptr_t)ws_dev) & 255) return fail(SHLR_E_WORKSPACE, "workspace must be 256-byte aligned");
-    if (precision == SHLR_PREC_MIXED)
-        return lowrank_impl<float>(n_mat, J, n, k, use_vc, use_w, beta, tau, thr, h_dev, d_dev, b_dev, ranks_dev,
+    if (prec_c64(precision))
+        return lowrank_impl<float>(precision, n_mat, J, n, k, use_vc, use_w, beta, tau, thr, h_dev, d_dev, b_dev, ranks_dev,
                                    (unsigned char*)ws_dev, L, (hipStream_t)stream);
-    return lowrank_impl<double>(n_mat, J, n, k, use_vc, use_w, beta, tau, thr, h_dev, d_dev, b_dev, ranks_dev,
+    return lowrank_impl<double>(precision, n_mat, J, n, k, use_vc, use_w, beta, tau, thr, h_dev, d_dev, b_dev, ranks_dev,
                                 (unsigned char*)ws_dev, L, (hipStream_t)stream);
 }
 

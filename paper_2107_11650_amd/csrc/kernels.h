@@ -35,6 +35,7 @@ struct RowAddr {
 struct XupdRows {
     int n, n1, n0, n_rows;
     int rc_digit;                   // which digit indexes the rc table
+    int unit_digit = -1;            // stop-test unit of a row: digit d2 when 2, else unit 0
     RowAddr bo, a, y, k, out, msk;  // msk counts bytes
     int64_t rr_off, rc_off;         // offsets into the real table
 };
@@ -47,7 +48,8 @@ hipError_t launch_fft_lines(hipStream_t st, const cplx_t<R>* in, cplx_t<R>* out,
 template <typename R>
 hipError_t launch_xupd_rows(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>* a, const cplx_t<R>* y,
                             cplx_t<R>* k, cplx_t<R>* out, const uint8_t* m, const R* rtab, const XupdRows& x,
-                            double lam, double beta, int hard_dc, double* change_acc);
+                            double lam, double beta, int hard_dc, double* change_acc,
+                            const int32_t* active = nullptr);
 template <typename R>
 hipError_t launch_xupd_rows_rhs(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>* a, const cplx_t<R>* y,
                                 cplx_t<R>* rhs, const uint8_t* m, const R* rtab, const XupdRows& x, double lam,
@@ -79,6 +81,16 @@ hipError_t launch_fill_hash(hipStream_t st, cplx_t<R>* out, int64_t count, uint6
 template <typename R>
 hipError_t launch_maxabs(hipStream_t st, const cplx_t<R>* in, int64_t count, unsigned long long* out, uint32_t* flags);
 hipError_t launch_zero_doubles(hipStream_t st, double* p, int count);
+// change[0] += sum |a - b|^2, change[1] += sum |b|^2 over count elements, and commit[i] = a[i] when commit is
+// not null (it may be b); nothing happens when gate is not null and *gate == 0
+template <typename R>
+hipError_t launch_change_pair(hipStream_t st, const cplx_t<R>* a, const cplx_t<R>* b, int64_t count, double* change,
+                              const int32_t* gate, cplx_t<R>* commit = nullptr);
+// Relative-change stop of Algorithms S1 / S2 for n_units independent units: for every active unit,
+// iters += 1, rel = change[2u] / change[2u + 1] and the unit stops (active = 0) when rel < tol; the
+// number of units still active goes to *n_active.
+hipError_t launch_stop_test(hipStream_t st, const double* change, int32_t* active, int32_t* iters, double* rel,
+                            int n_units, double tol, int32_t* n_active);
 
 template <typename R>
 hipError_t launch_lift_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* wtab,

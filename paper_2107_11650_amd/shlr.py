@@ -25,6 +25,7 @@ MODEL_PI = 0
 MODEL_PARAM = 1
 PREC_MIXED = 0
 PREC_FP64 = 1
+PREC_MIXED_R32 = 2   # opt-in: FP32 Householder reduction (see include/shlr.h)
 
 STATUS = {
     0: "SHLR_OK", 1: "SHLR_E_INVALID_ARG", 2: "SHLR_E_SINGULAR", 3: "SHLR_E_NONFINITE",
@@ -37,6 +38,7 @@ EXPORTED = [
     "shlr_reconstruct", "shlr_fft_lines", "shlr_lowrank_workspace_size", "shlr_lowrank_lines",
     "shlr_last_error", "shlr_version", "shlr_timing_enable", "shlr_timing_enable_phases", "shlr_timing_read",
     "shlr_unrolled_sizes", "shlr_unrolled_forward", "shlr_unrolled_backward", "shlr_autotune",
+    "shlr_params_default", "shlr_unit_status",
 ]
 TIMING_PHASES = ("xupdate", "gram", "eig", "reproj", "spirit", "tridiag")
 
@@ -88,6 +90,8 @@ _lib.shlr_unrolled_forward.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, ctypes.c_s
 _lib.shlr_unrolled_backward.argtypes = [_vp, _i32, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp,
                                         ctypes.POINTER(ctypes.c_double)]
 _lib.shlr_autotune.argtypes = [_vp, _i32, ctypes.c_char_p, ctypes.c_size_t]
+_lib.shlr_params_default.argtypes = [_i32, _vp]
+_lib.shlr_unit_status.argtypes = [_vp, _i32, _vp, _vp, _vp]
 _lib.shlr_timing_enable.argtypes = [_vp, _i32]
 _lib.shlr_timing_enable_phases.argtypes = [_vp, ctypes.c_uint32]
 _lib.shlr_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
@@ -149,6 +153,18 @@ class Params:
                     tol=self.tol, d0=self.d0)
         return c, (Ma, Na)
 
+    @classmethod
+    def paper_defaults(cls, model=MODEL_PI, **fields):
+        """Params holding the library's defaults for a model (shlr_params_default: the iteration cap,
+        tolerance and initial multipliers of Algorithms S1 / S2), then the given fields."""
+        c = CParams()
+        _check(_lib.shlr_params_default(int(model), ctypes.byref(c)))
+        base = dict(model=c.model, precision=c.precision, use_vc=bool(c.use_vc), use_w=bool(c.use_w),
+                    spirit_ksize=c.spirit_ksize, hard_dc=bool(c.hard_dc), normalize=bool(c.normalize),
+                    max_iter=c.max_iter, n_cg=c.n_cg, tol=c.tol, d0=c.d0)
+        base.update(fields)
+        return cls(**base)
+
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
@@ -180,7 +196,7 @@ class Plan:
     @property
     def cdtype(self):
         import torch
-        return torch.complex64 if self.params.precision == PREC_MIXED else torch.complex128
+        return torch.complex128 if self.params.precision == PREC_FP64 else torch.complex64
 
     def _prep(self, y, mask):
         import torch
@@ -210,6 +226,18 @@ class Plan:
     def iterate_async(self, n, graph=False):
         f = _lib.shlr_iterate_graph if graph else _lib.shlr_iterate
         _check(f(self._h, int(n), None))
+
+    def unit_status(self):
+        """Per stop unit (slice, or FE position of the parameter model): (iterations run, last relative
+        change, still active) as numpy arrays."""
+        import numpy as np
+        n = len(self.params.M) if self.params.model == MODEL_PI else int(self.params.M[0])
+        it = np.zeros(n, dtype=np.int32)
+        rel = np.zeros(n, dtype=np.float64)
+        act = np.zeros(n, dtype=np.int32)
+        _check(_lib.shlr_unit_status(self._h, n, it.ctypes.data_as(ctypes.c_void_p),
+                                     rel.ctypes.data_as(ctypes.c_void_p), act.ctypes.data_as(ctypes.c_void_p)))
+        return it, rel, act.astype(bool)
 
     def autotune(self, reps=3):
         """Time the launch choices on this plan's shapes and keep the fastest; returns the report.
@@ -330,13 +358,14 @@ def lowrank_workspace_size(precision, n_mat, J, n, k, use_vc):
     return nb.value
 
 
-def lowrank_lines(h, D, k, beta, tau, thr, use_vc=False, use_w=True, ranks=False):
+def lowrank_lines(h, D, k, beta, tau, thr, use_vc=False, use_w=True, ranks=False, r32=False):
     """One Z/D step on a batch of lines (see shlr_lowrank_lines). D is updated in place.
 
     h: (B, J, n) complex; D: (B, p, q) complex.  Returns b (B, J, n) [and ranks (B,)].
+    r32 (complex64 only): the opt-in FP32 Householder reduction (SHLR_PREC_MIXED_R32).
     """
     import torch
-    prec = PREC_MIXED if h.dtype == torch.complex64 else PREC_FP64
+    prec = (PREC_MIXED_R32 if r32 else PREC_MIXED) if h.dtype == torch.complex64 else PREC_FP64
     B, J, n = h.shape
     assert D.is_contiguous() and h.is_contiguous()
     nb = lowrank_workspace_size(prec, B, J, n, k, use_vc)

@@ -85,7 +85,7 @@ LR_CASES = [
 
 
 @pytest.mark.parametrize("case", LR_CASES, ids=lambda c: f"B{c[0]}J{c[1]}n{c[2]}k{c[3]}vc{int(c[4])}")
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_r32"])
 def test_lowrank_step(case, prec):
     shlr = _lib()
     B, J, n, k, vc, use_w = case
@@ -106,7 +106,8 @@ def test_lowrank_step(case, prec):
     Dn_ref, b_ref = O.lowrank_step(lift, h, D, beta, tau, thr)
     dt = torch.complex128 if prec == "fp64" else torch.complex64
     hd, Dd = dev(h, dt), dev(D, dt)
-    b, ranks = shlr.lowrank_lines(hd, Dd, k, beta, tau, thr, use_vc=vc, use_w=use_w, ranks=True)
+    b, ranks = shlr.lowrank_lines(hd, Dd, k, beta, tau, thr, use_vc=vc, use_w=use_w, ranks=True,
+                                  r32=prec == "mixed_r32")
     torch.cuda.synchronize()
     e_d, e_b = nmse(host(Dd), Dn_ref), nmse(host(b), b_ref)
     rk_ref = (s > thr).sum(-1)
