@@ -115,6 +115,7 @@ def _raw_plan(shlr, **kw):
     (dict(normalize=False, hard_dc=True), False),          # lambda = inf has no lambda derivative
     (dict(normalize=False, spirit_ksize=5, lambda1=1.0), False),
     (dict(normalize=False, model=1, M=(8,), N=(64,), L=8, k_col=4), False),
+    (dict(normalize=False, precision=2), False),           # the opt-in FP32 reduction: not differentiated
 ])
 def test_unrolled_scope_and_sizes(kw, ok):
     import ctypes
@@ -131,5 +132,33 @@ def test_unrolled_scope_and_sizes(kw, ok):
         else:
             assert st == 6, shlr.library().shlr_last_error()
         assert shlr.library().shlr_unrolled_sizes(h, 0, ctypes.byref(ck), ctypes.byref(wk)) != 0
+    finally:
+        shlr.library().shlr_plan_destroy(h)
+
+
+def test_library_defaults_are_the_papers():
+    # shlr_params_default against the values Algorithms S1 / S2 print (tests/golden/paper_constants.json)
+    import json
+    from paper_2107_11650_amd import shlr
+    with open(os.path.join(ROOT, "tests", "golden", "paper_constants.json")) as f:
+        c = json.load(f)
+    pi = shlr.Params.paper_defaults(shlr.MODEL_PI)
+    pa = shlr.Params.paper_defaults(shlr.MODEL_PARAM)
+    assert pi.max_iter == c["alg_s1_caps"]["max_iter"] and pi.tol == c["alg_s1_caps"]["tol"]
+    assert pa.max_iter == c["alg_s2_caps"]["max_iter"] and pa.tol == c["alg_s2_caps"]["tol"]
+    assert pi.d0 == pa.d0 == c["alg_init"]["d0"]
+    assert pi.precision == shlr.PREC_MIXED and pi.use_w and pi.normalize and not pi.use_vc
+    with pytest.raises(shlr.ShlrError):
+        shlr.Params.paper_defaults(7)
+
+
+def test_unit_status_needs_an_initialised_plan():
+    import ctypes
+    from paper_2107_11650_amd import shlr
+    h, keep = _raw_plan(shlr, M=(40, 64), N=(48, 32), J=2, k_row=5, k_col=5)
+    try:
+        it = (ctypes.c_int32 * 2)()
+        st = shlr.library().shlr_unit_status(h, 2, it, None, None)
+        assert st == 7, shlr.library().shlr_last_error()      # SHLR_E_STATE: no shlr_init yet
     finally:
         shlr.library().shlr_plan_destroy(h)

@@ -352,3 +352,171 @@ def test_param_oracle_fe_subset_matches_full_run():
     hyb = np.transpose(O.ifftc(full, axis=2), (2, 0, 1, 3))          # (M, L, J, N)
     sub = O.shlr_param(Y, mask, prm, fe_positions=[1, 4])
     assert rel(sub, hyb[[1, 4]]) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# SPIRiT over whole iterations, and the calibration (Eq. 3)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("vc", [False, True])
+def test_spirit_iterations_match_brute_force(vc):
+    # SHLR-S / SHLR-SV: the oracle's PCG X-update (run to convergence) inside whole ADMM iterations
+    # against the dense solve of the brute force, 6 iterations on 8 x 8 k-space
+    Y, mask = _tiny_pi(seed=2)
+    g = inputs.random_complex((2, 2, 3, 3), seed=41) * 0.2
+    for t in range(2):
+        g[t, t, 1, 1] = 0
+    prm = O.PIParams(k_row=3, k_col=3, lam=20.0, lam1=5.0, beta=1.0, vc=vc, n_cg=100, iters=6, normalize=False)
+    K = O.shlr_pi(Y, mask, prm, g=g)
+    Kb = brute.BrutePI(Y, mask, 3, 3, 20.0, 5.0, 1.0, 1.0, vc, g=g).run(6)
+    assert O.nmse(K, Kb) < 1e-20
+
+
+def _shift_conv(K, a):
+    """out(x) = sum_d a[d] K(x + d) with d = (dm - h, dn - h), circular (the relation Eq. 3 states)."""
+    h = a.shape[-1] // 2
+    out = np.zeros_like(K)
+    for dm in range(a.shape[0]):
+        for dn in range(a.shape[1]):
+            out = out + a[dm, dn] * np.roll(K, shift=(-(dm - h), -(dn - h)), axis=(-2, -1))
+    return out
+
+
+def _planted(M, N, acs, ks, tgt):
+    # two coils: the target coil is exactly a planted 5x5 convolution of the other coil inside the
+    # centred acs x acs block (a window shifted by one sample sees the perturbed outside)
+    base = inputs.random_complex((M, N), seed=51)
+    a = inputs.random_complex((ks, ks), seed=52) * 0.3
+    K = np.stack([_shift_conv(base, a), base]) if tgt == 0 else np.stack([base, _shift_conv(base, a)])
+    cm, cn = M // 2, N // 2
+    inside = np.zeros((M, N), dtype=bool)
+    inside[cm - acs // 2: cm - acs // 2 + acs, cn - acs // 2: cn - acs // 2 + acs] = True
+    K[1 - tgt][~inside] += inputs.random_complex(((~inside).sum(),), seed=54)
+    gp = np.zeros((2, 2, ks, ks), dtype=np.complex128)
+    gp[tgt, 1 - tgt] = a
+    return K, gp
+
+
+@pytest.mark.parametrize("shape", [(40, 36), (41, 37)])
+@pytest.mark.parametrize("tgt", [0, 1])
+def test_spirit_calibration_recovers_planted_kernel(shape, tgt):
+    M, N = shape
+    K, gp = _planted(M, N, 24, 5, tgt)
+    g = O.spirit_calibrate(K, acs=24, ks=5, reg=0.0)
+    assert np.abs(g[tgt] - gp[tgt]).max() < 1e-10
+    # the same data one sample off the centred block no longer fit the planted kernel
+    for sh in ((1, 0), (0, 1), (-1, 0), (0, -1)):
+        g2 = O.spirit_calibrate(np.roll(K, shift=sh, axis=(1, 2)), acs=24, ks=5, reg=0.0)
+        assert np.abs(g2[tgt] - gp[tgt]).max() > 1e-3
+
+
+def test_spirit_calibration_is_the_tikhonov_minimiser():
+    # with reg > 0 each target's kernel is a stationary point of
+    # sum_x |K_t(x) - sum_{s,d} g K_s(x + d)|^2 + mu |g|^2 over the fit positions, mu = reg tr(A^H A) / n,
+    # checked through the gradient formed with circular shifts (not the calibration's matrix)
+    J, M, N, acs, ks, reg = 3, 32, 30, 20, 5, 1e-2
+    K = inputs.phantom_kspace(J, M, N, seed=1005)
+    K = K / np.abs(K).max()
+    g = O.spirit_calibrate(K, acs=acs, ks=ks, reg=reg)
+    h = ks // 2
+    cm, cn = M // 2, N // 2
+    fit = np.zeros((M, N), dtype=bool)
+    fit[cm - acs // 2 + h: cm - acs // 2 + acs - h, cn - acs // 2 + h: cn - acs // 2 + acs - h] = True
+    for t in range(J):
+        r = K[t] - sum(_shift_conv(K[s], g[t, s]) for s in range(J))
+        grad = np.zeros((J, ks, ks), dtype=np.complex128)
+        energy = 0.0
+        for s in range(J):
+            for dm in range(ks):
+                for dn in range(ks):
+                    if s == t and dm == h and dn == h:
+                        continue
+                    src = np.roll(K[s], shift=(-(dm - h), -(dn - h)), axis=(0, 1))[fit]
+                    grad[s, dm, dn] = np.vdot(src, r[fit])          # sum_x conj(K_s(x+d)) r(x)
+                    energy += np.vdot(src, src).real
+        n_unk = J * ks * ks - 1
+        mu = reg * energy / n_unk
+        keep = np.ones((J, ks, ks), dtype=bool)
+        keep[t, h, h] = False
+        assert rel(grad[keep], mu * g[t][keep]) < 1e-9
+        assert g[t, t, h, h] == 0
+
+
+# --------------------------------------------------------------------------
+# the relative-change stop of Algorithms S1 / S2
+# --------------------------------------------------------------------------
+
+def _stop_rule(Ks, tol):
+    """First k (1-based) with ||K^k - K^{k-1}||^2 / ||K^{k-1}||^2 < tol, from the list [K^0, K^1, ...]."""
+    for k in range(1, len(Ks)):
+        d = np.sum(np.abs(Ks[k] - Ks[k - 1]) ** 2)
+        if d / np.sum(np.abs(Ks[k - 1]) ** 2) < tol:
+            return k
+    return None
+
+
+def test_pi_tol_stop_follows_the_printed_rule():
+    J, M, N = 2, 24, 20
+    k = inputs.phantom_kspace(J, M, N, seed=1013)
+    mask = inputs.mask_cartesian_vd(M, N, R=2.5, n_center=4, seed=2013)
+    Y = inputs.undersample(k, mask)
+    base = dict(k_row=4, k_col=4, lam=1e3, beta=6.0)
+    Ks = [Y] + [O.shlr_pi(Y, mask, O.PIParams(**base, iters=n)) for n in range(1, 16)]
+    rels = [np.sum(np.abs(Ks[i] - Ks[i - 1]) ** 2) / np.sum(np.abs(Ks[i - 1]) ** 2) for i in range(1, 16)]
+    # a tolerance between the changes of iterations 9 and 10, at least 10% from both
+    tol = np.sqrt(rels[8] * rels[9])
+    assert rels[9] < rels[8] and min(rels[8] / tol, tol / rels[9]) > 1.1, rels
+    want = _stop_rule(Ks, tol)
+    got, st = O.shlr_pi(Y, mask, O.PIParams(**base, iters=40, tol=tol), return_state=True)
+    assert st.it == want
+    assert np.array_equal(got, Ks[want])
+
+
+def test_param_tol_stop_is_per_fe_position():
+    L, J, M, N = 5, 2, 4, 24
+    k = inputs.t2_kspace(J, M, N, L=L, seed=1014)
+    k = k + 0.02 * np.abs(k).max() * inputs.random_complex(k.shape, seed=1015)
+    mask = inputs.mask_t2_cartesian(L, N, R=3, n_center=4)
+    Y = inputs.undersample(k, mask[:, None, None, :])
+    base = dict(k_pe=4, k_l=2, lam=1e3, lam2=1.5, beta=5.0)
+    Yh = np.transpose(O.ifftc(Y, axis=2), (2, 0, 1, 3))
+    tol = 1e-3   # every change within 6% of it stays on one side (FP64 rounding cannot move a stop)
+    want = []
+    for m in range(M):
+        Ks = [Yh[m]] + [O.shlr_param(Y, mask, O.ParamParams(**base, iters=n), fe_positions=[m])[0]
+                        for n in range(1, 20)]
+        want.append(_stop_rule(Ks, tol))
+    assert None not in want and len(set(want)) > 1, want
+    _, st = O.shlr_param(Y, mask, O.ParamParams(**base, iters=60, tol=tol), return_state=True)
+    assert st.it_fe.tolist() == want
+
+
+# --------------------------------------------------------------------------
+# values the paper prints (tests/golden/paper_constants.json)
+# --------------------------------------------------------------------------
+
+def _paper():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")) as f:
+        return json.load(f)
+
+
+def test_stdlr_block_hankel_size_fixes_the_lift_orientation():
+    # the introduction's block Hankel of 4-coil 256 x 256 data with pencil 23 is 2116 x 54756: window
+    # and coils on one axis, positions on the other.  The 1D lift of reading c-4 (positions x window*coils)
+    # gives that size when taken in both directions: (k * q) x p^2.
+    c = _paper()["stdlr_block_hankel_shape"]
+    lift = O.LineLift(c["n"], c["window"], True, False)
+    assert c["window"] * lift.q(c["coils"]) == c["rows"]
+    assert lift.p ** 2 == c["cols"]
+    # the rejected orientation (coils along the positions axis) would give another size
+    assert (c["window"] ** 2, (lift.p * c["coils"]) ** 2) != (c["rows"], c["cols"])
+
+
+def test_oracle_defaults_follow_the_algorithms():
+    c = _paper()
+    assert O.PIParams().d0 == c["alg_init"]["d0"] and O.ParamParams().d0 == c["alg_init"]["d0"]
+    assert O.ParamParams().iters == c["alg_s2_caps"]["max_iter"]
+    st = O.pi_init(np.ones((1, 8, 8), complex), np.ones((8, 8), bool), O.PIParams(k_row=3, k_col=3))
+    assert np.all(st.Zr == c["alg_init"]["z0"]) and np.all(st.Dr == c["alg_init"]["d0"])
