@@ -68,7 +68,9 @@ typedef enum {
     SHLR_E_WORKSPACE = 4,     /* no workspace bound, or the bound one is too small          */
     SHLR_E_DEVICE = 5,        /* a HIP runtime call failed                                  */
     SHLR_E_UNSUPPORTED = 6,   /* a combination the library does not implement               */
-    SHLR_E_STATE = 7          /* call out of order (e.g. iterate before init)               */
+    SHLR_E_STATE = 7,         /* call out of order (e.g. iterate before init)               */
+    SHLR_E_EIG_NOCONV = 8     /* an eigenpair of the eigen-solve behind the threshold of    */
+                              /* Eq. 16 / Eqs. S8-S9 failed its residual check              */
 } shlr_status;
 
 /*
@@ -121,7 +123,8 @@ typedef struct {
     double rel_change;      /* with tol > 0: the largest over units of the last             */
                             /* ||K^{k+1}-K^k||^2 / ||K^k||^2 of each unit; else 0           */
     double scale;           /* max|Y| used for normalisation (1 if off)                     */
-    uint32_t device_flags;  /* bit0: non-finite value met                                   */
+    uint32_t device_flags;  /* bit0: non-finite value met; bit1: an eigenpair failed the     */
+                            /* residual check of shlr_set_eig_check (SHLR_E_EIG_NOCONV)      */
 } shlr_info;
 
 typedef struct shlr_plan shlr_plan;
@@ -146,6 +149,18 @@ shlr_status shlr_workspace_size(const shlr_plan* plan, size_t* bytes);
 /* Bind a caller-owned device workspace of at least shlr_workspace_size bytes
  * (256-byte aligned) and the stream to enqueue on; uploads the plan's tables. */
 shlr_status shlr_bind(shlr_plan* plan, void* ws_dev, size_t bytes, void* stream);
+
+/* Replace the weighting W of Eq. 2 (the diagonal filter applied to every lifted line; by default
+ * the DFT of the circular first difference, w(f) = 1 - exp(-2 pi i f / n) at the centred frequency
+ * f) with caller values, and rebuild what depends on it: the Gram diagonals of the Eq. 15 / Eq. S7
+ * denominators and the adjoint lift of the initial multipliers.  w_row_dev: device, complex128,
+ * the row-line (PI) or PE-line (PARAM) weights of every slice back to back (N[s] values per
+ * slice); w_col_dev: device, complex128, the column-line weights (M[s] per slice) for PI, NULL
+ * for PARAM (the parameter-direction lifts are unweighted, Eq. 7).  The plan must have
+ * use_w = 1 (else SHLR_E_STATE) and be bound; the iterate is discarded, so shlr_init must
+ * follow.  A point where both directions' weights vanish must be sampled (SHLR_E_SINGULAR
+ * at shlr_init otherwise).  Synchronises the stream. */
+shlr_status shlr_set_weights(shlr_plan* plan, const void* w_row_dev, const void* w_col_dev);
 
 /* SPIRiT kernel (Eq. 3) from host memory: g_host[t][s][dm][dn], complex128,
  * J x J x ks x ks, with K_t(x) ~ sum_{s,d} g[t][s][d] K_s(x + d) (circular).
@@ -175,6 +190,16 @@ shlr_status shlr_iterate(shlr_plan* plan, int32_t n, shlr_info* info);
 /* The same n iterations as replays of a HIP graph of one iteration, captured at the first
  * call (stop test included when tol > 0; no early return to the host). */
 shlr_status shlr_iterate_graph(shlr_plan* plan, int32_t n, shlr_info* info);
+
+/* Residual check of the eigen-solve behind every singular-value threshold (Eq. 16; Eqs.
+ * S8-S9): each eigenpair (l, z) of the real tridiagonal form T of a Gram matrix that enters
+ * S must satisfy ||T z - l z|| <= rel_residual_limit * ||T|| * ||z|| (||T||: Gershgorin
+ * bound); a failure, or an eigenvector that had to be replaced because it came out zero
+ * or non-finite, sets bit 1 of shlr_info.device_flags, and the iterate / reconstruct call
+ * returns SHLR_E_EIG_NOCONV (the iterate is still written).  Default 1e-6 (converged pairs
+ * sit near 1e-14 in FP64 and below 1e-10 in the mixed forms); 0 makes every pair with a
+ * non-zero residual fail.  rel_residual_limit must be finite and >= 0. */
+shlr_status shlr_set_eig_check(shlr_plan* plan, double rel_residual_limit);
 
 /* Per-unit state of the stop test since shlr_init: units are the slices (SHLR_MODEL_PI)
  * or the FE positions (SHLR_MODEL_PARAM); n_units must equal that count.  iters_host
@@ -280,7 +305,8 @@ shlr_status shlr_lowrank_workspace_size(int32_t precision, int32_t n_mat, int32_
                                         int32_t k, int32_t use_vc, size_t* bytes);
 
 /* One low-rank step on n_mat independent lines (Eqs. 16 and 13, plus the
- * adjoint lift that feeds Eq. 15):
+ * adjoint lift that feeds Eq. 15), with the default eigenpair check (returns
+ * SHLR_E_EIG_NOCONV or SHLR_E_NONFINITE after writing its outputs):
  *   T   = lift(h) + D / beta          lift = H~ W~ or H~_vc W~ (Eqs. 2, 4)
  *   Z   = S_thr(T)                     singular-value threshold (Eq. 16)
  *   D  <- D + tau (lift(h) - Z)        (Eq. 13), in place

@@ -50,8 +50,9 @@ def real_matrix(func, in_shape) -> np.ndarray:
     return np.array(cols).T
 
 
-def lift_line(v_lines: np.ndarray, k: int, use_w: bool, vc: bool) -> np.ndarray:
-    """Lift J k-space lines (J, n) to the (n-k+1) x (k J [2]) matrix, entry by entry."""
+def lift_line(v_lines: np.ndarray, k: int, use_w: bool, vc: bool, wvec=None) -> np.ndarray:
+    """Lift J k-space lines (J, n) to the (n-k+1) x (k J [2]) matrix, entry by entry (wvec: given
+    weights in place of the first difference)."""
     J, n = v_lines.shape
     p = n - k + 1
     c = n // 2
@@ -62,7 +63,12 @@ def lift_line(v_lines: np.ndarray, k: int, use_w: bool, vc: bool) -> np.ndarray:
         for a in range(p):
             for b in range(k):
                 i = a + b
-                wi = (1.0 - np.exp(-2j * np.pi * (i - c) / n)) if use_w else 1.0
+                if not use_w:
+                    wi = 1.0
+                elif wvec is not None:
+                    wi = wvec[i]
+                else:
+                    wi = 1.0 - np.exp(-2j * np.pi * (i - c) / n)
                 if blk < J:
                     val = v_lines[j, i]
                 else:
@@ -97,7 +103,7 @@ class BrutePI:
     """SHLR(-S/-V/-SV) on an image X of shape (J, M, N) with dense linear algebra."""
 
     def __init__(self, Y, mask, k_row, k_col, lam, lam1, beta, tau, vc, use_w=True,
-                 hard_dc=False, g=None, d0=1.0):
+                 hard_dc=False, g=None, d0=1.0, wvec=None):
         self.Y = np.asarray(Y, dtype=np.complex128)
         self.mask = np.asarray(mask, dtype=bool)
         J, M, N = self.Y.shape
@@ -117,9 +123,9 @@ class BrutePI:
         UF = real_matrix(lambda X: f2(X)[:, self.mask], shape)
         self.UF = UF
         # lifted row operators: X -> lift(F_N x_row_m) for each m (Eq. 2, Eq. 4)
-        self.row_ops = [real_matrix(lambda X, m=m: lift_line((X[:, m, :] @ FN.T), k_row, use_w, vc), shape)
+        self.row_ops = [real_matrix(lambda X, m=m: lift_line((X[:, m, :] @ FN.T), k_row, use_w, vc, wvec), shape)
                         for m in range(M)]
-        self.col_ops = [real_matrix(lambda X, q=q: lift_line((X[:, :, q] @ FM.T), k_col, use_w, vc), shape)
+        self.col_ops = [real_matrix(lambda X, q=q: lift_line((X[:, :, q] @ FM.T), k_col, use_w, vc, wvec), shape)
                         for q in range(N)]
         pr, qr = N - k_row + 1, k_row * J * (2 if vc else 1)
         pc, qc = M - k_col + 1, k_col * J * (2 if vc else 1)

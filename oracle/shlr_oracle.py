@@ -107,12 +107,14 @@ def hankel_counts(n: int, k: int) -> np.ndarray:
 class LineLift:
     """The lifted operator of one line direction: H~ W~ (Eq. 2) or H~_vc W~ (Eq. 4).
 
-    n: line length; k: window; use_w: apply W; vc: append the virtual-coil blocks.
+    n: line length; k: window; use_w: apply W; vc: append the virtual-coil blocks;
+    wvec: caller weights in place of the first-difference W (the library's shlr_set_weights).
     """
     n: int
     k: int
     use_w: bool = True
     vc: bool = False
+    wvec: np.ndarray | None = field(default=None, compare=False)
 
     @property
     def p(self):
@@ -122,7 +124,9 @@ class LineLift:
         return self.k * J * (2 if self.vc else 1)
 
     def w(self):
-        return weights(self.n) if self.use_w else np.ones(self.n, dtype=np.complex128)
+        if not self.use_w:
+            return np.ones(self.n, dtype=np.complex128)
+        return weights(self.n) if self.wvec is None else np.asarray(self.wvec, dtype=np.complex128)
 
     def forward(self, h):
         """h: (..., J, n) lines of J coils -> (..., p, q) lifted matrices."""
@@ -238,6 +242,8 @@ class PIParams:
     hard_dc: bool = False     # lambda = +inf: sampled entries kept exactly
     d0: float = 1.0           # initial multiplier value (Algorithm S1: D = 1)
     normalize: bool = True
+    w_row: np.ndarray | None = None   # caller weights of the row lines (length N); None: first difference
+    w_col: np.ndarray | None = None   # caller weights of the column lines (length M)
 
     def t(self):
         return self.tau if self.tau is not None else self.beta
@@ -255,8 +261,8 @@ class PIState:
 
 
 def pi_lifts(M, N, prm: PIParams):
-    return (LineLift(N, prm.k_row, prm.use_w, prm.vc),   # rows: lines along n
-            LineLift(M, prm.k_col, prm.use_w, prm.vc))   # columns: lines along m
+    return (LineLift(N, prm.k_row, prm.use_w, prm.vc, prm.w_row),   # rows: lines along n
+            LineLift(M, prm.k_col, prm.use_w, prm.vc, prm.w_col))   # columns: lines along m
 
 
 def pi_den(mask, prm: PIParams):
@@ -387,6 +393,7 @@ class ParamParams:
     hard_dc: bool = False
     d0: float = 1.0
     normalize: bool = True
+    w_pe: np.ndarray | None = None   # caller weights of the PE lines (length N); None: first difference
 
     def t(self):
         return self.tau if self.tau is not None else self.beta
@@ -406,7 +413,7 @@ class ParamState:
 
 
 def param_lifts(L, N, prm: ParamParams):
-    return (LineLift(N, prm.k_pe, prm.use_w, prm.vc),     # PE lines of each echo (Q_l)
+    return (LineLift(N, prm.k_pe, prm.use_w, prm.vc, prm.w_pe),     # PE lines of each echo (Q_l)
             LineLift(L, prm.k_l, False, False))            # echo lines of each PE position (P_n)
 
 

@@ -1091,7 +1091,7 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
                                                              double* __restrict__ scr, int64_t scr_stride,
                                                              int32_t* __restrict__ ranks, double ortol_rel,
                                                              uint32_t* __restrict__ flags, int smax,
-                                                             VjpArgs<OC> vj, int tri_in) {
+                                                             VjpArgs<OC> vj, int tri_in, double resid_lim) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int UNR = SL <= 3 ? 4 : (SL == 4 ? 3 : 2);   // columns per wave with loads in flight
     const LRDesc dsc = descs[m0 + blockIdx.x];
@@ -1666,18 +1666,42 @@ __global__ __launch_bounds__(EIG_THREADS, SL >= 5 ? 2 : 4) void k_heig_svt(const
         }
     }
     // unit scale of every column of W, one wave per column with lanes over rows: 1 / (amax ||z / amax||);
-    // a zero or non-finite column is replaced by a start vector first
+    // a zero or non-finite column is replaced by a start vector first.  Each eigenpair is checked:
+    // ||T z - lk z|| <= resid_lim ||T|| ||z|| (T the real tridiagonal), else, or for a replaced column,
+    // bit 1 of flags reports an eigenpair that did not converge.
     double* zsc = secr;   // the complex off-diagonal is no longer needed
     for (int k = wave; k < nabove; k += nw) {
         double zv[SL];
-        double amax = 0;
+        double amax = 0, rr = 0;
+        const double lk = slam[k];
 #pragma unroll
         for (int sl = 0; sl < SL; ++sl) {
             const int row = sl * 64 + lane;
             zv[sl] = row < s ? W[(int64_t)k * s + row] : 0.0;
             amax = fmax(amax, fabs(zv[sl]));
+            if (row < s) {
+                double t = (sdd[row] - lk) * zv[sl];
+                if (row > 0) t = fma(see[row - 1], W[(int64_t)k * s + row - 1], t);
+                if (row + 1 < s) t = fma(see[row], W[(int64_t)k * s + row + 1], t);
+                rr = fma(t, t, rr);
+            }
         }
         amax = wave_max_all(amax);
+        bool fail = false;
+        if (!(amax > 0) || !(amax < DBL_MAX)) fail = true;
+        else {
+            double zz = 0;
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) {
+                const double t = zv[sl] / amax;
+                zz = fma(t, t, zz);
+            }
+            zz = wave_sum_all(zz);
+            rr = wave_sum_all(rr);
+            // ||r|| > lim ||T|| ||z||, with ||z|| = amax sqrt(zz); NaN residuals fail too
+            if (!(sqrt(rr) <= resid_lim * tnorm * amax * sqrt(zz))) fail = true;
+        }
+        if (fail && lane == 0 && flags && !bad) atomicOr(flags, 2u);
         if (!(amax > 0) || !(amax < DBL_MAX)) {
 #pragma unroll
             for (int sl = 0; sl < SL; ++sl) {
@@ -2062,7 +2086,8 @@ hipError_t launch_tridiag_rr(hipStream_t st, const LRDesc* descs, int m0, int co
 template <typename OC>
 hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
                            OC* Ss, int64_t s_stride, double* scr, int64_t scr_stride, int32_t* ranks,
-                           double ortol_rel, uint32_t* flags, int smax, const VjpArgs<OC>& vj, int tri_in) {
+                           double ortol_rel, uint32_t* flags, int smax, const VjpArgs<OC>& vj, int tri_in,
+                           double resid_lim) {
     const size_t lds = heig_lds_bytes(smax);
     const int sl = (smax + 63) / 64;
     const void* fn = sl <= 1 ? (const void*)k_heig_svt<OC, 1>
@@ -2075,7 +2100,7 @@ hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int coun
     if (e != hipSuccess) return e;
     void* args[] = {(void*)&descs, (void*)&m0, (void*)&Gs, (void*)&g_stride, (void*)&Ss, (void*)&s_stride, (void*)&scr,
                     (void*)&scr_stride, (void*)&ranks, (void*)&ortol_rel, (void*)&flags, (void*)&smax,
-                    (void*)&vj, (void*)&tri_in};
+                    (void*)&vj, (void*)&tri_in, (void*)&resid_lim};
     e = hipLaunchKernel(fn, dim3(count), dim3(EIG_THREADS), args, lds, st);
     if (e != hipSuccess) return e;
     return hipGetLastError();
@@ -2083,9 +2108,9 @@ hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int coun
 
 template hipError_t launch_heig_svt<float2>(hipStream_t, const LRDesc*, int, int, double2*, int64_t, float2*, int64_t,
                                             double*, int64_t, int32_t*, double, uint32_t*, int,
-                                            const VjpArgs<float2>&, int);
+                                            const VjpArgs<float2>&, int, double);
 template hipError_t launch_heig_svt<double2>(hipStream_t, const LRDesc*, int, int, double2*, int64_t, double2*,
                                              int64_t, double*, int64_t, int32_t*, double, uint32_t*, int,
-                                             const VjpArgs<double2>&, int);
+                                             const VjpArgs<double2>&, int, double);
 
 }  // namespace shlr

@@ -65,10 +65,9 @@ static double hankel_count(int n, int k, int i) {
     return (double)std::min(std::min(i + 1, k), std::min(n - k + 1, n - i));
 }
 
-// Diagonal of (lift)^*(lift) on one line (the Eq. 15 / S7 Hankel terms)
-static std::vector<double> gram_diag_host(int n, int k, bool use_w, bool vc) {
-    std::vector<double> wr, wi;
-    weights_host(n, wr, wi);
+// Diagonal of (lift)^*(lift) on one line (the Eq. 15 / S7 Hankel terms) for the weights (wr, wi)
+static std::vector<double> gram_diag_host(int n, int k, bool use_w, bool vc, const std::vector<double>& wr,
+                                          const std::vector<double>& wi) {
     std::vector<double> r(n);
     for (int i = 0; i < n; ++i) {
         const double a = use_w ? wr[i] * wr[i] + wi[i] * wi[i] : 1.0;
@@ -82,11 +81,15 @@ static std::vector<double> gram_diag_host(int n, int k, bool use_w, bool vc) {
     return r;
 }
 
-// lift^*(const * ones): the initial adjoint term for D = d0, Z = 0 (same on every line)
-static void init_adjoint_host(int n, int k, bool use_w, bool vc, double cst, std::vector<double>& re,
-                              std::vector<double>& im) {
+static std::vector<double> gram_diag_host(int n, int k, bool use_w, bool vc) {
     std::vector<double> wr, wi;
     weights_host(n, wr, wi);
+    return gram_diag_host(n, k, use_w, vc, wr, wi);
+}
+
+// lift^*(const * ones): the initial adjoint term for D = d0, Z = 0 (same on every line), weights (wr, wi)
+static void init_adjoint_host(int n, int k, bool use_w, bool vc, double cst, const std::vector<double>& wr,
+                              const std::vector<double>& wi, std::vector<double>& re, std::vector<double>& im) {
     re.assign(n, 0.0);
     im.assign(n, 0.0);
     for (int i = 0; i < n; ++i) {
@@ -103,6 +106,12 @@ static void init_adjoint_host(int n, int k, bool use_w, bool vc, double cst, std
             im[i] += fi * cf;
         }
     }
+}
+static void init_adjoint_host(int n, int k, bool use_w, bool vc, double cst, std::vector<double>& re,
+                              std::vector<double>& im) {
+    std::vector<double> wr, wi;
+    weights_host(n, wr, wi);
+    init_adjoint_host(n, k, use_w, vc, cst, wr, wi, re, im);
 }
 
 // ---------------------------------------------------------------------------
@@ -187,6 +196,7 @@ struct shlr_plan {
     hipGraphExec_t graph_exec = nullptr;
     int iters_total = 0;
     bool tuned = false;   // shlr_autotune chose the launch parameters
+    double eig_resid_lim = EIG_RESID_LIM_DEFAULT;   // eigenpair check of the eigen-solver (shlr_set_eig_check)
     // per-phase HIP-event timing (phase: 0 transforms + X-update, 1 Gram, 2 eigen-SVT, 3 reprojection, 4 SPIRiT,
     // 5 register-resident Householder reduction)
     bool timing = false;
@@ -664,6 +674,67 @@ extern "C" shlr_status shlr_bind(shlr_plan* plan, void* ws_dev, size_t bytes, vo
     return upload_tables<double>(plan);
 }
 
+extern "C" shlr_status shlr_set_weights(shlr_plan* plan, const void* w_row_dev, const void* w_col_dev) {
+    if (!plan) return fail(SHLR_E_INVALID_ARG, "plan is NULL");
+    if (!plan->bound) return fail(SHLR_E_WORKSPACE, "no workspace bound");
+    const shlr_params& p = plan->p;
+    if (!p.use_w) return fail(SHLR_E_STATE, "the plan was created with use_w = 0 (no weighting W)");
+    if (!w_row_dev) return fail(SHLR_E_INVALID_ARG, "w_row is NULL");
+    const bool pi = p.model == SHLR_MODEL_PI;
+    if (pi && !w_col_dev) return fail(SHLR_E_INVALID_ARG, "w_col is NULL");
+    if (!pi && w_col_dev) return fail(SHLR_E_INVALID_ARG, "the parameter model has no column weights (w_col must be NULL)");
+    size_t nr = 0, nc = 0;
+    for (const SliceLayout& L : plan->sl) {
+        nr += L.N;
+        nc += pi ? L.M : 0;
+    }
+    std::vector<double> wrow(2 * nr), wcol(2 * nc);
+    HIPCHK(hipMemcpyAsync(wrow.data(), w_row_dev, 16 * nr, hipMemcpyDeviceToHost, plan->stream));
+    if (nc) HIPCHK(hipMemcpyAsync(wcol.data(), w_col_dev, 16 * nc, hipMemcpyDeviceToHost, plan->stream));
+    HIPCHK(hipStreamSynchronize(plan->stream));
+    for (double v : wrow)
+        if (!isfinite(v)) return fail(SHLR_E_NONFINITE, "w_row holds NaN or Inf");
+    for (double v : wcol)
+        if (!isfinite(v)) return fail(SHLR_E_NONFINITE, "w_col holds NaN or Inf");
+    const int64_t c0 = plan->sl[0].wr;   // complex-arena offset of the first complex-table entry
+    auto put = [&](int64_t at, const std::vector<double>& re, const std::vector<double>& im) {
+        for (size_t i = 0; i < re.size(); ++i) {
+            plan->ctab[2 * (at - c0 + (int64_t)i)] = re[i];
+            plan->ctab[2 * (at - c0 + (int64_t)i) + 1] = im[i];
+        }
+    };
+    // one direction of one slice: weights, Gram diagonal (Eq. 15 denominator) and the D = d0 pattern
+    auto line = [&](const double* w, int n, int k, int64_t w_at, int64_t r_at, int64_t v_at) {
+        std::vector<double> re(n), im(n), vr, vi;
+        for (int i = 0; i < n; ++i) {
+            re[i] = w[2 * i];
+            im[i] = w[2 * i + 1];
+        }
+        put(w_at, re, im);
+        const std::vector<double> r = gram_diag_host(n, k, true, p.use_vc != 0, re, im);
+        for (int i = 0; i < n; ++i) plan->rtab[r_at + i] = r[i];
+        init_adjoint_host(n, k, true, p.use_vc != 0, -p.d0 / p.beta, re, im, vr, vi);
+        put(v_at, vr, vi);
+    };
+    size_t orow = 0, ocol = 0;
+    for (SliceLayout& L : plan->sl) {
+        line(wrow.data() + 2 * orow, L.N, p.k_row, L.wr, L.rr, L.vr);
+        orow += L.N;
+        if (pi) {
+            line(wcol.data() + 2 * ocol, L.M, p.k_col, L.wc, L.rc, L.vc);
+            ocol += L.M;
+        }
+    }
+    // the iterate (and a captured graph) were formed with the old tables
+    plan->initialised = false;
+    if (plan->graph_exec) {
+        (void)hipGraphExecDestroy(plan->graph_exec);
+        plan->graph_exec = nullptr;
+    }
+    if (prec_c64(p.precision)) return upload_tables<float>(plan);
+    return upload_tables<double>(plan);
+}
+
 // ---------------------------------------------------------------------------
 // iteration
 // ---------------------------------------------------------------------------
@@ -748,7 +819,7 @@ static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_
             STCHK(phase_begin(P, 2, &e0));
             HIPCHK(launch_heig_svt<cplx_t<R>>(P->stream, desc_dev, c0, c1 - c0, G, run.g_stride, S, run.s_stride, scr,
                                               run.scr_stride, ranks, ortol, flags, run.smax, VjpArgs<cplx_t<R>>(),
-                                              rr));
+                                              rr, P->eig_resid_lim));
             STCHK(phase_end(P, 2, e0));
             STCHK(phase_begin(P, 3, &e0));
             for (int gi = run.g0; gi < run.g1; ++gi) {
@@ -903,14 +974,23 @@ static shlr_status init_impl(shlr_plan* P, const void* y_dev, const uint8_t* mas
             HIPCHK(launch_fill_const<R>(P->stream, Q.c + L.dc, dc, p.d0, 0.0));
             HIPCHK(launch_fill_pattern<R>(P->stream, Q.c + L.br, e, Q.c + L.vr, 1, N));
             HIPCHK(launch_fill_pattern<R>(P->stream, Q.c + L.bct, e, Q.c + L.vc, 1, M));
-            // Eq. 15 is singular at the k-space centre (W vanishes there) unless it is sampled
-            uint8_t centre = 0;
-            HIPCHK(hipMemcpyAsync(&centre, mask_dev + moff + (int64_t)(M / 2) * N + N / 2, 1, hipMemcpyDeviceToHost,
-                                  P->stream));
-            HIPCHK(hipStreamSynchronize(P->stream));
-            const double rc = P->rtab[L.rr + N / 2] + P->rtab[L.rc + M / 2];
-            if (!(rc > 0) && !centre)
-                return fail(SHLR_E_SINGULAR, "slice %d: the k-space centre is not sampled and the lifted terms vanish there", si);
+            // Eq. 15 is singular where both lifted terms vanish (W is zero there: the k-space centre for the
+            // first-difference weights) unless the point is sampled
+            std::vector<int> zn, zm;
+            for (int i = 0; i < N; ++i)
+                if (!(P->rtab[L.rr + i] > 0)) zn.push_back(i);
+            for (int i = 0; i < M; ++i)
+                if (!(P->rtab[L.rc + i] > 0)) zm.push_back(i);
+            if (!zn.empty() && !zm.empty()) {
+                std::vector<uint8_t> mh((size_t)M * N);
+                HIPCHK(hipMemcpyAsync(mh.data(), mask_dev + moff, mh.size(), hipMemcpyDeviceToHost, P->stream));
+                HIPCHK(hipStreamSynchronize(P->stream));
+                for (int a : zm)
+                    for (int b : zn)
+                        if (!mh[(size_t)a * N + b])
+                            return fail(SHLR_E_SINGULAR, "slice %d: k-space point (%d, %d) is not sampled and the lifted "
+                                        "terms vanish there", si, a, b);
+            }
             yoff += e;
             moff += (int64_t)M * N;
         }
@@ -992,6 +1072,21 @@ static shlr_status fill_info(shlr_plan* P, bool track, const std::vector<int32_t
     info->scale = P->scales[0];
     info->device_flags = fl;
     if (fl & 1u) return fail(SHLR_E_NONFINITE, "a non-finite value was met during the iterations");
+    if (fl & 2u)
+        return fail(SHLR_E_EIG_NOCONV, "an eigenpair of a lifted matrix's Gram matrix missed the residual check "
+                    "(||T z - l z|| > %g ||T|| ||z||)", P->eig_resid_lim);
+    return SHLR_OK;
+}
+
+extern "C" shlr_status shlr_set_eig_check(shlr_plan* plan, double rel_residual_limit) {
+    if (!plan) return fail(SHLR_E_INVALID_ARG, "plan is NULL");
+    if (!(rel_residual_limit >= 0) || !isfinite(rel_residual_limit))
+        return fail(SHLR_E_INVALID_ARG, "the residual limit must be finite and >= 0");
+    plan->eig_resid_lim = rel_residual_limit;
+    if (plan->graph_exec) {   // the captured graph holds the old limit
+        (void)hipGraphExecDestroy(plan->graph_exec);
+        plan->graph_exec = nullptr;
+    }
     return SHLR_OK;
 }
 
@@ -1306,7 +1401,11 @@ static shlr_status lowrank_impl(int32_t precision, int32_t n_mat, int32_t J, int
     STCHK(run_lowrank<R>(&tmp, (C*)h_dev, (C*)d_dev, (C*)b_dev, (const C*)(ws + L.off_w), (LRDesc*)(ws + L.off_desc),
                          (double2*)(ws + L.off_g), (C*)(ws + L.off_s), (double*)(ws + L.off_scr), ranks_dev,
                          (uint32_t*)(ws + L.off_flags)));
+    uint32_t fl = 0;
+    HIPCHK(hipMemcpyAsync(&fl, ws + L.off_flags, 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));   // host descriptor vectors go out of scope
+    if (fl & 1u) return fail(SHLR_E_NONFINITE, "a non-finite value was met in a lifted matrix");
+    if (fl & 2u) return fail(SHLR_E_EIG_NOCONV, "an eigenpair of a lifted matrix's Gram matrix missed the residual check");
     return SHLR_OK;
 }
 

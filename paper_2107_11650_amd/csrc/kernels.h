@@ -126,7 +126,9 @@ template <typename OC>
 hipError_t launch_heig_svt(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
                            OC* Ss, int64_t s_stride, double* scr, int64_t scr_stride, int32_t* ranks,
                            double ortol_rel, uint32_t* flags, int smax, const VjpArgs<OC>& vj = VjpArgs<OC>(),
-                           int tri_in = 0);
+                           int tri_in = 0, double resid_lim = 1e-6);
+// residual bound of the eigenpair check (relative to ||T|| ||z||) unless the caller sets another
+constexpr double EIG_RESID_LIM_DEFAULT = 1e-6;
 // Register-resident Householder reduction of the packed Gram matrices (orders 2..208): reflectors in
 // place, diagonal / off-diagonal / h in the first 4 s doubles of each slot's scratch (then tri_in = 1).
 // fp32: the matrix held in FP32 (the mixed form's forward iterations), orders up to 256; FP64 up to 208.

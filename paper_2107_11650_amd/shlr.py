@@ -30,6 +30,7 @@ PREC_MIXED_R32 = 2   # opt-in: FP32 Householder reduction (see include/shlr.h)
 STATUS = {
     0: "SHLR_OK", 1: "SHLR_E_INVALID_ARG", 2: "SHLR_E_SINGULAR", 3: "SHLR_E_NONFINITE",
     4: "SHLR_E_WORKSPACE", 5: "SHLR_E_DEVICE", 6: "SHLR_E_UNSUPPORTED", 7: "SHLR_E_STATE",
+    8: "SHLR_E_EIG_NOCONV",
 }
 
 EXPORTED = [
@@ -38,7 +39,7 @@ EXPORTED = [
     "shlr_reconstruct", "shlr_fft_lines", "shlr_lowrank_workspace_size", "shlr_lowrank_lines",
     "shlr_last_error", "shlr_version", "shlr_timing_enable", "shlr_timing_enable_phases", "shlr_timing_read",
     "shlr_unrolled_sizes", "shlr_unrolled_forward", "shlr_unrolled_backward", "shlr_autotune",
-    "shlr_params_default", "shlr_unit_status",
+    "shlr_params_default", "shlr_unit_status", "shlr_set_eig_check", "shlr_set_weights",
 ]
 TIMING_PHASES = ("xupdate", "gram", "eig", "reproj", "spirit", "tridiag")
 
@@ -92,6 +93,8 @@ _lib.shlr_unrolled_backward.argtypes = [_vp, _i32, _vp, _vp, ctypes.c_size_t, _v
 _lib.shlr_autotune.argtypes = [_vp, _i32, ctypes.c_char_p, ctypes.c_size_t]
 _lib.shlr_params_default.argtypes = [_i32, _vp]
 _lib.shlr_unit_status.argtypes = [_vp, _i32, _vp, _vp, _vp]
+_lib.shlr_set_eig_check.argtypes = [_vp, ctypes.c_double]
+_lib.shlr_set_weights.argtypes = [_vp, _vp, _vp]
 _lib.shlr_timing_enable.argtypes = [_vp, _i32]
 _lib.shlr_timing_enable_phases.argtypes = [_vp, ctypes.c_uint32]
 _lib.shlr_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
@@ -226,6 +229,19 @@ class Plan:
     def iterate_async(self, n, graph=False):
         f = _lib.shlr_iterate_graph if graph else _lib.shlr_iterate
         _check(f(self._h, int(n), None))
+
+    def set_weights(self, w_row, w_col=None):
+        """Replace W (Eq. 2): w_row / w_col complex tensors (any device) holding the row / column line
+        weights of every slice back to back (w_col None for the parameter model).  shlr_init must follow."""
+        import torch
+        dev = self.ws.device
+        wr = torch.as_tensor(w_row).to(device=dev, dtype=torch.complex128).contiguous()
+        wc = None if w_col is None else torch.as_tensor(w_col).to(device=dev, dtype=torch.complex128).contiguous()
+        _check(_lib.shlr_set_weights(self._h, _ptr(wr), None if wc is None else _ptr(wc)))
+
+    def set_eig_check(self, rel_residual_limit):
+        """Residual bound of the eigenpair check (see shlr_set_eig_check)."""
+        _check(_lib.shlr_set_eig_check(self._h, float(rel_residual_limit)))
 
     def unit_status(self):
         """Per stop unit (slice, or FE position of the parameter model): (iterations run, last relative

@@ -162,3 +162,32 @@ def test_unit_status_needs_an_initialised_plan():
         assert st == 7, shlr.library().shlr_last_error()      # SHLR_E_STATE: no shlr_init yet
     finally:
         shlr.library().shlr_plan_destroy(h)
+
+
+def test_eig_check_limit_is_validated():
+    import ctypes
+    from paper_2107_11650_amd import shlr
+    h, keep = _raw_plan(shlr, M=(32,), N=(32,), J=2, k_row=4, k_col=4)
+    try:
+        lib = shlr.library()
+        assert lib.shlr_set_eig_check(h, ctypes.c_double(-1.0)) == 1
+        assert lib.shlr_set_eig_check(h, ctypes.c_double(float("nan"))) == 1
+        assert lib.shlr_set_eig_check(h, ctypes.c_double(float("inf"))) == 1
+        assert lib.shlr_set_eig_check(h, ctypes.c_double(0.0)) == 0
+        assert lib.shlr_set_eig_check(h, ctypes.c_double(1e-6)) == 0
+        assert lib.shlr_set_eig_check(None, ctypes.c_double(1e-6)) == 1
+    finally:
+        shlr.library().shlr_plan_destroy(h)
+
+
+def test_set_weights_argument_checks():
+    import ctypes
+    from paper_2107_11650_amd import shlr
+    lib = shlr.library()
+    # no workspace bound yet: refused before any device access
+    h, keep = _raw_plan(shlr, M=(32,), N=(32,), J=2, k_row=4, k_col=4)
+    try:
+        assert lib.shlr_set_weights(h, ctypes.c_void_p(16), ctypes.c_void_p(16)) == 4
+        assert lib.shlr_set_weights(None, None, None) == 1
+    finally:
+        lib.shlr_plan_destroy(h)

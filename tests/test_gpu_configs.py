@@ -7,8 +7,9 @@
   Cartesian masks, PE window 25 with virtual coils, echo window 4.  Each
   frequency-encode position iterates independently, so the oracle runs
   sampled positions and is compared in hybrid space.
-* Bar: NMSE <= 1e-5 per result (mixed precision: FP32 MFMA products, FP64
-  eigen-solves).
+* Bars (mixed precision: FP32 MFMA products, FP64 eigen-solves): NMSE per
+  result and the largest relative error of any k-space row or column of one
+  coil (tests/parity_util.py).
 """
 
 import numpy as np
@@ -16,6 +17,7 @@ import pytest
 
 from oracle import shlr_oracle as O
 from paper_2107_11650_amd import inputs
+from parity_util import check
 
 pytestmark = pytest.mark.gpu
 
@@ -60,9 +62,8 @@ def test_ragged_batch_32_slices_12_coils_sampled():
     for i in picks:
         ref = O.shlr_pi(Ys[i], masks[i], prm)
         got = out[offs[i]:offs[i + 1]].reshape(Ys[i].shape)
-        e = O.nmse(got, ref)
-        print(f"slice {i} {sizes[i]}: nmse={e:.3e}", flush=True)
-        assert e < 1e-5
+        # 2 iterations from D = 1: the initial multipliers still cancel (measured 3e-12 and 8e-5)
+        check(got, ref, 1e-10, 1e-3, label=f"ragged slice {i} {sizes[i]}")
 
 
 def test_t2_series_shlr_vp_256_12_coils_sampled_fe():
@@ -84,6 +85,6 @@ def test_t2_series_shlr_vp_256_12_coils_sampled_fe():
     picks = [40, 77, 128, 180, 220]   # inside the object along FE
     ref = O.shlr_param(Y, mask, prm, fe_positions=picks)
     for j, mpos in enumerate(picks):
-        e = O.nmse(hyb[mpos], ref[j])
-        print(f"FE position {mpos}: nmse={e:.3e}", flush=True)
-        assert e < 1e-5
+        # after 3 iterations from D = 1 the large initial multipliers still cancel in the iterate, and
+        # some FE positions sit at NMSE 5e-11 (mixed) rather than the 1e-14 of longer runs
+        check(hyb[mpos], ref[j], 1e-9, 2e-3, label=f"T2 FE position {mpos}", axes=(-1, -3))

@@ -2,9 +2,13 @@
 
 Tolerances (NMSE = ||gpu - oracle||^2 / ||oracle||^2):
 * FP64 form: 1e-20 per stage, 1e-18 over whole runs (rounding order only);
-* mixed form (complex64 data, FP32 MFMA products, FP64 eigensolves): the
-  per-result bar NMSE <= 1e-5 stated for the method; single transforms are
-  held to 1e-11 (FP32 rounding of an O(log n)-depth FFT).
+* mixed form (complex64 data, FP32 MFMA products, FP64 eigensolves): NMSE
+  1e-12 over whole runs and 1e-11 per stage (the method's per-result bar is
+  1e-5; measured levels are 4e-15 to 3e-13) and, through tests/parity_util.py,
+  a bound of 2e-4 on the relative error of every single k-space row and column
+  (or lifted-matrix row and column; measured at most 3e-5), so that a 1e-3
+  error confined to one line fails; single transforms are held to 1e-11 (FP32
+  rounding of an O(log n)-depth FFT).  FP64 line errors are held to 1e-11.
 """
 
 import numpy as np
@@ -12,6 +16,7 @@ import pytest
 
 from oracle import shlr_oracle as O
 from paper_2107_11650_amd import inputs
+from parity_util import check
 
 pytestmark = pytest.mark.gpu
 
@@ -33,6 +38,10 @@ def host(t):
 
 def nmse(a, b):
     return O.nmse(a, b)
+
+
+# whole-run bars: (NMSE, largest relative error of one k-space row or column)
+RUN_BARS = {"fp64": (1e-18, 1e-11), "mixed": (1e-12, 2e-4)}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -113,8 +122,11 @@ def test_lowrank_step(case, prec):
     rk_ref = (s > thr).sum(-1)
     print(f"lowrank {case} {prec}: nmse D={e_d:.3e} b={e_b:.3e} ranks={ranks.cpu().numpy().tolist()}", flush=True)
     assert np.array_equal(ranks.cpu().numpy(), rk_ref)
-    tol = 1e-20 if prec == "fp64" else 1e-5
+    tol = 1e-20 if prec == "fp64" else 1e-11
     assert e_d < tol and e_b < tol
+    lbar = 1e-11 if prec == "fp64" else 2e-4
+    check(host(Dd), Dn_ref, tol, lbar, label=f"lowrank {case} {prec} D")
+    check(host(b), b_ref, tol, lbar, label=f"lowrank {case} {prec} b")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -144,8 +156,11 @@ def test_lowrank_step_clustered(prec):
     e_d, e_b = nmse(host(Dd), Dn_ref), nmse(host(b), b_ref)
     print(f"lowrank clustered {prec}: nmse D={e_d:.3e} b={e_b:.3e} ranks={ranks.cpu().numpy().tolist()}", flush=True)
     assert ranks.cpu().numpy().tolist() == [int((sig > thr).sum())] * B
-    tol = 1e-20 if prec == "fp64" else 1e-5
+    tol = 1e-20 if prec == "fp64" else 1e-11
     assert e_d < tol and e_b < tol
+    lbar = 1e-11 if prec == "fp64" else 2e-4
+    check(host(Dd), Dn_ref, tol, lbar, label=f"lowrank clustered {prec} D")
+    check(host(b), b_ref, tol, lbar, label=f"lowrank clustered {prec} b")
 
 
 def test_lowrank_step_zero_and_full_threshold():
@@ -236,7 +251,7 @@ def test_phase_timing_mask():
         plan.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-18), ("mixed", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-18), ("mixed", 1e-12)])
 def test_pi_config1_20_iterations(prec, tol):
     # 4 coils, 64 x 64, 1D variable-density Cartesian R=3 with 8 centre lines, window 8, 20 iterations
     shlr = _lib()
@@ -244,9 +259,7 @@ def test_pi_config1_20_iterations(prec, tol):
     prm = O.PIParams(k_row=8, k_col=8, lam=1e4, beta=10.0, iters=20)
     ref = O.shlr_pi(Y, mask, prm)
     out = run_pi_gpu(Y, mask, prm, shlr.PREC_FP64 if prec == "fp64" else shlr.PREC_MIXED)
-    e = nmse(out, ref)
-    print(f"PI config 1 {prec}: nmse={e:.3e}", flush=True)
-    assert e < tol
+    check(out, ref, min(tol, RUN_BARS[prec][0]), RUN_BARS[prec][1], label=f"PI config 1 {prec}")
 
 
 @pytest.mark.parametrize("vc,hard", [(True, False), (False, True)])
@@ -270,11 +283,9 @@ def test_pi_prime_sizes_chirp_z():
     Y, mask = pi_problem(3, 37, 41, seed=9, n_center=6)
     prm = O.PIParams(k_row=7, k_col=6, lam=1e4, beta=10.0, vc=True, iters=5)
     ref = O.shlr_pi(Y, mask, prm)
-    for prec, tol in ((shlr.PREC_FP64, 1e-18), (shlr.PREC_MIXED, 1e-5)):
+    for prec, name in ((shlr.PREC_FP64, "fp64"), (shlr.PREC_MIXED, "mixed")):
         out = run_pi_gpu(Y, mask, prm, prec)
-        e = nmse(out, ref)
-        print(f"PI 37x41 prec={prec}: nmse={e:.3e}", flush=True)
-        assert e < tol
+        check(out, ref, *RUN_BARS[name], label=f"PI 37x41 {name}")
 
 
 def test_pi_multislice_batch():
@@ -284,9 +295,7 @@ def test_pi_multislice_batch():
     prm = O.PIParams(k_row=5, k_col=5, lam=1e4, beta=8.0, iters=6)
     outs = run_pi_gpu(Ys, ms, prm, shlr.PREC_FP64, slices=True)
     for Y, m, o in zip(Ys, ms, outs):
-        e = nmse(o, O.shlr_pi(Y, m, prm))
-        print(f"multislice nmse={e:.3e}", flush=True)
-        assert e < 1e-18
+        check(o, O.shlr_pi(Y, m, prm), *RUN_BARS["fp64"], label="multislice fp64")
 
 
 def test_graph_replays_match_eager():
@@ -322,7 +331,7 @@ def run_param_gpu(Y, mask, prm: O.ParamParams, precision):
 
 
 @pytest.mark.parametrize("vc", [False, True])
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-18), ("mixed", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-18), ("mixed", 1e-12)])
 def test_param_iterations(vc, prec, tol):
     shlr = _lib()
     L, J, M, N = 8, 4, 6, 64
@@ -332,9 +341,7 @@ def test_param_iterations(vc, prec, tol):
     prm = O.ParamParams(k_pe=8, k_l=4, lam=1e4, lam2=2.0, beta=10.0, vc=vc, iters=10)
     ref = O.shlr_param(Y, mask, prm)
     out = run_param_gpu(Y, mask, prm, shlr.PREC_FP64 if prec == "fp64" else shlr.PREC_MIXED)
-    e = nmse(out, ref)
-    print(f"PARAM vc={vc} {prec}: nmse={e:.3e}", flush=True)
-    assert e < tol
+    check(out, ref, min(tol, RUN_BARS[prec][0]), RUN_BARS[prec][1], label=f"PARAM vc={vc} {prec}")
 
 
 # ---------------------------------------------------------------------------
@@ -366,7 +373,7 @@ def run_spirit_gpu(Y, mask, prm, precision, g=None, acs=16):
 
 
 @pytest.mark.parametrize("vc", [False, True])
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-20), ("mixed", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-20), ("mixed", 1e-12)])
 def test_spirit_given_kernel(vc, prec, tol):
     shlr = _lib()
     Y, mask = spirit_problem()
@@ -374,12 +381,10 @@ def test_spirit_given_kernel(vc, prec, tol):
     prm = O.PIParams(k_row=6, k_col=6, lam=1e4, lam1=10.0, beta=10.0, vc=vc, n_cg=6, iters=5)
     ref = O.shlr_pi(Y, mask, prm, g=g)
     out = run_spirit_gpu(Y, mask, prm, shlr.PREC_FP64 if prec == "fp64" else shlr.PREC_MIXED, g=g)
-    e = nmse(out, ref)
-    print(f"SPIRiT given kernel vc={vc} {prec}: nmse={e:.3e}", flush=True)
-    assert e < tol
+    check(out, ref, min(tol, RUN_BARS[prec][0]), RUN_BARS[prec][1], label=f"SPIRiT given kernel vc={vc} {prec}")
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-16), ("mixed", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-16), ("mixed", 1e-12)])
 def test_spirit_calibrated_on_device(prec, tol):
     shlr = _lib()
     Y, mask = spirit_problem(seed=8)
@@ -387,9 +392,7 @@ def test_spirit_calibrated_on_device(prec, tol):
     prm = O.PIParams(k_row=6, k_col=6, lam=1e4, lam1=10.0, beta=10.0, n_cg=6, iters=5)
     ref = O.shlr_pi(Y, mask, prm, g=g)
     out = run_spirit_gpu(Y, mask, prm, shlr.PREC_FP64 if prec == "fp64" else shlr.PREC_MIXED, g=None, acs=16)
-    e = nmse(out, ref)
-    print(f"SPIRiT calibrated {prec}: nmse={e:.3e}", flush=True)
-    assert e < tol
+    check(out, ref, min(tol, RUN_BARS[prec][0]), RUN_BARS[prec][1], label=f"SPIRiT calibrated {prec}")
 
 
 # ---------------------------------------------------------------------------
@@ -418,5 +421,5 @@ def test_autotune_keeps_the_iterates(prec):
         plan.close()
     e_ref, e_pair = nmse(outs[1], ref), nmse(outs[1], outs[0])
     print(f"autotune {prec}: nmse vs oracle {e_ref:.3e}, vs untuned {e_pair:.3e}", flush=True)
-    assert e_ref < (1e-18 if prec == "fp64" else 1e-5)
+    assert e_ref < (1e-18 if prec == "fp64" else 1e-12)
     assert e_pair < (1e-20 if prec == "fp64" else 1e-9)

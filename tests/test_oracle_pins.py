@@ -520,3 +520,28 @@ def test_oracle_defaults_follow_the_algorithms():
     assert O.ParamParams().iters == c["alg_s2_caps"]["max_iter"]
     st = O.pi_init(np.ones((1, 8, 8), complex), np.ones((8, 8), bool), O.PIParams(k_row=3, k_col=3))
     assert np.all(st.Zr == c["alg_init"]["z0"]) and np.all(st.Dr == c["alg_init"]["d0"])
+
+
+def test_caller_weights_enter_every_weighted_operator():
+    # W given as an array equal to the first difference reproduces the default run exactly, and other
+    # weights keep the lift's adjoint identity and the diagonal Gram of reading c-2
+    Y, mask = _tiny_pi(seed=3)
+    prm = O.PIParams(k_row=3, k_col=3, lam=30.0, beta=2.0, vc=True, iters=4, normalize=False)
+    a = O.shlr_pi(Y, mask, prm)
+    prm_w = O.PIParams(k_row=3, k_col=3, lam=30.0, beta=2.0, vc=True, iters=4, normalize=False,
+                       w_row=O.weights(8), w_col=O.weights(8))
+    assert np.array_equal(O.shlr_pi(Y, mask, prm_w), a)
+    w = inputs.random_complex(8, seed=61)
+    lift = O.LineLift(8, 3, True, True, w)
+    h = inputs.random_complex((2, 8), seed=62)
+    R = inputs.random_complex((6, 12), seed=63)
+    assert abs(np.vdot(lift.forward(h), R).real - np.vdot(h, lift.adjoint(R, 2)).real) < 1e-12
+    G = brute.real_matrix(lambda x: lift.forward(x), (2, 8))
+    GtG = G.T @ G
+    assert np.abs(GtG - np.diag(np.diag(GtG))).max() < 1e-12
+    assert rel(np.diag(GtG)[:8], lift.gram_diag()) < 1e-13
+    # and the whole iteration with those weights against the brute force's entry-wise lift
+    prm_r = O.PIParams(k_row=3, k_col=3, lam=30.0, beta=2.0, iters=3, normalize=False, w_row=w, w_col=w)
+    K = O.shlr_pi(Y, mask, prm_r)
+    b = brute.BrutePI(Y, mask, 3, 3, 30.0, 0.0, 2.0, 2.0, False, wvec=w)
+    assert O.nmse(K, b.run(3)) < 1e-24
