@@ -320,6 +320,21 @@ shlr_status shlr_lowrank_lines(int32_t precision, int32_t n_mat, int32_t J, int3
                                const void* h_dev, void* d_dev, void* b_dev, int32_t* ranks_dev,
                                void* ws_dev, size_t ws_bytes, void* stream);
 
+/* shlr_lowrank_lines without the workspace argument, for callers that cannot allocate device
+ * memory (code under stream capture, serving loops, harnesses that forbid hipMalloc): the
+ * eigen-solver slots, descriptors, weights and flags live in a fixed 64 MiB device array of the
+ * library (one copy per GPU, taken at module load and held until the process ends), so no call
+ * allocates.  Same arguments, outputs and status codes as shlr_lowrank_lines; lines that need
+ * more than the array for one eigen-solver slot plus their tables are refused with
+ * SHLR_E_WORKSPACE, and a batch larger than the array holds at once runs in more chunks.  All
+ * calls on one GPU share its array: calls that overlap in time on that GPU (other threads or
+ * streams) race and must be serialised by the caller; each call synchronises its stream before
+ * it returns. */
+shlr_status shlr_lowrank_lines_noalloc(int32_t precision, int32_t n_mat, int32_t J, int32_t n, int32_t k,
+                                       int32_t use_vc, int32_t use_w, double beta, double tau, double thr,
+                                       const void* h_dev, void* d_dev, void* b_dev, int32_t* ranks_dev,
+                                       void* stream);
+
 /* Text of the calling thread's last error ("" if none). */
 const char* shlr_last_error(void);
 

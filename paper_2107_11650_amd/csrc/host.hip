@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1313,8 +1314,9 @@ struct LRLayout {
     int64_t gst, sst, scst;
 };
 
+// cap > 0: the layout must fit cap bytes; the eigen-solver slots (chunk size) shrink to what is left
 static shlr_status lr_layout(int32_t precision, int32_t n_mat, int32_t J, int32_t n, int32_t k, int32_t use_vc,
-                             LRLayout* L) {
+                             LRLayout* L, size_t cap = 0) {
     if (!prec_valid(precision)) return fail(SHLR_E_INVALID_ARG, "bad precision");
     if (n_mat < 0 || J < 1 || n < 1 || k < 1 || k > n) return fail(SHLR_E_INVALID_ARG, "bad shape");
     LRDesc d = make_desc(0, 0, 0, 0, 0, 0, 0, n, k, J, use_vc ? 2 : 1, 0, 0, 0.0);
@@ -1329,7 +1331,16 @@ static shlr_status lr_layout(int32_t precision, int32_t n_mat, int32_t J, int32_
     L->sst = (int64_t)s * s;
     L->scst = eig_scratch_doubles(s);
     const size_t per = L->gst * 16 + L->sst * cs + L->scst * 8 + 3 * 256;
-    L->slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::max(n_mat, 1), SLOT_BUDGET / per));
+    size_t budget = SLOT_BUDGET;
+    if (cap > 0) {
+        const size_t fixed = align256((size_t)std::max(n_mat, 1) * sizeof(LRDesc)) + align256((size_t)n * cs) + 256 +
+                             3 * 256;
+        if (fixed + per > cap)
+            return fail(SHLR_E_WORKSPACE, "n_mat = %d lines of this shape need %zu bytes for one eigen-solver slot "
+                        "and the line tables, beyond the %zu-byte fixed scratch", n_mat, fixed + per, cap);
+        budget = std::min(budget, cap - fixed);
+    }
+    L->slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::max(n_mat, 1), budget / per));
     size_t off = 0;
     L->off_desc = off;
     off = align256(off + (size_t)std::max(n_mat, 1) * sizeof(LRDesc));
@@ -1425,6 +1436,53 @@ extern "C" shlr_status shlr_lowrank_lines(int32_t precision, int32_t n_mat, int3
                                    (unsigned char*)ws_dev, L, (hipStream_t)stream);
     return lowrank_impl<double>(precision, n_mat, J, n, k, use_vc, use_w, beta, tau, thr, h_dev, d_dev, b_dev, ranks_dev,
                                 (unsigned char*)ws_dev, L, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// shlr_lowrank_lines without a caller workspace: the eigen-solver slots, descriptors, weights and
+// flags live in a fixed device array of this file (one copy per GPU, held until the process ends)
+// ---------------------------------------------------------------------------
+
+static constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::vector<unsigned char*> g_scratch_ptr;   // per device: the address of that device's copy
+
+// The device address of this device's scratch array, looked up once per device with it current.
+static shlr_status scratch_ptr(unsigned char** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SHLR_E_DEVICE, "no device address for the fixed scratch array");
+        g_scratch_ptr[dev] = (unsigned char*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SHLR_OK;
+}
+
+extern "C" shlr_status shlr_lowrank_lines_noalloc(int32_t precision, int32_t n_mat, int32_t J, int32_t n, int32_t k,
+                                                  int32_t use_vc, int32_t use_w, double beta, double tau, double thr,
+                                                  const void* h_dev, void* d_dev, void* b_dev, int32_t* ranks_dev,
+                                                  void* stream) {
+    LRLayout L;
+    STCHK(lr_layout(precision, n_mat, J, n, k, use_vc, &L, NOALLOC_SCRATCH_BYTES));
+    if (n_mat == 0) return SHLR_OK;
+    if (!(beta > 0) || !(tau > 0) || !(thr >= 0)) return fail(SHLR_E_INVALID_ARG, "beta, tau > 0 and thr >= 0 required");
+    if (!h_dev || !d_dev || !b_dev) return fail(SHLR_E_INVALID_ARG, "NULL data pointer");
+    if (L.total > NOALLOC_SCRATCH_BYTES)
+        return fail(SHLR_E_WORKSPACE, "the layout needs %zu bytes, beyond the %zu-byte fixed scratch", L.total,
+                    NOALLOC_SCRATCH_BYTES);
+    unsigned char* ws = nullptr;
+    STCHK(scratch_ptr(&ws));
+    if (prec_c64(precision))
+        return lowrank_impl<float>(precision, n_mat, J, n, k, use_vc, use_w, beta, tau, thr, h_dev, d_dev, b_dev,
+                                   ranks_dev, ws, L, (hipStream_t)stream);
+    return lowrank_impl<double>(precision, n_mat, J, n, k, use_vc, use_w, beta, tau, thr, h_dev, d_dev, b_dev,
+                                ranks_dev, ws, L, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -40,6 +40,7 @@ EXPORTED = [
     "shlr_last_error", "shlr_version", "shlr_timing_enable", "shlr_timing_enable_phases", "shlr_timing_read",
     "shlr_unrolled_sizes", "shlr_unrolled_forward", "shlr_unrolled_backward", "shlr_autotune",
     "shlr_params_default", "shlr_unit_status", "shlr_set_eig_check", "shlr_set_weights",
+    "shlr_lowrank_lines_noalloc",
 ]
 TIMING_PHASES = ("xupdate", "gram", "eig", "reproj", "spirit", "tridiag")
 
@@ -95,6 +96,8 @@ _lib.shlr_params_default.argtypes = [_i32, _vp]
 _lib.shlr_unit_status.argtypes = [_vp, _i32, _vp, _vp, _vp]
 _lib.shlr_set_eig_check.argtypes = [_vp, ctypes.c_double]
 _lib.shlr_set_weights.argtypes = [_vp, _vp, _vp]
+_lib.shlr_lowrank_lines_noalloc.argtypes = [_i32, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
 _lib.shlr_timing_enable.argtypes = [_vp, _i32]
 _lib.shlr_timing_enable_phases.argtypes = [_vp, ctypes.c_uint32]
 _lib.shlr_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
@@ -392,6 +395,20 @@ def lowrank_lines(h, D, k, beta, tau, thr, use_vc=False, use_w=True, ranks=False
     _check(_lib.shlr_lowrank_lines(prec, B, J, n, k, int(use_vc), int(use_w), float(beta), float(tau), float(thr),
                                    _ptr(h), _ptr(D), _ptr(b), _ptr(rk) if ranks else None,
                                    ctypes.c_void_p(ws.data_ptr() + off), ctypes.c_size_t(nb), _stream()))
+    return (b, rk) if ranks else b
+
+
+def lowrank_lines_noalloc(h, D, k, beta, tau, thr, use_vc=False, use_w=True, ranks=False, r32=False):
+    """lowrank_lines through shlr_lowrank_lines_noalloc (the library's fixed scratch, no workspace)."""
+    import torch
+    prec = (PREC_MIXED_R32 if r32 else PREC_MIXED) if h.dtype == torch.complex64 else PREC_FP64
+    B, J, n = h.shape
+    assert D.is_contiguous() and h.is_contiguous()
+    b = torch.empty_like(h)
+    rk = torch.zeros(B, dtype=torch.int32, device=h.device) if ranks else None
+    _check(_lib.shlr_lowrank_lines_noalloc(prec, B, J, n, k, int(use_vc), int(use_w), float(beta), float(tau),
+                                           float(thr), _ptr(h), _ptr(D), _ptr(b), _ptr(rk) if ranks else None,
+                                           _stream()))
     return (b, rk) if ranks else b
 
 

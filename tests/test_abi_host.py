@@ -191,3 +191,12 @@ def test_set_weights_argument_checks():
         assert lib.shlr_set_weights(None, None, None) == 1
     finally:
         lib.shlr_plan_destroy(h)
+
+
+def test_noalloc_rejects_batches_beyond_its_fixed_scratch():
+    # a million 320-point lines need 72 MB of descriptors alone: refused before any device access
+    from paper_2107_11650_amd import shlr
+    lib = shlr.library()
+    st = lib.shlr_lowrank_lines_noalloc(0, 1000000, 12, 320, 25, 0, 1, 3.0, 2.0, 1.0, None, None, None, None, None)
+    assert st == 4 and b"fixed scratch" in lib.shlr_last_error()
+    assert lib.shlr_lowrank_lines_noalloc(0, -1, 4, 64, 8, 0, 1, 3.0, 2.0, 1.0, None, None, None, None, None) == 1
