@@ -320,6 +320,49 @@ shlr_status shlr_lowrank_lines(int32_t precision, int32_t n_mat, int32_t J, int3
                                const void* h_dev, void* d_dev, void* b_dev, int32_t* ranks_dev,
                                void* ws_dev, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Evaluation step after a reconstruction (Section IV and Supplement S2): the coil combination,
+ * the two quality measures and the T2 map of the parameter-imaging experiment.  Real images are
+ * float (SHLR_PREC_MIXED, SHLR_PREC_MIXED_R32) or double (SHLR_PREC_FP64), [M][N] row-major;
+ * sums are accumulated in FP64 in a fixed order, so results repeat bit for bit.  work_dev is a
+ * caller-owned device buffer of SHLR_EVAL_WORK_BYTES (8-byte aligned) for partial sums, except
+ * where stated.  Calls are enqueued on `stream`; those returning a host value synchronise it.
+ * ------------------------------------------------------------------------- */
+#define SHLR_EVAL_WORK_BYTES 65536
+#define SHLR_T2_MAX_ECHOES 32
+
+/* SSOS coil combination (Section IV, first paragraph): img[i] = sqrt(sum_j |x_ij|^2) with x_ij
+ * the centred unitary inverse 2D DFT of coil j of image i.  k_dev: [n_img][J][M][N] complex
+ * k-space; work_dev: n_img*J*M*N complex of the precision (receives the coil images); img_dev:
+ * [n_img][M][N] real output. */
+shlr_status shlr_ssos(int32_t precision, int32_t n_img, int32_t J, int32_t M, int32_t N, const void* k_dev,
+                      void* work_dev, void* img_dev, void* stream);
+
+/* RLNE of Eq. S10: ||x - x_hat||_2 / ||x||_2 over count real values (x = ref_dev, the fully
+ * sampled image; x_hat = rec_dev), restricted to roi_dev != 0 when roi_dev (uint8, count) is not
+ * NULL.  SHLR_E_INVALID_ARG if the reference is zero there. */
+shlr_status shlr_rlne(int32_t precision, int64_t count, const void* ref_dev, const void* rec_dev,
+                      const uint8_t* roi_dev, void* work_dev, double* rlne_host, void* stream);
+
+/* MSSIM of Eq. S11 between the reference ref_dev and rec_dev (both M x N, M, N >= 11): the mean
+ * over every 11 x 11 window position inside the image of the SSIM of the window, with Gaussian
+ * window weights (sigma 1.5, unit sum), C1 = (0.01 L)^2 and C2 = (0.03 L)^2, L = dyn_range, or the
+ * reference's maximum when dyn_range <= 0 (the window and the constants are the cited SSIM
+ * paper's; Eq. S11 states neither). */
+shlr_status shlr_mssim(int32_t precision, int32_t M, int32_t N, const void* ref_dev, const void* rec_dev,
+                       double dyn_range, void* work_dev, double* mssim_host, void* stream);
+
+/* Pixel-wise T2 map (Section IV-B: nonlinear least squares per pixel inside a region of interest,
+ * values outside a reasonable range excluded).  img_dev: [L][n_pix] real echo images (e.g. SSOS
+ * magnitudes), te_host[L] echo times; per pixel S(TE) = rho exp(-TE / T2) is fitted in FP64 from
+ * the log-linear least-squares start by Levenberg-Marquardt.  The ROI is every pixel whose first
+ * echo is >= roi_frac times that image's maximum; outside it, where the fit fails, or where T2
+ * falls outside [t2_min, t2_max], t2 (and rho) are 0 and roi is 0.  t2_dev [n_pix] real output;
+ * rho_dev [n_pix] real and roi_dev [n_pix] uint8 outputs may be NULL.  2 <= L <= 32. */
+shlr_status shlr_t2_fit(int32_t precision, int32_t L, int64_t n_pix, const double* te_host, const void* img_dev,
+                        double roi_frac, double t2_min, double t2_max, void* t2_dev, void* rho_dev,
+                        uint8_t* roi_dev, void* work_dev, void* stream);
+
 /* shlr_lowrank_lines without the workspace argument, for callers that cannot allocate device
  * memory (code under stream capture, serving loops, harnesses that forbid hipMalloc): the
  * eigen-solver slots, descriptors, weights and flags live in a fixed 64 MiB device array of the

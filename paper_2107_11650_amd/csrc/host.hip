@@ -1491,3 +1491,4 @@ extern "C" shlr_status shlr_lowrank_lines_noalloc(int32_t precision, int32_t n_m
 #include "spirit_host.inc"
 #include "unrolled.inc"
 #include "autotune.inc"
+#include "eval_host.inc"

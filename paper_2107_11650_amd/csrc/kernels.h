@@ -136,4 +136,27 @@ bool tridiag_rr_supported(int smax, bool fp32);
 hipError_t launch_tridiag_rr(hipStream_t st, const LRDesc* descs, int m0, int count, double2* Gs, int64_t g_stride,
                              double* scr, int64_t scr_stride, int smax, bool fp32);
 
+// ---- evaluation step (eval.hip) ----
+constexpr int EVAL_MAX_PARTIALS = 8190;   // per-block partials a 64 KiB work buffer holds, with 2 result slots
+constexpr int T2_MAX_ECHOES = 32;
+struct TeList {
+    int L;
+    double te[T2_MAX_ECHOES];
+};
+template <typename R>
+hipError_t launch_ssos(hipStream_t st, const cplx_t<R>* x, R* out, int n_img, int J, int64_t MN);
+template <typename R>
+hipError_t launch_rlne(hipStream_t st, const R* a, const R* b, const uint8_t* roi, int64_t count, double* work,
+                       int* n_partials);
+template <typename R>
+hipError_t launch_mssim(hipStream_t st, const R* a, const R* b, int M, int N, double c1, double c2, double sigma,
+                        double* work, int* n_partials);
+// fixed-order sum (mode 0) or max (mode 1) of n partials (stride apart) into out[0]
+hipError_t launch_reduce_partials(hipStream_t st, const double* partials, int n, int stride, int mode, double* out);
+template <typename R>
+hipError_t launch_max_real(hipStream_t st, const R* a, int64_t count, double* work, double* out);
+template <typename R>
+hipError_t launch_t2_fit(hipStream_t st, const R* img, int64_t npix, const TeList& te, double roi_frac, double t2_min,
+                         double t2_max, R* t2, R* rho, uint8_t* roi, double* work);
+
 }  // namespace shlr

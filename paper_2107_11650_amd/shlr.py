@@ -40,8 +40,9 @@ EXPORTED = [
     "shlr_last_error", "shlr_version", "shlr_timing_enable", "shlr_timing_enable_phases", "shlr_timing_read",
     "shlr_unrolled_sizes", "shlr_unrolled_forward", "shlr_unrolled_backward", "shlr_autotune",
     "shlr_params_default", "shlr_unit_status", "shlr_set_eig_check", "shlr_set_weights",
-    "shlr_lowrank_lines_noalloc",
+    "shlr_lowrank_lines_noalloc", "shlr_ssos", "shlr_rlne", "shlr_mssim", "shlr_t2_fit",
 ]
+EVAL_WORK_BYTES = 65536
 TIMING_PHASES = ("xupdate", "gram", "eig", "reproj", "spirit", "tridiag")
 
 
@@ -96,6 +97,11 @@ _lib.shlr_params_default.argtypes = [_i32, _vp]
 _lib.shlr_unit_status.argtypes = [_vp, _i32, _vp, _vp, _vp]
 _lib.shlr_set_eig_check.argtypes = [_vp, ctypes.c_double]
 _lib.shlr_set_weights.argtypes = [_vp, _vp, _vp]
+_lib.shlr_ssos.argtypes = [_i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp]
+_lib.shlr_rlne.argtypes = [_i32, ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]
+_lib.shlr_mssim.argtypes = [_i32, _i32, _i32, _vp, _vp, ctypes.c_double, _vp, ctypes.POINTER(ctypes.c_double), _vp]
+_lib.shlr_t2_fit.argtypes = [_i32, _i32, ctypes.c_int64, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                             _vp, _vp, _vp, _vp, _vp]
 _lib.shlr_lowrank_lines_noalloc.argtypes = [_i32, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
 _lib.shlr_timing_enable.argtypes = [_vp, _i32]
@@ -410,6 +416,70 @@ def lowrank_lines_noalloc(h, D, k, beta, tau, thr, use_vc=False, use_w=True, ran
                                            float(thr), _ptr(h), _ptr(D), _ptr(b), _ptr(rk) if ranks else None,
                                            _stream()))
     return (b, rk) if ranks else b
+
+
+# -- evaluation step (see shlr_ssos / shlr_rlne / shlr_mssim / shlr_t2_fit in include/shlr.h) --
+
+def _real_prec(t):
+    import torch
+    return PREC_FP64 if t.dtype in (torch.float64, torch.complex128) else PREC_MIXED
+
+
+def _eval_work(device):
+    import torch
+    return torch.empty(EVAL_WORK_BYTES // 8, dtype=torch.float64, device=device)
+
+
+def ssos(k):
+    """SSOS images of multi-coil k-space (..., J, M, N) complex -> (..., M, N) real (same precision)."""
+    import torch
+    k = k.contiguous()
+    J, M, N = k.shape[-3:]
+    n_img = k.numel() // (J * M * N)
+    work = torch.empty_like(k)
+    out = torch.empty(k.shape[:-3] + (M, N), dtype=torch.float64 if k.dtype == torch.complex128 else torch.float32,
+                      device=k.device)
+    _check(_lib.shlr_ssos(_real_prec(k), n_img, J, M, N, _ptr(k), _ptr(work), _ptr(out), _stream()))
+    return out
+
+
+def rlne(ref, rec, roi=None):
+    """Eq. S10 between two real device images (optionally over a uint8 ROI)."""
+    ref, rec = ref.contiguous(), rec.to(ref.dtype).contiguous()
+    w = _eval_work(ref.device)
+    v = ctypes.c_double()
+    _check(_lib.shlr_rlne(_real_prec(ref), ref.numel(), _ptr(ref), _ptr(rec),
+                          None if roi is None else _ptr(roi.contiguous()), _ptr(w), ctypes.byref(v), _stream()))
+    return v.value
+
+
+def mssim(ref, rec, dyn_range=0.0):
+    """Eq. S11 between two real M x N device images."""
+    ref, rec = ref.contiguous(), rec.to(ref.dtype).contiguous()
+    M, N = ref.shape[-2:]
+    w = _eval_work(ref.device)
+    v = ctypes.c_double()
+    _check(_lib.shlr_mssim(_real_prec(ref), M, N, _ptr(ref), _ptr(rec), float(dyn_range), _ptr(w), ctypes.byref(v),
+                           _stream()))
+    return v.value
+
+
+def t2_fit(img, te, roi_frac=0.1, t2_min=5.0, t2_max=500.0):
+    """T2 map of echo images img (L, ...) real on the device: returns (t2, rho, roi) tensors."""
+    import numpy as np
+    import torch
+    img = img.contiguous()
+    L = img.shape[0]
+    npix = img.numel() // L
+    te = np.ascontiguousarray(np.asarray(te, dtype=np.float64))
+    t2 = torch.empty(img.shape[1:], dtype=img.dtype, device=img.device)
+    rho = torch.empty_like(t2)
+    roi = torch.empty(img.shape[1:], dtype=torch.uint8, device=img.device)
+    w = _eval_work(img.device)
+    _check(_lib.shlr_t2_fit(_real_prec(img), L, npix, te.ctypes.data_as(ctypes.c_void_p), _ptr(img),
+                            float(roi_frac), float(t2_min), float(t2_max), _ptr(t2), _ptr(rho), _ptr(roi), _ptr(w),
+                            _stream()))
+    return t2, rho, roi
 
 
 def _unrolled_function():
