@@ -181,6 +181,88 @@ def diff_leg(batch, steps, kw, lam, beta, reps=2):
     }
 
 
+def quality_leg(t2_iters=30):
+    """Synthetic analogues of the paper's comparisons, scored on the GPU (SSOS, RLNE, MSSIM, T2 fit):
+    SHLR / -S / -V / -SV at Gaussian Cartesian 0.34 with 22 ACS lines (as in Fig. 4), SHLR-SV over
+    8..22 ACS lines at the same rate (Fig. 11), SHLR-SV under the other patterns (Figs. 7, 9, S1,
+    S2), and SHLR-P / SHLR-VP T2 maps at R = 6 (Figs. 6, 10) against the map of the fully sampled
+    series.  Every PI run uses the paper's Algorithm S1 settings (cap 50, tolerance 1e-6)."""
+    import numpy as np
+    import torch
+    from paper_2107_11650_amd import inputs as I, shlr
+    J, M, N = 8, 256, 256
+    k = I.phantom_kspace(J, M, N, seed=1000)
+    kd = torch.from_numpy(k).to(torch.complex64).cuda()
+    truth = shlr.ssos(kd)
+    kw = 25
+
+    def run(mask, vc, spirit, acs):
+        Y = I.undersample(k, mask)
+        p = shlr.Params.paper_defaults(shlr.MODEL_PI, M=(M,), N=(N,), J=J, k_row=kw, k_col=kw, use_vc=vc,
+                                       lam=1e4, lambda1=10.0 if spirit else 0.0, beta=30.0, tau=30.0,
+                                       spirit_ksize=5 if spirit else 0, n_cg=10)
+        plan = shlr.Plan(p)
+        plan.init(torch.from_numpy(Y).to(torch.complex64).cuda(), torch.from_numpy(mask.astype(np.uint8)).cuda())
+        if spirit:
+            plan.calibrate_spirit(acs=acs, reg=1e-3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = plan.iterate(p.max_iter)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        img = shlr.ssos(plan.kspace())
+        plan.close()
+        return {"rlne": shlr.rlne(truth, img), "mssim": shlr.mssim(truth, img), "iterations": info.iters_done,
+                "it_per_s": info.iters_done / (t1 - t0), "rate": round(I.sampling_rate(mask), 4)}
+
+    out = {"workload": "8-coil 256x256 phantom (seed 1000), window 25, lambda 1e4, lambda1 10, beta = tau = 30, "
+                       "cap 50 iterations, tolerance 1e-6; scored against the fully sampled SSOS image"}
+    cart = I.mask_gaussian_cartesian(M, N, rate=0.34, n_acs=22, seed=2000)
+    out["models_cartesian_0.34"] = {name: run(cart, vc, sp, 22) for name, vc, sp in
+                                    (("SHLR", False, False), ("SHLR-S", False, True), ("SHLR-V", True, False),
+                                     ("SHLR-SV", True, True))}
+    out["acs_sweep_shlr_sv"] = {str(a): run(I.mask_gaussian_cartesian(M, N, rate=0.34, n_acs=a, seed=2000), True,
+                                            True, a) for a in range(8, 23, 2)}
+    pats = {"uniform_R6_acs20": (I.mask_uniform_cartesian(M, N, R=6, n_acs=20), 20),
+            "cartesian_pf3/4_0.30": (I.mask_gaussian_cartesian(M, N, rate=0.30, n_acs=22, seed=2000, pf=0.75), 22),
+            "random2d_0.18": (I.mask_random_2d(M, N, rate=0.18, acs=16, seed=2000), 16),
+            "random2d_pf4/5_0.17": (I.mask_random_2d(M, N, rate=0.17, acs=16, seed=2000, pf=0.8), 16),
+            "uniform_R6_pf3/4": (I.mask_uniform_cartesian(M, N, R=6, n_acs=20, pf=0.75), 20)}
+    out["patterns_shlr_sv"] = {name: run(m, True, True, a) for name, (m, a) in pats.items()}
+    # T2 maps (SHLR-P / SHLR-VP)
+    L, J2 = 8, 12
+    te = 10.0 * (np.arange(L) + 1)
+    k2 = I.t2_kspace(J2, M, N, L=L, seed=1004)
+    m2 = I.mask_t2_cartesian(L, N, R=6, n_center=16)
+    t2_true, _, roi = shlr.t2_fit(shlr.ssos(torch.from_numpy(k2).to(torch.complex64).cuda()), te)
+    res = {}
+    for name, vc in (("SHLR-P", False), ("SHLR-VP", True)):
+        p = shlr.Params(model=shlr.MODEL_PARAM, M=(M,), N=(N,), J=J2, L=L, k_row=kw, k_col=4, use_vc=vc, lam=1e4,
+                        lambda2=2.0, beta=30.0, tau=30.0)
+        plan = shlr.Plan(p)
+        plan.init(torch.from_numpy(I.undersample(k2, m2[:, None, None, :])).to(torch.complex64).cuda(),
+                  torch.from_numpy(m2.astype(np.uint8)).cuda())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.iterate(t2_iters)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        img = shlr.ssos(plan.kspace())
+        plan.close()
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        t2_rec, _, _ = shlr.t2_fit(img, te)
+        torch.cuda.synchronize()
+        f1 = time.perf_counter()
+        res[name] = {"t2_map_rlne": shlr.rlne(t2_true, t2_rec, roi), "iterations": t2_iters,
+                     "it_per_s": t2_iters / (t1 - t0), "t2_fit_ms": 1e3 * (f1 - f0)}
+    out["t2_maps_R6"] = {"workload": "T2 series 8 echoes x 12 coils x 256x256 (seed 1004), per-echo shifted R=6 + 16 "
+                                     "centre lines, PE window 25, echo window 4, lambda 1e4, lambda2 2, beta = tau = 30; "
+                                     "T2 maps fitted to the SSOS echo images (ROI 0.1, range 5..500 ms), RLNE over the "
+                                     "ROI of the fully sampled map", "roi_pixels": int(roi.sum().item()), **res}
+    return out
+
+
 def timed_run(plan, steps, warmup, check_iters):
     """The accuracy-check iterations, the warm-up with every phase timed, then `steps` iterations timed
     with HIP events around the dominant phase only (each timed phase adds an event pair per launch)."""
@@ -225,6 +307,9 @@ def main():
     ap.add_argument("--precision", choices=["mixed", "fp64", "mixed-r32"], default="mixed",
                     help="mixed: FP32 MFMA products, FP64 eigen-solve (the default); fp64: FP64 throughout; "
                          "mixed-r32: the opt-in form whose Householder reduction runs in FP32")
+    ap.add_argument("--quality-only", action="store_true",
+                    help="only run the synthetic quality comparisons (models, ACS sweep, patterns, T2 maps) and "
+                         "print them as one JSON line")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the comparison runs of the other precision forms on the same workload")
     ap.add_argument("--workload", choices=["pi256", "ragged", "t2"], default="pi256",
@@ -258,6 +343,9 @@ def main():
         print(json.dumps({"copy_probe_bytes": 4 * n, "copies": 3}))
         return
     from paper_2107_11650_amd import shlr
+    if args.quality_only:
+        print(json.dumps(quality_leg()))
+        return
 
     kw, lam, lam1, beta = 25, 1e4, 10.0, 30.0
     precs = {"mixed": shlr.PREC_MIXED, "fp64": shlr.PREC_FP64, "mixed-r32": shlr.PREC_MIXED_R32}

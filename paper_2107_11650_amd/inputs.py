@@ -215,6 +215,66 @@ def mask_t2_cartesian(L: int, N: int, R: int = 6, n_center: int = 16):
 
 
 # ---------------------------------------------------------------------------
+# the paper's other sampling patterns (parallel imaging, Section IV-A and Supplement S3)
+# ---------------------------------------------------------------------------
+
+def _acs_rows(M: int, n_acs: int):
+    c = M // 2
+    return set(range(c - n_acs // 2, c - n_acs // 2 + n_acs))
+
+
+def _pf_rows(M: int, pf: float):
+    """Rows a partial-Fourier acquisition keeps: the first round(pf M) phase-encode rows, which hold
+    the k-space centre and one side of it."""
+    return np.arange(M) < int(round(pf * M))
+
+
+def mask_uniform_cartesian(M: int, N: int, R: int = 6, n_acs: int = 20, pf: float = 1.0):
+    """Uniform Cartesian undersampling: every R-th phase-encode row (the centre row among them),
+    plus n_acs central ACS rows, optionally cut to partial Fourier pf (e.g. 3/4)."""
+    c = M // 2
+    rows = ((np.arange(M) - c) % R) == 0
+    rows[list(_acs_rows(M, n_acs))] = True
+    rows &= _pf_rows(M, pf)
+    return np.repeat(rows[:, None], N, axis=1)
+
+
+def mask_gaussian_cartesian(M: int, N: int, rate: float = 0.34, n_acs: int = 22, seed: int = 2000,
+                            pf: float = 1.0, width: float = 0.3):
+    """Gaussian variable-density Cartesian undersampling at a total sampling rate: round(rate M)
+    phase-encode rows, n_acs central ACS rows among them, the others drawn without replacement
+    with density exp(-(k / (width M))^2) in the centred row index k, only from the rows a partial-
+    Fourier acquisition pf keeps."""
+    rng = np.random.default_rng(seed)
+    c = M // 2
+    keep = _pf_rows(M, pf)
+    acs = sorted(i for i in _acs_rows(M, n_acs) if keep[i])
+    rest = np.array([i for i in range(M) if keep[i] and i not in set(acs)])
+    kc = (rest - c).astype(np.float64)
+    p = np.exp(-(kc / (width * M)) ** 2)
+    p /= p.sum()
+    n_extra = max(0, min(len(rest), int(round(rate * M)) - len(acs)))
+    extra = rng.choice(rest, size=n_extra, replace=False, p=p)
+    rows = np.zeros(M, dtype=bool)
+    rows[acs] = True
+    rows[extra] = True
+    return np.repeat(rows[:, None], N, axis=1)
+
+
+def mask_random_2d(M: int, N: int, rate: float = 0.18, acs: int = 16, seed: int = 2000, pf: float = 1.0):
+    """2D random undersampling at a sampling rate: the Poisson-disc pattern (radially growing radius,
+    fully sampled acs x acs centre) tuned to rate / pf of the points, then cut to partial Fourier pf
+    along the first axis (so the kept part carries about the requested total rate)."""
+    m = mask_poisson_disc(M, N, R=pf / rate, acs=acs, seed=seed)
+    m &= _pf_rows(M, pf)[:, None]
+    return m
+
+
+def sampling_rate(mask) -> float:
+    return float(np.mean(mask))
+
+
+# ---------------------------------------------------------------------------
 # random states for step-level tests
 # ---------------------------------------------------------------------------
 
