@@ -229,6 +229,20 @@ def quality_leg(t2_iters=30):
             "random2d_pf4/5_0.17": (I.mask_random_2d(M, N, rate=0.17, acs=16, seed=2000, pf=0.8), 16),
             "uniform_R6_pf3/4": (I.mask_uniform_cartesian(M, N, R=6, n_acs=20, pf=0.75), 20)}
     out["patterns_shlr_sv"] = {name: run(m, True, True, a) for name, (m, a) in pats.items()}
+    # parameter sweeps (Supplement S5): lambda and lambda1 of SHLR-SV at Cartesian 0.34
+    def run_prm(lam, lam1):
+        Y = I.undersample(k, cart)
+        p = shlr.Params.paper_defaults(shlr.MODEL_PI, M=(M,), N=(N,), J=J, k_row=kw, k_col=kw, use_vc=True,
+                                       lam=lam, lambda1=lam1, beta=30.0, tau=30.0, spirit_ksize=5, n_cg=10)
+        plan = shlr.Plan(p)
+        plan.init(torch.from_numpy(Y).to(torch.complex64).cuda(), torch.from_numpy(cart.astype(np.uint8)).cuda())
+        plan.calibrate_spirit(acs=22, reg=1e-3)
+        info = plan.iterate(p.max_iter)
+        img = shlr.ssos(plan.kspace())
+        plan.close()
+        return {"rlne": shlr.rlne(truth, img), "mssim": shlr.mssim(truth, img), "iterations": info.iters_done}
+    out["lambda_sweep_shlr_sv"] = {f"{v:g}": run_prm(v, 10.0) for v in (1e2, 1e3, 1e4, 1e5, 1e6)}
+    out["lambda1_sweep_shlr_sv"] = {f"{v:g}": run_prm(1e4, v) for v in (0.1, 1.0, 10.0, 1e2, 1e3, 1e4)}
     # T2 maps (SHLR-P / SHLR-VP)
     L, J2 = 8, 12
     te = 10.0 * (np.arange(L) + 1)
@@ -256,6 +270,18 @@ def quality_leg(t2_iters=30):
         f1 = time.perf_counter()
         res[name] = {"t2_map_rlne": shlr.rlne(t2_true, t2_rec, roi), "iterations": t2_iters,
                      "it_per_s": t2_iters / (t1 - t0), "t2_fit_ms": 1e3 * (f1 - f0)}
+    lam2_sweep = {}
+    for l2 in (0.5, 1.0, 2.0, 5.0, 10.0):
+        p = shlr.Params(model=shlr.MODEL_PARAM, M=(M,), N=(N,), J=J2, L=L, k_row=kw, k_col=4, use_vc=True, lam=1e4,
+                        lambda2=l2, beta=30.0, tau=30.0)
+        plan = shlr.Plan(p)
+        plan.init(torch.from_numpy(I.undersample(k2, m2[:, None, None, :])).to(torch.complex64).cuda(),
+                  torch.from_numpy(m2.astype(np.uint8)).cuda())
+        plan.iterate(t2_iters)
+        t2_rec, _, _ = shlr.t2_fit(shlr.ssos(plan.kspace()), te)
+        plan.close()
+        lam2_sweep[f"{l2:g}"] = {"t2_map_rlne": shlr.rlne(t2_true, t2_rec, roi)}
+    res["lambda2_sweep_shlr_vp"] = lam2_sweep
     out["t2_maps_R6"] = {"workload": "T2 series 8 echoes x 12 coils x 256x256 (seed 1004), per-echo shifted R=6 + 16 "
                                      "centre lines, PE window 25, echo window 4, lambda 1e4, lambda2 2, beta = tau = 30; "
                                      "T2 maps fitted to the SSOS echo images (ROI 0.1, range 5..500 ms), RLNE over the "
@@ -355,6 +381,12 @@ def main():
     k_check, warm, n_warm, phases, dom = run["k_check"], run["warm"], run["n_warm"], run["phases"], run["dom"]
     elapsed = run["elapsed"]
     value = args.steps / elapsed
+    # the same iterations as replays of the captured one-iteration graph (no per-phase events inside)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    plan.iterate_async(args.steps, graph=True)
+    torch.cuda.synchronize()
+    g1 = time.perf_counter()
 
     # roofline of the dominant kernel: algorithmic work of one iteration / launches per iteration
     csize = 16 if prec == shlr.PREC_FP64 else 8
@@ -400,6 +432,10 @@ def main():
         "phases_timed_over": "warm-up iterations, every phase timed" if n_warm == args.warmup and args.warmup > 0
                              else "timed iterations",
         "roofline": roof,
+        "graph_replay": {"value": args.steps / (g1 - g0), "ms_per_step": 1e3 * (g1 - g0) / args.steps,
+                         "how": "the same step count right after the timed region, as replays of the hipGraph of one "
+                                "iteration (shlr_iterate_graph); value above is the eager path with HIP events on the "
+                                "dominant phase"},
     }
 
     # the low-rank step per iteration, from the phase times of the warm-up: the contraction kernels
@@ -446,6 +482,16 @@ def main():
             "sample": f"the first {args.check_iters} iterations of the same workload (NumPy FP64, LAPACK SVD "
                       f"per lift, SPIRiT kernel calibrated beforehand)",
         }
+        # the same oracle on one host thread, over its first iteration (a bounded sample)
+        from threadpoolctl import threadpool_limits
+        prm1 = O.PIParams(k_row=kw, k_col=kw, lam=lam, lam1=lam1, beta=beta, n_cg=args.n_cg, iters=1)
+        with threadpool_limits(limits=1):
+            c2 = time.perf_counter()
+            O.shlr_pi(Y, mask.astype(bool), prm1, g=g)
+            c3 = time.perf_counter()
+        result["cpu_baseline"]["single_thread"] = {
+            "value": 1.0 / (c3 - c2), "unit": "iterations/s", "cores": 1,
+            "sample": "the first iteration of the same workload, BLAS limited to one thread"}
         result["nmse_vs_oracle"] = O.nmse(k_check, k_ref)
         result["nmse_iters"] = args.check_iters
         if not args.no_forms:

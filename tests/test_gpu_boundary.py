@@ -101,3 +101,32 @@ def test_caller_weights_param(prec):
     out = host(plan.kspace())
     plan.close()
     check(out, ref, *BARS[prec], label=f"PARAM weights {prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replays_with_spirit_match_eager(prec):
+    """The captured iteration with the SPIRiT PCG X-update: each replay, with eager work and a
+    synchronisation between replays (reading K back), equals the eager iteration bit for bit."""
+    shlr = _lib()
+    J, M, N = 4, 48, 40
+    k = inputs.phantom_kspace(J, M, N, seed=1008)
+    mask = inputs.mask_poisson_disc(M, N, R=3.0, acs=16, seed=2008)
+    Y = inputs.undersample(k, mask)
+    p = shlr.Params(M=(M,), N=(N,), J=J, k_row=6, k_col=6, use_vc=True, lam=1e4, lambda1=10.0, beta=10.0, tau=10.0,
+                    n_cg=6, spirit_ksize=5, precision=shlr.PREC_FP64 if prec == "fp64" else shlr.PREC_MIXED)
+    runs = []
+    for graph in (False, True):
+        plan = shlr.Plan(p)
+        plan.init(dev(Y, plan.cdtype), dev(mask.astype(np.uint8), torch.uint8))
+        plan.calibrate_spirit(acs=16, reg=1e-3)
+        ks = []
+        for _ in range(4):
+            plan.iterate(1, graph=graph)
+            ks.append(host(plan.kspace()))
+        plan.close()
+        runs.append(ks)
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+    g = O.spirit_calibrate(Y / np.abs(Y).max(), acs=16, ks=5)
+    ref = O.shlr_pi(Y, mask, O.PIParams(k_row=6, k_col=6, lam=1e4, lam1=10.0, beta=10.0, vc=True, n_cg=6, iters=4), g=g)
+    check(runs[1][-1], ref, *BARS[prec], label=f"graph SHLR-SV {prec}")
