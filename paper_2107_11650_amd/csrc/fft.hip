@@ -216,21 +216,52 @@ __device__ inline void store_lines_centred(C* dstg, const C* res, const LineAddr
     }
 }
 
+// block `blk` of a line-transform launch: lines [blk NL, blk NL + NL)
 template <typename R>
-__global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(const cplx_t<R>* in, cplx_t<R>* out, LineAddr ia,
-                                                           LineAddr oa, FftPlan pl, int n_lines, int NL, int inverse,
-                                                           R scale) {
+__device__ inline void fft_lines_block(unsigned char* smem, const cplx_t<R>* in, cplx_t<R>* out, const LineAddr& ia,
+                                       const LineAddr& oa, const FftPlan& pl, int n_lines, int NL, int inverse,
+                                       R scale, int blk) {
     using C = cplx_t<R>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = pl.n, ls = pl.f;
     const int tid = threadIdx.x;
-    const FftLds<C> L = fft_setup<C>(smem_raw, pl, NL, tid, FFT_THREADS);
-    const int g0 = blockIdx.x * NL;
+    const FftLds<C> L = fft_setup<C>(smem, pl, NL, tid, FFT_THREADS);
+    const int g0 = blk * NL;
     const int nl = min(NL, n_lines - g0);
     load_lines_centred(L.b0, in, ia, g0, nl, n, ls, tid, FFT_THREADS);
     __syncthreads();
     C* res = dft_run(L, nl, pl, inverse != 0, tid, FFT_THREADS);
     store_lines_centred(out, res, oa, g0, nl, n, ls, scale, tid, FFT_THREADS);
+}
+
+template <typename R>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(const cplx_t<R>* in, cplx_t<R>* out, LineAddr ia,
+                                                           LineAddr oa, FftPlan pl, int n_lines, int NL, int inverse,
+                                                           R scale) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    fft_lines_block<R>(smem_raw, in, out, ia, oa, pl, n_lines, NL, inverse, scale, blockIdx.x);
+}
+
+// the segment of a segmented launch that owns block b (segments sorted by first block)
+template <typename S>
+__device__ inline int find_seg(const S* segs, int n_seg, int b) {
+    int lo = 0, hi = n_seg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].block0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One launch over the lines of several slices (segments of their own length and plan).
+template <typename R>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_lines_seg(const cplx_t<R>* in, cplx_t<R>* out,
+                                                               const FftSeg* __restrict__ segs, int n_seg) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int si = find_seg(segs, n_seg, blockIdx.x);
+    const FftSeg sg = segs[si];
+    fft_lines_block<R>(smem_raw, in, out, sg.ia, sg.oa, sg.pl, sg.n_lines, sg.NL, sg.inverse, (R)sg.scale,
+                       blockIdx.x - sg.block0);
 }
 
 // ---------------------------------------------------------------------------
@@ -252,23 +283,19 @@ __device__ inline int64_t row_off(const RowAddr& a, int d2, int d1, int d0) {
 }
 
 template <typename R>
-__global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __restrict__ base_bo,
-                                                           const cplx_t<R>* __restrict__ base_a,
-                                                           const cplx_t<R>* __restrict__ base_y,
-                                                           cplx_t<R>* __restrict__ base_k,
-                                                           cplx_t<R>* __restrict__ base_out,
-                                                           const uint8_t* __restrict__ base_m,
-                                                           const R* __restrict__ rtab, XupdRows x, FftPlan pl,
-                                                           int NL, R lam, R beta, int hard_dc,
-                                                           double* __restrict__ change_acc,
-                                                           const int32_t* __restrict__ active, int rhs_only) {
+__device__ inline void xupd_rows_block(unsigned char* smem_raw, const cplx_t<R>* __restrict__ base_bo,
+                                       const cplx_t<R>* __restrict__ base_a, const cplx_t<R>* __restrict__ base_y,
+                                       cplx_t<R>* __restrict__ base_k, cplx_t<R>* __restrict__ base_out,
+                                       const uint8_t* __restrict__ base_m, const R* __restrict__ rtab,
+                                       const XupdRows& x, const FftPlan& pl, int NL, R lam, R beta, int hard_dc,
+                                       double* __restrict__ change_acc, const int32_t* __restrict__ active,
+                                       int rhs_only, int blk) {
     using C = cplx_t<R>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = x.n, ls = pl.f;
     const int tid = threadIdx.x;
     const FftLds<C> L = fft_setup<C>(smem_raw, pl, NL, tid, FFT_THREADS);
     C* b0 = L.b0;
-    const int g0 = blockIdx.x * NL;
+    const int g0 = blk * NL;
     const int nl = min(NL, x.n_rows - g0);
     const int c = n / 2;
     const R sc = (R)(1.0 / sqrt((double)n));
@@ -401,6 +428,39 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __re
             base_out[row_off(x.out, d2, d1, d0) + (int64_t)i * x.out.es] = cscale(res2[line * ls + f], sc);
         }
     }
+}
+
+template <typename R>
+__global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows(const cplx_t<R>* __restrict__ base_bo,
+                                                           const cplx_t<R>* __restrict__ base_a,
+                                                           const cplx_t<R>* __restrict__ base_y,
+                                                           cplx_t<R>* __restrict__ base_k,
+                                                           cplx_t<R>* __restrict__ base_out,
+                                                           const uint8_t* __restrict__ base_m,
+                                                           const R* __restrict__ rtab, XupdRows x, FftPlan pl,
+                                                           int NL, R lam, R beta, int hard_dc,
+                                                           double* __restrict__ change_acc,
+                                                           const int32_t* __restrict__ active, int rhs_only) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    xupd_rows_block<R>(smem_raw, base_bo, base_a, base_y, base_k, base_out, base_m, rtab, x, pl, NL, lam, beta,
+                       hard_dc, change_acc, active, rhs_only, blockIdx.x);
+}
+
+// One launch of the fused X-update over the rows of several slices; each segment's arrays sit at its
+// own offsets from the arena bases, and its stop unit indexes the change sums and the active flags.
+template <typename R>
+__global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows_seg(cplx_t<R>* cbase, const uint8_t* mbase,
+                                                               const R* __restrict__ rtab,
+                                                               const XupdSeg* __restrict__ segs, int n_seg, R lam,
+                                                               R beta, int hard_dc, double* change,
+                                                               const int32_t* active) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int si = find_seg(segs, n_seg, blockIdx.x);
+    const XupdSeg sg = segs[si];
+    xupd_rows_block<R>(smem_raw, cbase + sg.bo, cbase + sg.a, cbase + sg.y, cbase + sg.k, cbase + sg.out,
+                       mbase + sg.m, rtab, sg.x, sg.pl, sg.NL, lam, beta, hard_dc,
+                       change ? change + 2 * sg.unit : nullptr, active ? active + sg.unit : nullptr, 0,
+                       blockIdx.x - sg.block0);
 }
 
 // ---------------------------------------------------------------------------
@@ -788,6 +848,65 @@ hipError_t launch_xupd_rows(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>
 }
 
 template <typename R>
+FftSeg make_fft_seg(int n, int n_lines, int inverse, double scale, const LineAddr& ia, const LineAddr& oa, int block0,
+                    size_t* lds) {
+    FftSeg g;
+    g.pl = make_fft_plan(n);
+    g.NL = fft_lines_per_block<R>(g.pl, ia.es != 1 || oa.es != 1);
+    g.ia = ia;
+    g.oa = oa;
+    g.n_lines = n_lines;
+    g.block0 = block0;
+    g.inverse = inverse;
+    g.scale = scale;
+    *lds = fft_lds_bytes<R>(g.pl, g.NL);
+    return g;
+}
+template <typename R>
+XupdSeg make_xupd_seg(const XupdRows& x, int block0, int unit, int64_t bo, int64_t a, int64_t y, int64_t k,
+                      int64_t out, int64_t m, size_t* lds) {
+    XupdSeg g;
+    g.pl = make_fft_plan(x.n);
+    g.NL = fft_lines_per_block<R>(g.pl, x.bo.es != 1 || x.out.es != 1);
+    g.x = x;
+    g.block0 = block0;
+    g.unit = unit;
+    g.bo = bo;
+    g.a = a;
+    g.y = y;
+    g.k = k;
+    g.out = out;
+    g.m = m;
+    *lds = fft_lds_bytes<R>(g.pl, g.NL);
+    return g;
+}
+int fft_seg_blocks(const FftSeg& g) { return (g.n_lines + g.NL - 1) / g.NL; }
+int xupd_seg_blocks(const XupdSeg& g) { return (g.x.n_rows + g.NL - 1) / g.NL; }
+
+template <typename R>
+hipError_t launch_fft_lines_seg(hipStream_t st, const cplx_t<R>* in, cplx_t<R>* out, const FftSeg* segs_dev,
+                                int n_seg, int blocks, size_t lds) {
+    if (blocks <= 0) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)k_fft_lines_seg<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fft_lines_seg<R>), dim3(blocks), dim3(FFT_THREADS), lds, st, in, out, segs_dev, n_seg);
+    return hipGetLastError();
+}
+template <typename R>
+hipError_t launch_xupd_rows_seg(hipStream_t st, cplx_t<R>* cbase, const uint8_t* mbase, const R* rtab,
+                                const XupdSeg* segs_dev, int n_seg, int blocks, size_t lds, double lam, double beta,
+                                int hard_dc, double* change, const int32_t* active) {
+    if (blocks <= 0) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)k_xupd_rows_seg<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_xupd_rows_seg<R>), dim3(blocks), dim3(FFT_THREADS), lds, st, cbase, mbase, rtab, segs_dev,
+                       n_seg, (R)lam, (R)beta, hard_dc, change, active);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_xupd_rows_rhs(hipStream_t st, const cplx_t<R>* bo, const cplx_t<R>* a, const cplx_t<R>* y,
                                 cplx_t<R>* rhs, const uint8_t* m, const R* rtab, const XupdRows& x, double lam,
                                 double beta) {
@@ -929,6 +1048,13 @@ hipError_t launch_fft_rows_apply(hipStream_t st, cplx_t<R>* io, const cplx_t<R>*
     template hipError_t launch_fill_hash<R>(hipStream_t, cplx_t<R>*, int64_t, uint64_t, double);                     \
     template hipError_t launch_maxabs<R>(hipStream_t, const cplx_t<R>*, int64_t, unsigned long long*, uint32_t*);   \
     template int spirit_fused_blocks<R>(int, int, int);                                                              \
+    template FftSeg make_fft_seg<R>(int, int, int, double, const LineAddr&, const LineAddr&, int, size_t*);       \
+    template XupdSeg make_xupd_seg<R>(const XupdRows&, int, int, int64_t, int64_t, int64_t, int64_t, int64_t,     \
+                                      int64_t, size_t*);                                                          \
+    template hipError_t launch_fft_lines_seg<R>(hipStream_t, const cplx_t<R>*, cplx_t<R>*, const FftSeg*, int, int,  \
+                                                size_t);                                                         \
+    template hipError_t launch_xupd_rows_seg<R>(hipStream_t, cplx_t<R>*, const uint8_t*, const R*, const XupdSeg*,   \
+                                                int, int, size_t, double, double, int, double*, const int32_t*);  \
     template hipError_t launch_change_pair<R>(hipStream_t, const cplx_t<R>*, const cplx_t<R>*, int64_t, double*,     \
                                               const int32_t*, cplx_t<R>*);                                           \
     template hipError_t launch_fft_rows_dir<R>(hipStream_t, cplx_t<R>*, const cplx_t<R>*, cplx_t<R>*, int, int,        \

@@ -175,6 +175,12 @@ struct shlr_plan {
     size_t off_m = 0, bytes_m = 0;      // mask arena
     size_t off_desc = 0, off_g = 0, off_s = 0, off_scr = 0, off_ranks = 0, off_scal = 0;
     size_t off_spirit = 0, bytes_spirit = 0;
+    // segmented launches of the X-update phase (PI): every slice's lines in one launch per step
+    std::vector<FftSeg> seg_fwd, seg_inv;   // column transforms B_row -> A and K -> H_row
+    std::vector<XupdSeg> seg_x;             // fused row transform, Eq. 15 division, inverse (no SPIRiT)
+    int blk_fwd = 0, blk_inv = 0, blk_x = 0;
+    size_t lds_fwd = 0, lds_inv = 0, lds_x = 0;
+    size_t off_seg = 0, bytes_seg = 0;
     size_t total = 0;
     // host tables uploaded at bind
     std::vector<double> rtab;                      // real table (FP64, converted at upload)
@@ -411,6 +417,55 @@ extern "C" shlr_status shlr_params_default(int32_t model, shlr_params* p) {
     return SHLR_OK;
 }
 
+// Segment tables of the X-update phase of the PI model: one entry per slice, blocks numbered
+// consecutively over the slices, so that each step of the phase is one launch for the whole batch.
+template <typename R>
+static void build_segments(shlr_plan* P) {
+    const int J = P->p.J;
+    P->seg_fwd.clear();
+    P->seg_inv.clear();
+    P->seg_x.clear();
+    P->blk_fwd = P->blk_inv = P->blk_x = 0;
+    P->lds_fwd = P->lds_inv = P->lds_x = 0;
+    for (int si = 0; si < (int)P->sl.size(); ++si) {
+        const SliceLayout& L = P->sl[si];
+        const int M = L.M, N = L.N;
+        const int64_t MN = (int64_t)M * N;
+        size_t lds = 0;
+        // lines (j, n) along m
+        FftSeg f = make_fft_seg<R>(M, J * N, 0, 1.0 / sqrt((double)M), LineAddr{L.br, MN, 1, N, N},
+                                   LineAddr{L.a, MN, 1, N, N}, P->blk_fwd, &lds);
+        P->lds_fwd = std::max(P->lds_fwd, lds);
+        P->blk_fwd += fft_seg_blocks(f);
+        P->seg_fwd.push_back(f);
+        FftSeg g = make_fft_seg<R>(M, J * N, 1, 1.0 / sqrt((double)M), LineAddr{L.k, MN, 1, N, N},
+                                   LineAddr{L.hr, MN, 1, N, N}, P->blk_inv, &lds);
+        P->lds_inv = std::max(P->lds_inv, lds);
+        P->blk_inv += fft_seg_blocks(g);
+        P->seg_inv.push_back(g);
+        XupdRows x;
+        x.n = N;
+        x.n1 = J;
+        x.n0 = M;
+        x.n_rows = J * M;
+        x.rc_digit = 0;
+        x.bo = RowAddr{0, MN, 1, M};
+        x.a = RowAddr{0, MN, N, 1};
+        x.y = x.a;
+        x.k = x.a;
+        x.out = RowAddr{0, MN, 1, M};
+        x.msk = RowAddr{0, 0, N, 1};
+        x.rr_off = L.rr;
+        x.rc_off = L.rc;
+        XupdSeg xs = make_xupd_seg<R>(x, P->blk_x, si, L.bct, L.a, L.yn, L.k, L.hct, L.mask_b, &lds);
+        P->lds_x = std::max(P->lds_x, lds);
+        P->blk_x += xupd_seg_blocks(xs);
+        P->seg_x.push_back(xs);
+    }
+    P->bytes_seg = align256(P->seg_fwd.size() * sizeof(FftSeg)) + align256(P->seg_inv.size() * sizeof(FftSeg)) +
+                   align256(P->seg_x.size() * sizeof(XupdSeg));
+}
+
 extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
     if (!out) return fail(SHLR_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -615,6 +670,12 @@ extern "C" shlr_status shlr_plan_create(const shlr_params* p, shlr_plan** out) {
     P->off_spirit = off;
     P->bytes_spirit = spirit_bytes(P);
     off = align256(off + P->bytes_spirit);
+    if (p->model == SHLR_MODEL_PI) {
+        if (prec_c64(p->precision)) build_segments<float>(P);
+        else build_segments<double>(P);
+    }
+    P->off_seg = off;
+    off = align256(off + P->bytes_seg);
     P->total = off;
     P->scales.assign(p->n_slices, 1.0);
     *out = P;
@@ -653,6 +714,17 @@ static shlr_status upload_tables(shlr_plan* P) {
     }
     HIPCHK(hipMemcpyAsync(P->ws + P->off_desc, P->descs.data(), P->descs.size() * sizeof(LRDesc),
                           hipMemcpyHostToDevice, P->stream));
+    if (P->bytes_seg) {
+        unsigned char* d = P->ws + P->off_seg;
+        HIPCHK(hipMemcpyAsync(d, P->seg_fwd.data(), P->seg_fwd.size() * sizeof(FftSeg), hipMemcpyHostToDevice,
+                              P->stream));
+        d += align256(P->seg_fwd.size() * sizeof(FftSeg));
+        HIPCHK(hipMemcpyAsync(d, P->seg_inv.data(), P->seg_inv.size() * sizeof(FftSeg), hipMemcpyHostToDevice,
+                              P->stream));
+        d += align256(P->seg_inv.size() * sizeof(FftSeg));
+        HIPCHK(hipMemcpyAsync(d, P->seg_x.data(), P->seg_x.size() * sizeof(XupdSeg), hipMemcpyHostToDevice,
+                              P->stream));
+    }
     HIPCHK(hipStreamSynchronize(P->stream));   // host vectors go out of scope
     return SHLR_OK;
 }
@@ -795,19 +867,26 @@ static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_
     // group segment in the chunk, then one eigen-solver launch over the whole
     // chunk, then the reprojections.
     const double ortol = ortol_for(P);
+    std::vector<LRDesc> protos;
     for (const LRRun& run : P->runs) {
         for (int c0 = run.first; c0 < run.first + run.count; c0 += run.slots) {
             const int c1 = std::min(run.first + run.count, c0 + run.slots);
-            size_t e0 = 0;
-            STCHK(phase_begin(P, 1, &e0));
+            // the shapes of the groups in the chunk; a launch parameter the autotuner chose is kept
+            // where every group of the chunk agrees on it
+            protos.clear();
+            int gkc = -1, rkc = -1;
             for (int gi = run.g0; gi < run.g1; ++gi) {
                 const LRGroup& g = P->groups[gi];
-                const int s0 = std::max(c0, g.first), s1 = std::min(c1, g.first + g.count);
-                if (s0 >= s1) continue;
-                HIPCHK(launch_lift_gram<R>(P->stream, hb, db, wtab, desc_dev, g.proto, s0, s1 - s0,
-                                           G + (int64_t)(s0 - c0) * run.g_stride, run.g_stride, P->p.beta,
-                                           g.gram_kc));
+                if (std::max(c0, g.first) >= std::min(c1, g.first + g.count)) continue;
+                protos.push_back(g.proto);
+                gkc = gkc == -1 || gkc == g.gram_kc ? g.gram_kc : 0;
+                rkc = rkc == -1 || rkc == g.reproj_kc ? g.reproj_kc : 0;
             }
+            const int np = (int)protos.size();
+            size_t e0 = 0;
+            STCHK(phase_begin(P, 1, &e0));
+            HIPCHK(launch_lift_gram_multi<R>(P->stream, hb, db, wtab, desc_dev, protos.data(), np, c0, c1 - c0, G,
+                                             run.g_stride, P->p.beta, gkc));
             STCHK(phase_end(P, 1, e0));
             const bool r32 = prec_r32(P->p.precision);
             const int rr = run_uses_rr(run, r32);
@@ -823,14 +902,8 @@ static shlr_status run_lowrank(shlr_plan* P, cplx_t<R>* hb, cplx_t<R>* db, cplx_
                                               rr, P->eig_resid_lim));
             STCHK(phase_end(P, 2, e0));
             STCHK(phase_begin(P, 3, &e0));
-            for (int gi = run.g0; gi < run.g1; ++gi) {
-                const LRGroup& g = P->groups[gi];
-                const int s0 = std::max(c0, g.first), s1 = std::min(c1, g.first + g.count);
-                if (s0 >= s1) continue;
-                HIPCHK(launch_reproj<R>(P->stream, hb, db, bb, wtab, desc_dev, g.proto, s0, s1 - s0,
-                                        S + (int64_t)(s0 - c0) * run.s_stride, run.s_stride, P->p.beta, P->p.tau,
-                                        g.reproj_kc));
-            }
+            HIPCHK(launch_reproj_multi<R>(P->stream, hb, db, bb, wtab, desc_dev, protos.data(), np, c0, c1 - c0, S,
+                                          run.s_stride, P->p.beta, P->p.tau, rkc));
             STCHK(phase_end(P, 3, e0));
         }
     }
@@ -846,38 +919,22 @@ static shlr_status x_update_phase(shlr_plan* P, bool track_change) {
     size_t e0 = 0;
     STCHK(phase_begin(P, 0, &e0));
     if (p.model == SHLR_MODEL_PI) {
-        for (int si = 0; si < p.n_slices; ++si) {
-            const SliceLayout& L = P->sl[si];
-            const int M = L.M, N = L.N;
-            const int64_t MN = (int64_t)M * N;
-            // A = F_m(B_row): lines (j, n) along m
-            LineAddr col{0, MN, 1, N, N};
-            HIPCHK(launch_fft_lines<R>(P->stream, Q.c + L.br, Q.c + L.a, col, col, M, J * N, 0, 1.0 / sqrt((double)M)));
-            if (p.spirit_ksize > 0 && p.lambda1 > 0) {
-                STCHK(spirit_xupdate<R>(P, si, track_change));
-            } else {
-                XupdRows x;
-                x.n = N;
-                x.n1 = J;
-                x.n0 = M;
-                x.n_rows = J * M;
-                x.rc_digit = 0;
-                x.bo = RowAddr{0, MN, 1, M};
-                x.a = RowAddr{0, MN, N, 1};
-                x.y = x.a;
-                x.k = x.a;
-                x.out = RowAddr{0, MN, 1, M};
-                x.msk = RowAddr{0, 0, N, 1};
-                x.rr_off = L.rr;
-                x.rc_off = L.rc;
-                HIPCHK(launch_xupd_rows<R>(P->stream, Q.c + L.bct, Q.c + L.a, Q.c + L.yn, Q.c + L.k, Q.c + L.hct,
-                                           Q.m + L.mask_b, Q.r, x, p.lambda, p.beta, p.hard_dc,
-                                           track_change ? Q.change + 2 * si : nullptr,
-                                           track_change ? Q.active + si : nullptr));
-            }
-            // H_row = F_m^-1(K)
-            HIPCHK(launch_fft_lines<R>(P->stream, Q.c + L.k, Q.c + L.hr, col, col, M, J * N, 1, 1.0 / sqrt((double)M)));
+        // every slice in one launch per step: A = F_m(B_row), the X-update of Eq. 15 (or SPIRiT's
+        // PCG per slice), H_row = F_m^-1(K)
+        const FftSeg* sf = (const FftSeg*)(P->ws + P->off_seg);
+        const FftSeg* sv = (const FftSeg*)((const unsigned char*)sf + align256(P->seg_fwd.size() * sizeof(FftSeg)));
+        const XupdSeg* sx =
+            (const XupdSeg*)((const unsigned char*)sv + align256(P->seg_inv.size() * sizeof(FftSeg)));
+        const int ns = (int)P->seg_fwd.size();
+        HIPCHK(launch_fft_lines_seg<R>(P->stream, Q.c, Q.c, sf, ns, P->blk_fwd, P->lds_fwd));
+        if (p.spirit_ksize > 0 && p.lambda1 > 0) {
+            for (int si = 0; si < p.n_slices; ++si) STCHK(spirit_xupdate<R>(P, si, track_change));
+        } else {
+            HIPCHK(launch_xupd_rows_seg<R>(P->stream, Q.c, Q.m, Q.r, sx, ns, P->blk_x, P->lds_x, p.lambda, p.beta,
+                                           p.hard_dc, track_change ? Q.change : nullptr,
+                                           track_change ? Q.active : nullptr));
         }
+        HIPCHK(launch_fft_lines_seg<R>(P->stream, Q.c, Q.c, sv, ns, P->blk_inv, P->lds_inv));
     } else {
         const SliceLayout& L = P->sl[0];
         const int M = L.M, N = L.N, Lh = p.L;

@@ -42,6 +42,36 @@ struct XupdRows {
 
 FftPlan make_fft_plan(int n);
 
+// Segmented launches: the lines of several slices (each its own length and plan) in one launch.
+// Segments are sorted by their first block; a block finds its segment by binary search.
+struct FftSeg {
+    FftPlan pl;
+    LineAddr ia, oa;   // bases are offsets from the kernel's in / out pointers
+    int n_lines, NL, block0, inverse;
+    double scale;
+};
+struct XupdSeg {
+    FftPlan pl;
+    XupdRows x;
+    int NL, block0, unit;                 // unit: stop-test unit (slice) of the rows
+    int64_t bo, a, y, k, out, m;          // array offsets from the arena bases (m in bytes)
+};
+template <typename R>
+FftSeg make_fft_seg(int n, int n_lines, int inverse, double scale, const LineAddr& ia, const LineAddr& oa, int block0,
+                    size_t* lds);
+template <typename R>
+XupdSeg make_xupd_seg(const XupdRows& x, int block0, int unit, int64_t bo, int64_t a, int64_t y, int64_t k,
+                      int64_t out, int64_t m, size_t* lds);
+int fft_seg_blocks(const FftSeg& g);
+int xupd_seg_blocks(const XupdSeg& g);
+template <typename R>
+hipError_t launch_fft_lines_seg(hipStream_t st, const cplx_t<R>* in, cplx_t<R>* out, const FftSeg* segs_dev,
+                                int n_seg, int blocks, size_t lds);
+template <typename R>
+hipError_t launch_xupd_rows_seg(hipStream_t st, cplx_t<R>* cbase, const uint8_t* mbase, const R* rtab,
+                                const XupdSeg* segs_dev, int n_seg, int blocks, size_t lds, double lam, double beta,
+                                int hard_dc, double* change, const int32_t* active);
+
 template <typename R>
 hipError_t launch_fft_lines(hipStream_t st, const cplx_t<R>* in, cplx_t<R>* out, const LineAddr& ia,
                             const LineAddr& oa, int n, int n_lines, int inverse, double scale);
@@ -92,6 +122,16 @@ hipError_t launch_change_pair(hipStream_t st, const cplx_t<R>* a, const cplx_t<R
 hipError_t launch_stop_test(hipStream_t st, const double* change, int32_t* active, int32_t* iters, double* rel,
                             int n_units, double tol, int32_t* n_active);
 
+// one launch over matrices of several shapes (the prototypes): sized for the largest
+template <typename R>
+hipError_t launch_lift_gram_multi(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* wtab,
+                                  const LRDesc* descs_dev, const LRDesc* protos, int n_protos, int m0, int count,
+                                  double2* Gs, int64_t g_stride, double beta, int kc);
+template <typename R>
+hipError_t launch_reproj_multi(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cplx_t<R>* bb,
+                               const cplx_t<R>* wtab, const LRDesc* descs_dev, const LRDesc* protos, int n_protos,
+                               int m0, int count, const cplx_t<R>* Ss, int64_t s_stride, double beta, double tau,
+                               int kc);
 template <typename R>
 hipError_t launch_lift_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* wtab,
                             const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, double2* Gs,

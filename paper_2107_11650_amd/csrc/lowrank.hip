@@ -269,6 +269,9 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
 
     // unit of this wave
     const int n_units = (nt + 1) / 2;
+    // a launch over matrices of several orders sizes grid.y for the largest: blocks past this
+    // matrix's units have nothing to do (block-uniform, before any barrier)
+    if ((int)blockIdx.y * LR_WAVES >= n_units) return;
     const int unit = blockIdx.y * LR_WAVES + wave;
     const bool active = unit < n_units;
     int I1 = unit, I2 = nt - 1 - unit;
@@ -889,12 +892,24 @@ static hipError_t launch_gram_t(dim3 grid, size_t lds, hipStream_t st, const cpl
     return hipGetLastError();
 }
 
-// Launch the Gram kernel for matrices [m0, m0 + count) that share (V, J, n, k).
+// LDS of the Gram kernel over several shapes: the largest
 template <typename R>
-hipError_t launch_lift_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* wtab,
-                            const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, double2* Gs,
-                            int64_t g_stride, double beta, int kc) {
-    const int s = lr_s(proto);
+static size_t gram_lds_max(const LRDesc* protos, int n_protos, int KC) {
+    size_t b = 0;
+    for (int i = 0; i < n_protos; ++i)
+        b = std::max(b, gram_lds_bytes<R>(protos[i].V, protos[i].J, protos[i].n, lr_s(protos[i]), KC));
+    return b;
+}
+
+// Launch the Gram kernel for matrices [m0, m0 + count) whose shapes are among the prototypes
+// `protos`: one launch, sized for the largest (each block reads its own descriptor).
+template <typename R>
+hipError_t launch_lift_gram_multi(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* wtab,
+                                  const LRDesc* descs_dev, const LRDesc* protos, int n_protos, int m0, int count,
+                                  double2* Gs, int64_t g_stride, double beta, int kc) {
+    if (n_protos < 1) return hipErrorInvalidValue;
+    int s = 0;
+    for (int i = 0; i < n_protos; ++i) s = std::max(s, lr_s(protos[i]));
     const int nt = (s + 15) / 16;
     const int n_units = (nt + 1) / 2;
     const int groups = (n_units + LR_WAVES - 1) / LR_WAVES;
@@ -903,9 +918,9 @@ hipError_t launch_lift_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>
     int KC = 16;
     if (!gram_prefetches(sizeof(R), nt + 1, 16, s_pad) && gram_prefetches(sizeof(R), nt + 1, 8, s_pad)) KC = 8;
     if (kc == 4 || kc == 8 || kc == 16 || kc == 32) KC = kc;
-    while (KC > 4 && gram_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT) KC /= 2;
-    if (gram_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT) return hipErrorInvalidValue;
-    const size_t lds = gram_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC);
+    while (KC > 4 && gram_lds_max<R>(protos, n_protos, KC) > LDS_LIMIT) KC /= 2;
+    const size_t lds = gram_lds_max<R>(protos, n_protos, KC);
+    if (lds > LDS_LIMIT) return hipErrorInvalidValue;
     dim3 grid(count, groups);
     const R ib = (R)(1.0 / beta);
     const int need = nt + 1;
@@ -915,6 +930,14 @@ hipError_t launch_lift_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>
     if (need <= 16) return launch_gram_t<R, 16>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
     if (need <= 21) return launch_gram_t<R, 21>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
     return hipErrorInvalidValue;  // s > 320
+}
+
+// Launch the Gram kernel for matrices [m0, m0 + count) that share (V, J, n, k).
+template <typename R>
+hipError_t launch_lift_gram(hipStream_t st, const cplx_t<R>* hb, const cplx_t<R>* db, const cplx_t<R>* wtab,
+                            const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, double2* Gs,
+                            int64_t g_stride, double beta, int kc) {
+    return launch_lift_gram_multi<R>(st, hb, db, wtab, descs_dev, &proto, 1, m0, count, Gs, g_stride, beta, kc);
 }
 
 template <typename R, int MAXT>
@@ -929,20 +952,37 @@ static hipError_t launch_reproj_t(dim3 grid, size_t lds, hipStream_t st, const c
     return hipGetLastError();
 }
 
+// LDS of the reprojection kernel over several shapes: the largest
 template <typename R>
-hipError_t launch_reproj(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cplx_t<R>* bb, const cplx_t<R>* wtab,
-                         const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, const cplx_t<R>* Ss,
-                         int64_t s_stride, double beta, double tau, int kc) {
-    const int s = lr_s(proto), l = lr_l(proto);
+static size_t reproj_lds_max(const LRDesc* protos, int n_protos, int KC, bool stage) {
+    size_t b = 0;
+    for (int i = 0; i < n_protos; ++i)
+        b = std::max(b, reproj_lds_bytes<R>(protos[i].V, protos[i].J, protos[i].n, lr_s(protos[i]), KC, stage));
+    return b;
+}
+
+// Launch the reprojection kernel for matrices [m0, m0 + count) whose shapes are among the
+// prototypes `protos`: one launch with the chunk size every shape can take.
+template <typename R>
+hipError_t launch_reproj_multi(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cplx_t<R>* bb,
+                               const cplx_t<R>* wtab, const LRDesc* descs_dev, const LRDesc* protos, int n_protos,
+                               int m0, int count, const cplx_t<R>* Ss, int64_t s_stride, double beta, double tau,
+                               int kc) {
+    if (n_protos < 1) return hipErrorInvalidValue;
+    int s = 0, l_min = 1 << 30;
+    for (int i = 0; i < n_protos; ++i) {
+        s = std::max(s, lr_s(protos[i]));
+        l_min = std::min(l_min, lr_l(protos[i]));
+    }
     const int nt = (s + 15) / 16;
     int KC = (kc >= 16 && kc <= 64 && kc % 16 == 0) ? kc : 64;   // rows of A per chunk
-    while (KC > 16 && (reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC) > LDS_LIMIT || KC > ((l + 15) / 16) * 16))
+    while (KC > 16 && (reproj_lds_max<R>(protos, n_protos, KC, false) > LDS_LIMIT || KC > ((l_min + 15) / 16) * 16))
         KC -= 16;
-    size_t lds = reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC);
+    size_t lds = reproj_lds_max<R>(protos, n_protos, KC, false);
     if (lds > LDS_LIMIT) return hipErrorInvalidValue;
     // rows of S staged through LDS where the space allows
-    const int stage = reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC, true) <= LDS_LIMIT ? 1 : 0;
-    if (stage) lds = reproj_lds_bytes<R>(proto.V, proto.J, proto.n, s, KC, true);
+    const int stage = reproj_lds_max<R>(protos, n_protos, KC, true) <= LDS_LIMIT ? 1 : 0;
+    if (stage) lds = reproj_lds_max<R>(protos, n_protos, KC, true);
     // column tiles per wave: the fewest waves that share a row tile take ceil(nt / that) each
     const int need = (nt + LR_WAVES / (KC / 16) - 1) / (LR_WAVES / (KC / 16));
     dim3 grid(count);
@@ -958,6 +998,25 @@ hipError_t launch_reproj(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cpl
     return hipErrorInvalidValue;
 }
 
+template <typename R>
+hipError_t launch_reproj(hipStream_t st, const cplx_t<R>* hb, cplx_t<R>* db, cplx_t<R>* bb, const cplx_t<R>* wtab,
+                         const LRDesc* descs_dev, const LRDesc& proto, int m0, int count, const cplx_t<R>* Ss,
+                         int64_t s_stride, double beta, double tau, int kc) {
+    return launch_reproj_multi<R>(st, hb, db, bb, wtab, descs_dev, &proto, 1, m0, count, Ss, s_stride, beta, tau, kc);
+}
+
+template hipError_t launch_lift_gram_multi<float>(hipStream_t, const float2*, const float2*, const float2*,
+                                                  const LRDesc*, const LRDesc*, int, int, int, double2*, int64_t,
+                                                  double, int);
+template hipError_t launch_lift_gram_multi<double>(hipStream_t, const double2*, const double2*, const double2*,
+                                                   const LRDesc*, const LRDesc*, int, int, int, double2*, int64_t,
+                                                   double, int);
+template hipError_t launch_reproj_multi<float>(hipStream_t, const float2*, float2*, float2*, const float2*,
+                                               const LRDesc*, const LRDesc*, int, int, int, const float2*, int64_t,
+                                               double, double, int);
+template hipError_t launch_reproj_multi<double>(hipStream_t, const double2*, double2*, double2*, const double2*,
+                                                const LRDesc*, const LRDesc*, int, int, int, const double2*, int64_t,
+                                                double, double, int);
 template hipError_t launch_lift_gram<float>(hipStream_t, const float2*, const float2*, const float2*, const LRDesc*,
                                             const LRDesc&, int, int, double2*, int64_t, double, int);
 template hipError_t launch_lift_gram<double>(hipStream_t, const double2*, const double2*, const double2*,
