@@ -476,22 +476,52 @@ __device__ inline double2 rank2_sub(double2 a, double2 ur, double2 qr, double2 u
 }
 
 
+// sum of the NW per-wave partials v[0 .. NW-1] as a fixed pairwise tree (the same value in every thread)
+template <int NW>
+__device__ inline double tree_sum(const double* v) {
+    double a[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) a[i] = v[i];
+#pragma unroll
+    for (int w = 1; w < NW; w *= 2)
+#pragma unroll
+        for (int i = 0; i + w < NW; i += 2 * w) a[i] += a[i + w];
+    return a[0];
+}
+// the same total in groups of four (fewer registers at once): ((v0 + v1) + (v2 + v3)) + ...
+template <int NW>
+__device__ inline double group_sum(const double* v) {
+    double t = 0.0;
+#pragma unroll
+    for (int g = 0; g < NW; g += 4) {
+        double a = v[g];
+        if (g + 1 < NW) a += v[g + 1];
+        double b = g + 2 < NW ? v[g + 2] : 0.0;
+        if (g + 3 < NW) b += v[g + 3];
+        t = g == 0 ? a + b : t + (a + b);
+    }
+    return t;
+}
+
 template <int MAXB>
 __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restrict__ descs, int m0,
                                                               double2* __restrict__ Gs, int64_t g_stride,
                                                               double* __restrict__ scr, int64_t scr_stride) {
     // separate LDS objects, so that the stores of partial sums do not order the vector loads
     constexpr int RR_SP = ((RR_MAXS + 15) / 16) * 16;
-    constexpr int RR_NB = RR_SP / 16, RR_NBLK = RR_NB * (RR_NB + 1) / 2;
+    constexpr int RR_NB = RR_SP / 16;
     // operands of the pending update in the lane order of the matrix cores (negated):
     // opA[I][lane] = (a, a') of row I*16 + lane%16, opB[J][lane] = b of column J*16 + lane%16
     __shared__ double2 opA[RR_NB * 64];
     __shared__ double opB[RR_NB * 64];
-    __shared__ double2 qp[RR_SP];                 // pending q_{i-1}
     __shared__ double2 uc[RR_SP];                 // current reflector u_i
     __shared__ double2 xraw[RR_SP];               // captured column i+1
-    __shared__ double2 yrow[RR_NBLK * 16];        // [block][16] row partials
-    __shared__ double2 ycol[RR_NBLK * 16];        // [block][16] column partials
+    // partial products with u of the rows of block-row I: ypart[I][t][16] holds the row partials of
+    // block (I, t) for t <= I and the column partials of block (t, I) for t > I, so that row
+    // 16 I + rr sums ypart[I][jlo .. nb-1][rr] with fixed strides.  Rows of RR_PS >= nb + 3
+    // entries, zero past nb: the sum reads whole batches of four
+    constexpr int RR_PS = ((RR_NB + 3 + 3) / 4) * 4;
+    __shared__ double2 ypart[RR_NB * RR_PS * 16];
     __shared__ double2 rtile[RR_WAVES * RR_TILE];  // per wave: products of a block, 16 rows of 17
     __shared__ double2 salpha[2];                 // [0] alpha of the reflector, [1] p_j
     __shared__ double red[2 * (RR_THREADS / 64)];  // per-wave partial sums: u^H p, then tails
@@ -546,10 +576,8 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
                 ai_[t][q] = v.y;
             }
         }
-        for (int e = tid; e < sp; e += RR_THREADS) {
-            qp[e] = make_double2(0.0, 0.0);
-            uc[e] = make_double2(0.0, 0.0);
-        }
+        for (int e = tid; e < sp; e += RR_THREADS) uc[e] = make_double2(0.0, 0.0);
+        for (int e = tid; e < RR_NB * RR_PS * 16; e += RR_THREADS) ypart[e] = make_double2(0.0, 0.0);
         for (int e = tid; e < nb * 64; e += RR_THREADS) {
             opA[e] = make_double2(0.0, 0.0);
             opB[e] = 0.0;
@@ -569,8 +597,6 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
     __syncthreads();
 
     // Thread t works on row j + t of the current column j (every row count here is below 512).
-    // finish_and_reflect: column j (rows >= j, raw in xraw) minus the update (u, q) of step j-1
-    // (in uc / qp, none for j = 0), its diagonal entry, and the reflector of column j into uc.
     // the thread index, recomputed where it is used (the wave index is a scalar), so that no
     // vector register keeps it across the step loop
     auto tid_now = [&]() {
@@ -578,67 +604,63 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
         asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
         return wave * 64 + ln;
     };
-    auto finish_and_reflect = [&](int j, bool pending, double2 q_j) {
-        const int tl = tid_now();
-        const int r = j + tl;
+    // reflect_column: v is this thread's entry (row r = j + t) of column j, finished with every
+    // update before step j.  Writes the diagonal entry, forms the norm of the entries below the
+    // subdiagonal over all threads, and the reflector of column j into uc (and the packed matrix).
+    auto reflect_column = [&](int j, int r, double2 v) {
         double tail = 0;
         if (r < s) {
-            double2 v = xraw[r];
-            if (pending) {
-                const double2 u0 = uc[j];
-                const double2 ur = uc[r], qr = qp[r];
-                v.x -= qr.x * u0.x + qr.y * u0.y + ur.x * q_j.x + ur.y * q_j.y;
-                v.y -= qr.y * u0.x - qr.x * u0.y + ur.y * q_j.x - ur.x * q_j.y;
-            }
-            xraw[r] = v;   // kept in LDS across the barrier below (this thread's own entry)
             if (r == j) tdd[j] = v.x;
             if (r == j + 1) salpha[0] = v;
             if (r > j + 1) tail = cabs2(v);
         }
         tail = wave_sum_to63(tail);
-        if ((tl & 63) == 63) red[RR_THREADS / 64 + wave] = tail;
+        if (((r - j) & 63) == 63) red[RR_THREADS / 64 + wave] = tail;
         __syncthreads();
         if (j + 1 >= s) return;
-        tail = 0;
-        for (int w = 0; w < RR_THREADS / 64; ++w) tail += red[RR_THREADS / 64 + w];
+        tail = tree_sum<RR_THREADS / 64>(red + RR_THREADS / 64);
         const double2 al = salpha[0];
         const bool refl = tail > 0.0;
         double hh = 1.0, xn = 0.0;
         double2 ph = make_double2(1.0, 0.0);
         if (refl) {
-            const double aabs = sqrt(al.x * al.x + al.y * al.y);
-            xn = sqrt(aabs * aabs + tail);
-            if (aabs > 0) ph = make_double2(al.x / aabs, al.y / aabs);
-            hh = xn * xn + aabs * xn;
+            // |alpha| and its phase from one reciprocal square root, beside the norm of the column
+            const double a2 = al.x * al.x + al.y * al.y;
+            xn = sqrt(a2 + tail);
+            double aabs = 0.0;
+            if (a2 > 0) {
+                const double ia = rsqrt(a2);
+                ph = make_double2(al.x * ia, al.y * ia);
+                aabs = a2 * ia;
+            }
+            hh = xn * (xn + aabs);
         }
-        if (tl == 0) {
+        if (r == j) {
             ter[j] = refl ? -ph.x * xn : al.x;
             tei[j] = refl ? -ph.y * xn : al.y;
             thv[j] = refl ? hh : 0.0;
-        }
-        if (r == j) {
             // entries at and above the column stay zero (the zero is made here rather than kept
             // in registers across the loop)
             double zx, zy;
             asm volatile("v_mov_b64 %0, 0\n\tv_mov_b64 %1, 0" : "=v"(zx), "=v"(zy));
             uc[j] = make_double2(zx, zy);
+            rh[0] = hh;   // 1 / h is formed at the start of the next step, off this chain
+            rrefl = refl;
         }
         if (r > j && r < s) {
             double2 u = make_double2(0.0, 0.0);
             if (refl) {
-                u = (r == j + 1) ? make_double2(al.x + ph.x * xn, al.y + ph.y * xn) : xraw[r];
+                u = (r == j + 1) ? make_double2(al.x + ph.x * xn, al.y + ph.y * xn) : v;
                 A[pk(r, j, s)] = u;
             }
             uc[r] = u;
         }
-        if (tl == 0) {
-            rh[0] = hh;
-            rh[1] = 1.0 / hh;
-            rrefl = refl;
-        }
     };
 
-    finish_and_reflect(0, false, make_double2(0.0, 0.0));
+    {
+        const int r = tid_now();
+        reflect_column(0, r, r < s ? xraw[r] : make_double2(0.0, 0.0));
+    }
     __syncthreads();
 
     for (int i = 0; i + 1 < s; ++i) {
@@ -685,8 +707,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
             }
             const double ycs = colsum4_pair(ycx, ycy);
             // a diagonal block is held in full and Hermitian: its column sums are its row sums
-            double2* ydst = I == J ? yrow : ycol;
-            if (lk < 2) reinterpret_cast<double*>(ydst + b * 16 + lr)[lk] = ycs;
+            if (lk < 2) reinterpret_cast<double*>(ypart + (J * RR_PS + I) * 16 + lr)[lk] = ycs;
             if (I != J) {
                 // row partials A u_C: the lane's products go through a per-wave LDS tile (rows of
                 // 17 entries, so that neither pass conflicts on banks); a quad of lanes then sums
@@ -708,58 +729,81 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
                 }
                 __builtin_amdgcn_wave_barrier();
                 rs = quad_sum_z(rs);
-                if ((ln & 3) == 0) yrow[b * 16 + rho] = rs;
+                if ((ln & 3) == 0) ypart[(I * RR_PS + J) * 16 + rho] = rs;
             }
         }
+        // 1 / h of the reflector of step i, for (b); formed here by the first wave (the least loaded)
+        if (wave == 0) {
+            const double ih = 1.0 / rh[0];
+            if ((threadIdx.x & 63) == 0) rh[1] = ih;
+        }
         __syncthreads();
-        // (b) p = A u_i / h and u^H p over all threads, then q_i, column i+1 and the next reflector
+        // (b) p = A u_i / h and u^H p over all threads, then q_i, column i+1 finished with the
+        // update of step i, and the next reflector.
         {
             const int j = i + 1;
-            const int tl = tid_now();
-            const int r = j + tl;
+            const int r = j + tid_now();
             const bool refl = rrefl != 0;
-            const double hh = rh[0], ihh = rh[1];
-            double2 pv = make_double2(0.0, 0.0);
+            const double ihh = rh[1];
+            const bool live = r < s;
+            const double2 zero = make_double2(0.0, 0.0);
+            const double2 ur = (live && refl) ? uc[r] : zero;
+            double2 pv = zero;
             double uhp = 0;
-            if (r < s && refl) {
+            if (live && refl) {
                 // row partials of blocks (I, jlo .. I), then column partials of blocks (I + 1 .. nb-1, I)
-                const int I = r >> 4, rr = r & 15;
-                gather_partials<RR_NB, 4>(yrow, ycol, I, rr, jlo, nb, pv.x, pv.y);
+                // (in batches of four loads; entries past nb are zero)
+                const double2* yp = ypart + ((r >> 4) * RR_PS + jlo) * 16 + (r & 15);
+                const int nt = nb - jlo;   // uniform over the block
+#pragma unroll
+                for (int t0 = 0; t0 < RR_PS; t0 += 4) {
+                    if (t0 >= nt) break;
+                    double2 y[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) y[u] = yp[(t0 + u) * 16];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        pv.x += y[u].x;
+                        pv.y += y[u].y;
+                    }
+                }
                 pv.x *= ihh;
                 pv.y *= ihh;
-                const double2 u = uc[r];
-                uhp = u.x * pv.x + u.y * pv.y;   // Re(conj(u) p)
+                uhp = ur.x * pv.x + ur.y * pv.y;   // Re(conj(u) p)
                 if (r == j) salpha[1] = pv;
             }
             uhp = wave_sum_to63(uhp);
-            if ((tl & 63) == 63) red[wave] = uhp;
+            if (((r - j) & 63) == 63) red[wave] = uhp;
             __syncthreads();
-            uhp = 0;
-            for (int w = 0; w < RR_THREADS / 64; ++w) uhp += red[w];
-            const double Kc = uhp / (2.0 * hh);
-            double2 qj = make_double2(0.0, 0.0);
-            if (refl) {
-                const double2 pj = salpha[1], uj = uc[j];
-                qj = make_double2(pj.x - Kc * uj.x, pj.y - Kc * uj.y);
-            }
-            if (r < s) {
-                const double2 u = refl ? uc[r] : make_double2(0.0, 0.0);
-                const double2 q = make_double2(pv.x - Kc * u.x, pv.y - Kc * u.y);
-                qp[r] = q;   // read back by this thread only
+            const double2 xr = live ? xraw[r] : zero;
+            const double2 u0 = uc[j];
+            const double2 pj = salpha[1];
+            uhp = group_sum<RR_THREADS / 64>(red);
+            const double Kc = 0.5 * uhp * ihh;   // u^H p / 2h
+            double2 qj = zero;
+            if (refl) qj = make_double2(pj.x - Kc * u0.x, pj.y - Kc * u0.y);
+            double2 v = xr;
+            if (live) {
+                const double2 q = make_double2(pv.x - Kc * ur.x, pv.y - Kc * ur.y);
                 // the update D -= [u_r q_r] [q_c u_c]^H as 16x16x4 products: lane (k, c) supplies
                 // A[c][k] = (u.x, u.y, q.x, q.y)[k] of row c (and A'[c][k] = (u.y, -u.x, q.y, -q.x)[k]
                 // for the imaginary part) and B[k][c] = (q.x, q.y, u.x, u.y)[k] of column c
                 const int o = (r >> 4) * 64 + (r & 15);
-                opA[o] = make_double2(-u.x, -u.y);
-                opA[o + 16] = make_double2(-u.y, u.x);
+                opA[o] = make_double2(-ur.x, -ur.y);
+                opA[o + 16] = make_double2(-ur.y, ur.x);
                 opA[o + 32] = make_double2(-q.x, -q.y);
                 opA[o + 48] = make_double2(-q.y, q.x);
                 opB[o] = q.x;
                 opB[o + 16] = q.y;
-                opB[o + 32] = u.x;
-                opB[o + 48] = u.y;
+                opB[o + 32] = ur.x;
+                opB[o + 48] = ur.y;
+                // column i+1 minus the update of step i: v -= q conj(u_j) + u conj(q_j)
+                if (refl) {
+                    v.x -= q.x * u0.x + q.y * u0.y + ur.x * qj.x + ur.y * qj.y;
+                    v.y -= q.y * u0.x - q.x * u0.y + ur.y * qj.x - ur.x * qj.y;
+                }
             }
-            finish_and_reflect(j, refl, qj);
+            reflect_column(j, r, v);
         }
         __syncthreads();
     }
