@@ -604,10 +604,11 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
         asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
         return wave * 64 + ln;
     };
-    // reflect_column: v is this thread's entry (row r = j + t) of column j, finished with every
-    // update before step j.  Writes the diagonal entry, forms the norm of the entries below the
-    // subdiagonal over all threads, and the reflector of column j into uc (and the packed matrix).
-    auto reflect_column = [&](int j, int r, double2 v) {
+    // Reflection of column j, v being this thread's entry (row r = j + t) finished with every update
+    // before step j.  norm_part: the diagonal entry, alpha, and the per-wave sums of the squared
+    // entries below the subdiagonal.  After a barrier, reflect: the reflector of column j into uc
+    // (and the packed matrix), h and whether the column is reflected.
+    auto norm_part = [&](int j, int r, double2 v) {
         double tail = 0;
         if (r < s) {
             if (r == j) tdd[j] = v.x;
@@ -616,9 +617,10 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
         }
         tail = wave_sum_to63(tail);
         if (((r - j) & 63) == 63) red[RR_THREADS / 64 + wave] = tail;
-        __syncthreads();
+    };
+    auto reflect = [&](int j, int r, double2 v) {
         if (j + 1 >= s) return;
-        tail = tree_sum<RR_THREADS / 64>(red + RR_THREADS / 64);
+        const double tail = tree_sum<RR_THREADS / 64>(red + RR_THREADS / 64);
         const double2 al = salpha[0];
         const bool refl = tail > 0.0;
         double hh = 1.0, xn = 0.0;
@@ -656,19 +658,39 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
             uc[r] = u;
         }
     };
+    // column c of the blocks as they stand (rows c .. s-1) into xraw
+    auto capture = [&](int c) {
+#pragma unroll
+        for (int t = 0; t < MAXB; ++t) {
+            const int b = wave + RR_WAVES * t;
+            if (b >= nblk || bJ[t] != (c >> 4)) continue;   // uniform over the wave
+            int ln;
+            asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+            if ((ln & 15) == (c & 15)) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = bI[t] * 16 + (ln >> 4) + 4 * q;
+                    if (r >= c && r < s) xraw[r] = make_double2(ar_[t][q], ai_[t][q]);
+                }
+            }
+        }
+    };
 
     {
         const int r = tid_now();
-        reflect_column(0, r, r < s ? xraw[r] : make_double2(0.0, 0.0));
+        const double2 v = r < s ? xraw[r] : make_double2(0.0, 0.0);
+        norm_part(0, r, v);
+        __syncthreads();
+        reflect(0, r, v);
+        capture(1);   // xraw is no longer read for column 0
     }
     __syncthreads();
 
+    // Step i: the blocks hold the matrix with the updates of steps < i applied, xraw column i+1
+    // of it (rows > i), uc the reflector u_i.
     for (int i = 0; i + 1 < s; ++i) {
         const int jlo = (i + 1) >> 4;
-        const bool pend = i > 0;
-        // (a) pending update on the matrix cores, capture of column i+1, products with u_i.  The
-        // whole block is updated: entries of u, q at and above the reduced columns are zero in uc,
-        // so the stale values there never reach a live product.
+        // (a) products of the live blocks with u_i
 #pragma unroll
         for (int t = 0; t < MAXB; ++t) {
             int b = wave + RR_WAVES * t;
@@ -680,21 +702,6 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
             int ln;
             asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
             const int lr = ln & 15, lk = ln >> 4;
-            if (pend) {
-                // D -= [u_r q_r] [q_c u_c]^H on the matrix cores, operands as stored in (b)
-                const double2 a = opA[I * 64 + ln];
-                const double bq = opB[J * 64 + ln];
-                ar_[t] = mfma16(a.x, bq, ar_[t]);
-                ai_[t] = mfma16(a.y, bq, ai_[t]);
-            }
-            const int cc = i + 1 - J * 16;
-            if (cc >= 0 && cc < 16 && lr == cc) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = I * 16 + lk + 4 * q;
-                    if (r > i && r < s) xraw[r] = make_double2(ar_[t][q], ai_[t][q]);
-                }
-            }
             // column partials conj(A)^T u over the block's rows: in-lane, then across the four rows
             // of lanes; lanes of row 0 end with the real part, lanes of row 1 the imaginary part
             const double2 uC = uc[J * 16 + lr];
@@ -803,7 +810,30 @@ __global__ __launch_bounds__(RR_THREADS) void k_tridiag_rr(const LRDesc* __restr
                     v.y -= q.y * u0.x - q.x * u0.y + ur.y * qj.x - ur.x * qj.y;
                 }
             }
-            reflect_column(j, r, v);
+            norm_part(j, r, v);
+            __syncthreads();
+            // the reflector of column i+1 (waves that hold rows of it), then the update of step i,
+            // D -= [u_i q_i] [q_i u_i]^H, on the matrix cores by every wave for the blocks live in
+            // step i+1 (the entries of u, q at and above the reduced columns are zero, so the stale
+            // values there never reach a live product), and the capture of column i+2
+            if (j + wave * 64 < s) reflect(j, r, v);
+            if (i + 2 < s) {
+                const int jlo2 = (i + 2) >> 4;
+#pragma unroll
+                for (int t = 0; t < MAXB; ++t) {
+                    int b = wave + RR_WAVES * t;
+                    if (b >= nblk || bJ[t] < jlo2) continue;   // uniform over the wave
+                    int I = bI[t], J = bJ[t];
+                    asm volatile("" : "+s"(I), "+s"(J), "+s"(b));
+                    int ln;
+                    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+                    const double2 a = opA[I * 64 + ln];
+                    const double bq = opB[J * 64 + ln];
+                    ar_[t] = mfma16(a.x, bq, ar_[t]);
+                    ai_[t] = mfma16(a.y, bq, ai_[t]);
+                }
+                capture(i + 2);
+            }
         }
         __syncthreads();
     }
