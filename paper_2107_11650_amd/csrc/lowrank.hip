@@ -53,10 +53,18 @@ __device__ inline void load_line_table(cplx_t<R>* U, const cplx_t<R>* hb, const 
     load_line_table_at<R>(U, hb, d.h_off, d.h_cs, d.h_es, wtab, d, tid, nth);
 }
 
+// e / d without an integer division, for 0 <= e < 2^21 and 1 <= d < 2^24, from a reciprocal of d
+// good to an ulp (v_rcp_f32): (e + 1/2) / d lies at least 1/(2d) from an integer, while the
+// product's relative error (under 2^-22) moves it by less than (e + 1/2) 2^-22 / d < 1/(2d), so
+// truncation gives the exact quotient.
+__device__ inline int div_small(int e, int d) {
+    return (int)(((float)e + 0.5f) * __builtin_amdgcn_rcpf((float)d));
+}
+
 // Value of T (without the D term) at (a, col).
 template <typename C>
 __device__ inline C lift_val(const C* U, int n, int k, int a, int col) {
-    int blk = col / k;
+    int blk = div_small(col, k);
     int b = col - blk * k;
     return U[blk * n + a + b];
 }
@@ -77,7 +85,7 @@ __device__ inline void stage_chunk(R* Ar, R* Ai, int ldA, const cplx_t<R>* U, R 
     const int total = KC * s_pad;
     if (side == 0) {
         for (int e = tid; e < total; e += nth) {
-            int r = e / s_pad, cidx = e - r * s_pad;
+            int r = div_small(e, s_pad), cidx = e - r * s_pad;
             int a = r0 + r;
             R re = 0, im = 0;
             if (a < l && cidx < s) {
@@ -91,7 +99,7 @@ __device__ inline void stage_chunk(R* Ar, R* Ai, int ldA, const cplx_t<R>* U, R 
         }
     } else {
         for (int e = tid; e < total; e += nth) {
-            int cidx = e / KC, r = e - cidx * KC;
+            int cidx = div_small(e, KC), r = e - cidx * KC;
             int col = r0 + r;
             R re = 0, im = 0;
             if (col < l && cidx < s) {
@@ -125,11 +133,11 @@ __device__ inline void stage_A_chunk(R* Ar, R* Ai, int ldA, const cplx_t<R>* U, 
             dv[j] = C{0, 0};
             if (e < total) {
                 if (side == 0) {
-                    const int r = e / s_pad, cidx = e - r * s_pad, a = r0 + r;
+                    const int r = div_small(e, s_pad), cidx = e - r * s_pad, a = r0 + r;
                     if (a < l && cidx < s) dv[j] = Dm[(int64_t)a * q + cidx];
                 } else {
                     // A[r][c] = conj(T[c][r]): rows of A are columns of T; read D with r fastest
-                    const int cidx = e / KC, r = e - cidx * KC, col = r0 + r;
+                    const int cidx = div_small(e, KC), r = e - cidx * KC, col = r0 + r;
                     if (col < l && cidx < s) dv[j] = Dm[(int64_t)cidx * q + col];
                 }
             }
@@ -141,7 +149,7 @@ __device__ inline void stage_A_chunk(R* Ar, R* Ai, int ldA, const cplx_t<R>* U, 
                 R re = 0, im = 0;
                 int r, cidx;
                 if (side == 0) {
-                    r = e / s_pad;
+                    r = div_small(e, s_pad);
                     cidx = e - r * s_pad;
                     if (r0 + r < l && cidx < s) {
                         const C lv = lift_val(U, d.n, d.k, r0 + r, cidx);
@@ -149,7 +157,7 @@ __device__ inline void stage_A_chunk(R* Ar, R* Ai, int ldA, const cplx_t<R>* U, 
                         im = lv.y + dv[j].y * inv_beta;
                     }
                 } else {
-                    cidx = e / KC;
+                    cidx = div_small(e, KC);
                     r = e - cidx * KC;
                     if (r0 + r < l && cidx < s) {
                         const C lv = lift_val(U, d.n, d.k, cidx, r0 + r);
@@ -188,10 +196,10 @@ __device__ inline void prefetch_D_chunk(cplx_t<R> (&dv)[NPF], const cplx_t<R>* D
         dv[j] = cplx_t<R>{0, 0};
         if (e < total) {
             if (side == 0) {
-                const int r = e / s_pad, cidx = e - r * s_pad, a = r0 + r;
+                const int r = div_small(e, s_pad), cidx = e - r * s_pad, a = r0 + r;
                 if (a < l && cidx < s) dv[j] = Dm[(int64_t)a * q + cidx];
             } else {
-                const int cidx = e / KC, r = e - cidx * KC, col = r0 + r;
+                const int cidx = div_small(e, KC), r = e - cidx * KC, col = r0 + r;
                 if (col < l && cidx < s) dv[j] = Dm[(int64_t)cidx * q + col];
             }
         }
@@ -217,7 +225,7 @@ __device__ inline void stage_A_prefetched(R* Ar, R* Ai, int ldA, const cplx_t<R>
             R re = 0, im = 0;
             int r, cidx;
             if (side == 0) {
-                r = e / s_pad;
+                r = div_small(e, s_pad);
                 cidx = e - r * s_pad;
                 if (r0 + r < l && cidx < s) {
                     const C lv = lift_val(U, d.n, d.k, r0 + r, cidx);
@@ -225,7 +233,7 @@ __device__ inline void stage_A_prefetched(R* Ar, R* Ai, int ldA, const cplx_t<R>
                     im = lv.y + dv[j].y * inv_beta;
                 }
             } else {
-                cidx = e / KC;
+                cidx = div_small(e, KC);
                 r = e - cidx * KC;
                 if (r0 + r < l && cidx < s) {
                     const C lv = lift_val(U, d.n, d.k, cidx, r0 + r);
@@ -237,6 +245,16 @@ __device__ inline void stage_A_prefetched(R* Ar, R* Ai, int ldA, const cplx_t<R>
             Ai[r * ldA + cidx] = im;
         }
     }
+}
+
+// Tile g of the upper-triangular tiles of an nt x nt tile grid listed row by row in the order
+// 0, nt-1, 1, nt-2, ...: pair m = g / (nt + 1) holds row m (nt - m tiles) then row nt - 1 - m.
+// Returns (block row, block column).
+__device__ inline int2 gram_tile_at(int nt, int g) {
+    const int m = g / (nt + 1), rem = g - m * (nt + 1);
+    const bool lo = rem < nt - m;
+    const int I = lo ? m : nt - 1 - m;
+    return int2{I, lo ? m + rem : I + (rem - (nt - m))};
 }
 
 // ---------------------------------------------------------------------------
@@ -257,7 +275,8 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
     using A4 = acc4_t<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const LRDesc d = descs[m0 + blockIdx.x];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int s = lr_s(d), l = lr_l(d);
     const int nt = (s + 15) / 16;
     const int s_pad = nt * 16;
@@ -267,18 +286,32 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
     R* Ar = reinterpret_cast<R*>(U + utab);
     R* Ai = Ar + KC * ldA;
 
-    // unit of this wave
-    const int n_units = (nt + 1) / 2;
-    // a launch over matrices of several orders sizes grid.y for the largest: blocks past this
-    // matrix's units have nothing to do (block-uniform, before any barrier)
-    if ((int)blockIdx.y * LR_WAVES >= n_units) return;
-    const int unit = blockIdx.y * LR_WAVES + wave;
-    const bool active = unit < n_units;
-    int I1 = unit, I2 = nt - 1 - unit;
-    if (I2 == I1) I2 = -1;  // middle row alone
-    const int cnt1 = active ? nt - I1 : 0;
-    const int cnt2 = (active && I2 >= 0) ? nt - I2 : 0;
-    const int count = cnt1 + cnt2;
+    // Tiles of this wave: the nt (nt + 1) / 2 upper-triangular tiles listed row by row in the
+    // order 0, nt-1, 1, nt-2, ... and cut into LR_WAVES * gridDim.y contiguous segments of equal
+    // size (every SIMD gets the same share).  A launch over matrices of several orders sizes
+    // grid.y for the largest: blocks past this matrix's tiles return at once (block-uniform,
+    // before any barrier).
+    const int n_tiles = nt * (nt + 1) / 2;
+    const int nseg = LR_WAVES * (int)gridDim.y;
+    const int per = (n_tiles + nseg - 1) / nseg;
+    if ((int)blockIdx.y * LR_WAVES * per >= n_tiles) return;
+    const int t_begin = min(((int)blockIdx.y * LR_WAVES + wave) * per, n_tiles);
+    const int count = min(per, n_tiles - t_begin);
+    const bool active = count > 0;
+    // The segment covers at most three pieces of tile rows: piece p is row Ip, tiles Jp, Jp + 1,
+    // ... for the wave's tiles E(p-1) .. Ep - 1 (E(-1) = 0; unused pieces repeat the last row).
+    // Tile g of the list: pair m = g / (nt + 1) holds row m (nt - m tiles) then row nt - 1 - m.
+    const int2 p0 = gram_tile_at(nt, min(t_begin, n_tiles - 1));
+    const int I0 = p0.x, J0 = p0.y;
+    const int E0 = min(count, nt - J0);                 // rest of row I0
+    const int2 p1 = gram_tile_at(nt, min(t_begin + E0, n_tiles - 1));
+    const int I1 = p1.x, J1 = p1.y;
+    const int E1 = E0 + min(count - E0, nt - J1);
+    const int2 p2 = gram_tile_at(nt, min(t_begin + E1, n_tiles - 1));
+    const int I2 = p2.x, J2 = p2.y;
+    // block row and column of tile t of the wave (wave-uniform)
+#define tile_I(t) ((t) < E0 ? I0 : ((t) < E1 ? I1 : I2))
+#define tile_J(t) ((t) < E0 ? J0 + (t) : ((t) < E1 ? J1 + ((t) - E0) : J2 + ((t) - E1)))
 
     A4 accR[MAXT], accI[MAXT];
 #pragma unroll
@@ -306,49 +339,46 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
             stage_A_chunk<R>(Ar, Ai, ldA, U, Dm, d, inv_beta, r0, KC, s_pad, tid, LR_THREADS);
             __syncthreads();
         }
-        if (!active) continue;
-        for (int kk = 0; kk < KC; kk += 4) {
-            const int row = (kk + lk) * ldA + li;
-            const R a1r = Ar[row + I1 * 16], a1i = Ai[row + I1 * 16];
-            R a2r = 0, a2i = 0;
-            if (I2 >= 0) { a2r = Ar[row + I2 * 16]; a2i = Ai[row + I2 * 16]; }
-            if constexpr (sizeof(R) == 4 && MAXT <= 16) {
-                // every B operand of the step is read before the products (one wait per
-                // step); wider tiles or FP64 operands would not fit in registers beside them
-                R br[MAXT], bi[MAXT];
+        if (active) {
+            for (int kk = 0; kk < KC; kk += 4) {
+                const int row = (kk + lk) * ldA + li;
+                if constexpr (sizeof(R) == 4 && MAXT <= 16) {
+                    // every operand of the step is read before the products (one wait per step);
+                    // wider tiles or FP64 operands would not fit in registers beside them
+                    const R pr0 = Ar[row + I0 * 16], pm0 = Ai[row + I0 * 16];
+                    const R pr1 = Ar[row + I1 * 16], pm1 = Ai[row + I1 * 16];
+                    const R pr2 = Ar[row + I2 * 16], pm2 = Ai[row + I2 * 16];
+                    R br[MAXT], bi[MAXT];
 #pragma unroll
-                for (int t = 0; t < MAXT; ++t) {
-                    if (t < count) {
-                        const int Jb = t < cnt1 ? I1 + t : I2 + (t - cnt1);
-                        br[t] = Ar[row + Jb * 16];
-                        bi[t] = Ai[row + Jb * 16];
+                    for (int t = 0; t < MAXT; ++t) {
+                        if (t < count) {
+                            br[t] = Ar[row + tile_J(t) * 16];
+                            bi[t] = Ai[row + tile_J(t) * 16];
+                        }
                     }
-                }
 #pragma unroll
-                for (int t = 0; t < MAXT; ++t) {
-                    if (t < count) {
-                        const bool first = t < cnt1;
-                        const R ar = first ? a1r : a2r;
-                        const R ai = first ? a1i : a2i;
-                        accR[t] = mfma16(ar, br[t], accR[t]);
-                        accR[t] = mfma16(ai, bi[t], accR[t]);
-                        accI[t] = mfma16(ar, bi[t], accI[t]);
-                        accI[t] = mfma16(-ai, br[t], accI[t]);
+                    for (int t = 0; t < MAXT; ++t) {
+                        if (t < count) {
+                            const R ar = t < E0 ? pr0 : (t < E1 ? pr1 : pr2);
+                            const R ai = t < E0 ? pm0 : (t < E1 ? pm1 : pm2);
+                            accR[t] = mfma16(ar, br[t], accR[t]);
+                            accR[t] = mfma16(ai, bi[t], accR[t]);
+                            accI[t] = mfma16(ar, bi[t], accI[t]);
+                            accI[t] = mfma16(-ai, br[t], accI[t]);
+                        }
                     }
-                }
-            } else {
+                } else {
 #pragma unroll
-                for (int t = 0; t < MAXT; ++t) {
-                    if (t < count) {
-                        const bool first = t < cnt1;
-                        const int Jb = first ? I1 + t : I2 + (t - cnt1);
-                        const R ar = first ? a1r : a2r;
-                        const R ai = first ? a1i : a2i;
-                        const R br = Ar[row + Jb * 16], bi = Ai[row + Jb * 16];
-                        accR[t] = mfma16(ar, br, accR[t]);
-                        accR[t] = mfma16(ai, bi, accR[t]);
-                        accI[t] = mfma16(ar, bi, accI[t]);
-                        accI[t] = mfma16(-ai, br, accI[t]);
+                    for (int t = 0; t < MAXT; ++t) {
+                        if (t < count) {
+                            const int Ib = tile_I(t), Jb = tile_J(t);
+                            const R ar = Ar[row + Ib * 16], ai = Ai[row + Ib * 16];
+                            const R br = Ar[row + Jb * 16], bi = Ai[row + Jb * 16];
+                            accR[t] = mfma16(ar, br, accR[t]);
+                            accR[t] = mfma16(ai, bi, accR[t]);
+                            accI[t] = mfma16(ar, bi, accI[t]);
+                            accI[t] = mfma16(-ai, br, accI[t]);
+                        }
                     }
                 }
             }
@@ -360,9 +390,7 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
 #pragma unroll
     for (int t = 0; t < MAXT; ++t) {
         if (t < count) {
-            const bool first = t < cnt1;
-            const int Ib = first ? I1 : I2;
-            const int Jb = first ? I1 + t : I2 + (t - cnt1);
+            const int Ib = tile_I(t), Jb = tile_J(t);
             const int col = Jb * 16 + li;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -376,6 +404,8 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
         }
     }
 }
+#undef tile_I
+#undef tile_J
 
 // ---------------------------------------------------------------------------
 // k_reproj
@@ -444,7 +474,7 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
 #pragma unroll
             for (int u = 0; u < SVN; ++u) {
                 const int e = tid + u * LR_THREADS;
-                const int row = kk + e / s_pad, col = e % s_pad;
+                const int eq = div_small(e, s_pad), row = kk + eq, col = e - eq * s_pad;
                 sv[u] = (e < srow && row < s && col < s) ? S[(int64_t)row * s + col] : cmk<C>(0, 0);
             }
         };
@@ -556,7 +586,7 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
         // anti-diagonal sums of this chunk, fixed order, one owner per entry
         const int rows_here = min(KC, l - r0);
         for (int e = tid; e < utab; e += LR_THREADS) {
-            const int i = e % n, blk = e / n;
+            const int blk = div_small(e, n), i = e - blk * n;
             C acc = Bacc[e];
             if (side == 0) {
                 // chunk rows are a in [r0, r0 + rows_here): b = i - a in [0, k)
@@ -911,25 +941,28 @@ hipError_t launch_lift_gram_multi(hipStream_t st, const cplx_t<R>* hb, const cpl
     int s = 0;
     for (int i = 0; i < n_protos; ++i) s = std::max(s, lr_s(protos[i]));
     const int nt = (s + 15) / 16;
-    const int n_units = (nt + 1) / 2;
-    const int groups = (n_units + LR_WAVES - 1) / LR_WAVES;
+    // tiles per wave: the upper triangle's tiles over LR_WAVES * groups waves, at most 16 each
+    const int n_tiles = nt * (nt + 1) / 2;
+    int groups = 1;
+    while ((n_tiles + LR_WAVES * groups - 1) / (LR_WAVES * groups) > 16) ++groups;
+    const int need = (n_tiles + LR_WAVES * groups - 1) / (LR_WAVES * groups);
     // rows of A staged per chunk; by default 16, or 8 where that lets the kernel prefetch
     const int s_pad = nt * 16;
     int KC = 16;
-    if (!gram_prefetches(sizeof(R), nt + 1, 16, s_pad) && gram_prefetches(sizeof(R), nt + 1, 8, s_pad)) KC = 8;
+    if (!gram_prefetches(sizeof(R), need, 16, s_pad) && gram_prefetches(sizeof(R), need, 8, s_pad)) KC = 8;
     if (kc == 4 || kc == 8 || kc == 16 || kc == 32) KC = kc;
     while (KC > 4 && gram_lds_max<R>(protos, n_protos, KC) > LDS_LIMIT) KC /= 2;
     const size_t lds = gram_lds_max<R>(protos, n_protos, KC);
     if (lds > LDS_LIMIT) return hipErrorInvalidValue;
     dim3 grid(count, groups);
     const R ib = (R)(1.0 / beta);
-    const int need = nt + 1;
     if (need <= 4) return launch_gram_t<R, 4>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
     if (need <= 8) return launch_gram_t<R, 8>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
-    if (need <= 12) return launch_gram_t<R, 12>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
-    if (need <= 16) return launch_gram_t<R, 16>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
-    if (need <= 21) return launch_gram_t<R, 21>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
-    return hipErrorInvalidValue;  // s > 320
+    if (need <= 12)
+        return launch_gram_t<R, 12>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
+    if (need <= 16)
+        return launch_gram_t<R, 16>(grid, lds, st, hb, db, wtab, descs_dev, m0, Gs, g_stride, ib, KC);
+    return hipErrorInvalidValue;
 }
 
 // Launch the Gram kernel for matrices [m0, m0 + count) that share (V, J, n, k).
