@@ -259,7 +259,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines_seg(const cplx_t<R>* 
                                                                const FftSeg* __restrict__ segs, int n_seg) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int si = find_seg(segs, n_seg, blockIdx.x);
-    const FftSeg sg = segs[si];
+    const FftSeg& sg = segs[si];   // read in place (a local copy of the plan's arrays would go to scratch)
     fft_lines_block<R>(smem_raw, in, out, sg.ia, sg.oa, sg.pl, sg.n_lines, sg.NL, sg.inverse, (R)sg.scale,
                        blockIdx.x - sg.block0);
 }
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows_seg(cplx_t<R>* cbase,
                                                                const int32_t* active) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int si = find_seg(segs, n_seg, blockIdx.x);
-    const XupdSeg sg = segs[si];
+    const XupdSeg& sg = segs[si];   // read in place (a local copy of the plan's arrays would go to scratch)
     xupd_rows_block<R>(smem_raw, cbase + sg.bo, cbase + sg.a, cbase + sg.y, cbase + sg.k, cbase + sg.out,
                        mbase + sg.m, rtab, sg.x, sg.pl, sg.NL, lam, beta, hard_dc,
                        change ? change + 2 * sg.unit : nullptr, active ? active + sg.unit : nullptr, 0,
