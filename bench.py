@@ -169,7 +169,32 @@ def diff_leg(batch, steps, kw, lam, beta, reps=2):
     ck, wk = plan.unrolled_sizes(steps)
     plan.close()
     fwd, bwd = min(tf), min(tb)
+    # accuracy of the timed (mixed) reverse mode on the first slice: the directional derivative
+    # <gY, d> against a central difference of L = Re <gk, K_steps> from two FP64 forwards
+    y1 = torch.from_numpy(ys[0].ravel()).to(torch.complex128).cuda()
+    m1 = torch.from_numpy(mask.ravel()).cuda()
+    g1 = gk[:y1.numel()].to(torch.complex128)
+    rng = np.random.default_rng(78)
+    d = torch.from_numpy(rng.standard_normal(y1.shape) + 1j * rng.standard_normal(y1.shape)).cuda()
+    one = dict(M=(M,), N=(N,), J=J, k_row=kw, k_col=kw, lam=lam, beta=beta, tau=beta, normalize=False)
+
+    def loss(yv):
+        pl = shlr.Plan(shlr.Params(precision=shlr.PREC_FP64, **one))
+        kv = pl.unrolled_forward(yv, m1, steps)
+        pl.close()
+        return float((torch.conj(g1) * kv.to(torch.complex128)).real.sum().item())
+
+    eps = 1e-6 * float(torch.linalg.vector_norm(y1)) / float(torch.linalg.vector_norm(d))
+    fd = (loss(y1 + eps * d) - loss(y1 - eps * d)) / (2 * eps)
+    pl = shlr.Plan(shlr.Params(precision=shlr.PREC_MIXED, **one))
+    pl.unrolled_forward(y1.to(torch.complex64), m1, steps)
+    gy, _ = pl.unrolled_backward(g1.to(torch.complex64), steps)
+    pl.close()
+    an = float(torch.sum((torch.conj(gy.to(torch.complex128)) * d).real).item())
     return {
+        "accuracy": {"what": "first slice: directional derivative <gY, d> of the mixed-precision reverse mode against "
+                             "a central difference of two FP64 forwards (step 1e-6 of |Y|, seeded direction)",
+                     "vjp": an, "central_difference": fd, "rel_error": abs(an - fd) / abs(fd)},
         "workload": f"reverse mode through {steps} unrolled SHLR iterations, batch {batch} x 8 coils x 256x256 "
                     "complex64 (seeds 1000+b, shared 2D Poisson-disc R=4 mask), window 25, lambda=1e4, beta=tau=30; "
                     "gradient w.r.t. Y and lambda; checkpoints K and D of every iteration",
