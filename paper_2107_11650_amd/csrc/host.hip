@@ -329,7 +329,7 @@ static LRDesc make_desc(int64_t h_off, int h_cs, int h_es, int64_t b_off, int b_
     return d;
 }
 
-static const size_t SLOT_BUDGET = (size_t)3 << 30;   // eigen-solver scratch for one chunk
+static const size_t SLOT_BUDGET = (size_t)16 << 30;   // eigen-solver scratch for one chunk (of 288 GB HBM)
 
 // Eigen-solver class of a matrix order: register-resident reductions (order <= 208, or <= 256
 // in FP32) apart from in-memory ones, then by the number of 64-row tiles the eigen kernel is
