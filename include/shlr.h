@@ -114,6 +114,10 @@ typedef struct {
     double tol;             /* relative-change stop of Algorithm S1/S2; <= 0: fixed count;  */
                             /* checked per unit (slice of PI, FE position of PARAM)         */
     double d0;              /* initial multiplier value (Algorithms S1/S2 use 1)           */
+    int64_t slot_budget;    /* bytes of eigen-solver slots per chunk of a run of lifted     */
+                            /* matrices (G, S and solver scratch per matrix); 0: 16 GiB.   */
+                            /* A run larger than the budget is solved in chunks, one set   */
+                            /* of launches each (results do not depend on it); >= 0        */
 } shlr_params;
 
 typedef struct {

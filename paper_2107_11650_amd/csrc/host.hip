@@ -277,6 +277,7 @@ static shlr_status validate(const shlr_params* p) {
         return fail(SHLR_E_INVALID_ARG, "lambda must be positive and finite (or set hard_dc)");
     if (!(p->lambda1 >= 0) || !isfinite(p->lambda1)) return fail(SHLR_E_INVALID_ARG, "lambda1 must be >= 0");
     if (!isfinite(p->d0)) return fail(SHLR_E_INVALID_ARG, "d0 must be finite");
+    if (p->slot_budget < 0) return fail(SHLR_E_INVALID_ARG, "slot_budget must be >= 0 (0: the default)");
     if (p->max_iter < 0) return fail(SHLR_E_INVALID_ARG, "max_iter must be >= 0");
     if (p->model == SHLR_MODEL_PARAM) {
         if (p->L < 2 || p->L > 512) return fail(SHLR_E_INVALID_ARG, "L must be in [2, 512]");
@@ -393,7 +394,8 @@ static void layout_slots(shlr_plan* P) {
         r.s_stride = (int64_t)r.smax * r.smax;                // working complex
         r.scr_stride = eig_scratch_doubles(r.smax);           // doubles
         const size_t per = r.g_stride * 16 + r.s_stride * P->csize + r.scr_stride * 8 + 3 * 256;
-        r.slots = (int)std::min<size_t>((size_t)r.count, std::max<size_t>(1, SLOT_BUDGET / per));
+        const size_t budget = P->p.slot_budget > 0 ? (size_t)P->p.slot_budget : SLOT_BUDGET;
+        r.slots = (int)std::min<size_t>((size_t)r.count, std::max<size_t>(1, budget / per));
         P->bytes_g = std::max(P->bytes_g, (size_t)r.slots * r.g_stride * 16);
         P->bytes_s = std::max(P->bytes_s, (size_t)r.slots * r.s_stride * P->csize);
         P->bytes_scr = std::max(P->bytes_scr, (size_t)r.slots * r.scr_stride * 8);

@@ -62,6 +62,7 @@ class CParams(ctypes.Structure):
         ("n_cg", ctypes.c_int32),
         ("lam", ctypes.c_double), ("lambda1", ctypes.c_double), ("lambda2", ctypes.c_double),
         ("beta", ctypes.c_double), ("tau", ctypes.c_double), ("tol", ctypes.c_double), ("d0", ctypes.c_double),
+        ("slot_budget", ctypes.c_int64),
     ]
 
 
@@ -152,6 +153,7 @@ class Params:
     tau: float | None = None
     tol: float = 0.0
     d0: float = 1.0
+    slot_budget: int = 0
 
     def to_c(self):
         n = len(self.M)
@@ -162,7 +164,7 @@ class Params:
                     spirit_ksize=self.spirit_ksize, hard_dc=int(self.hard_dc), normalize=int(self.normalize),
                     max_iter=self.max_iter, n_cg=self.n_cg, lam=self.lam, lambda1=self.lambda1,
                     lambda2=self.lambda2, beta=self.beta, tau=self.beta if self.tau is None else self.tau,
-                    tol=self.tol, d0=self.d0)
+                    tol=self.tol, d0=self.d0, slot_budget=int(self.slot_budget))
         return c, (Ma, Na)
 
     @classmethod

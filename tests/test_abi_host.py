@@ -67,6 +67,7 @@ def test_valid_plans_report_workspace():
     (dict(M=(1024,), N=(1024,), J=16, k_row=25, k_col=25), 6),   # min(p, q) > 320
     # FP64 virtual-coil lifts of 12-coil 256-point lines: line table beyond the LDS staging
     (dict(M=(256,), N=(256,), J=12, k_row=25, k_col=25, use_vc=True, precision=1), 6),
+    (dict(slot_budget=-1), 1),
 ])
 def test_invalid_plans_are_rejected(kw, code):
     from paper_2107_11650_amd import shlr
@@ -74,6 +75,19 @@ def test_invalid_plans_are_rejected(kw, code):
         shlr.plan_check(_p(**kw))
     assert ei.value.code == code
     assert str(ei.value)
+
+
+def test_slot_budget_bounds_the_workspace():
+    # a run's eigen-solver slots follow the budget: a small one gives a smaller workspace (more
+    # chunks of launches), the default 0 is the 16 GiB budget, and a budget under one slot still
+    # leaves one slot per run
+    from paper_2107_11650_amd import shlr
+    kw = dict(M=(40, 64), N=(48, 32), J=2, k_row=5, k_col=5)
+    full = shlr.plan_check(_p(**kw))
+    assert shlr.plan_check(_p(slot_budget=16 << 30, **kw)) == full
+    small = shlr.plan_check(_p(slot_budget=1 << 20, **kw))
+    one = shlr.plan_check(_p(slot_budget=1, **kw))
+    assert 0 < one < small < full
 
 
 def test_param_model_validation():

@@ -130,3 +130,27 @@ def test_graph_replays_with_spirit_match_eager(prec):
     g = O.spirit_calibrate(Y / np.abs(Y).max(), acs=16, ks=5)
     ref = O.shlr_pi(Y, mask, O.PIParams(k_row=6, k_col=6, lam=1e4, lam1=10.0, beta=10.0, vc=True, n_cg=6, iters=4), g=g)
     check(runs[1][-1], ref, *BARS[prec], label=f"graph SHLR-SV {prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_chunked_runs_match_one_chunk(prec):
+    """A slot budget under one run's size splits each run into chunks with launches of their own
+    (the per-matrix work is the same): three iterations of a ragged three-slice batch give K
+    bitwise equal to the default budget's single chunk per run."""
+    shlr = _lib()
+    probs = _slices() + [(lambda k, m: (inputs.undersample(k, m), m))(
+        inputs.phantom_kspace(2, 48, 44, seed=1033), inputs.mask_cartesian_vd(48, 44, R=2.5, n_center=6, seed=2033))]
+    outs = []
+    for budget in (0, 1 << 20):
+        p = shlr.Params(M=tuple(Y.shape[1] for Y, _ in probs), N=tuple(Y.shape[2] for Y, _ in probs), J=2, k_row=5,
+                        k_col=5, lam=1e3, beta=6.0, tau=6.0, max_iter=3, slot_budget=budget,
+                        precision=shlr.PREC_FP64 if prec == "fp64" else shlr.PREC_MIXED)
+        print(f"slot budget {budget}: workspace {shlr.plan_check(p)} bytes", flush=True)
+        plan = shlr.Plan(p)
+        plan.init(torch.cat([dev(Y, plan.cdtype).reshape(-1) for Y, _ in probs]),
+                  torch.cat([dev(m.astype(np.uint8), torch.uint8).reshape(-1) for _, m in probs]))
+        plan.iterate(3)
+        outs.append(host(plan.kspace()))
+        plan.close()
+    assert np.array_equal(outs[0], outs[1])
+
