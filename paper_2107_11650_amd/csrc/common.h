@@ -25,6 +25,14 @@ __device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x 
 // conj(a) * b
 __device__ inline double2 cmulc(double2 a, double2 b) { return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
 __device__ inline float2 cmulc(float2 a, float2 b) { return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
+// e / d without an integer division, for 0 <= e < 2^21 and 1 <= d < 2^24, from a reciprocal of d
+// good to an ulp (v_rcp_f32): (e + 1/2) / d lies at least 1/(2d) from an integer, while the
+// product's relative error (under 2^-22) moves it by less than (e + 1/2) 2^-22 / d < 1/(2d), so
+// truncation gives the exact quotient.
+__device__ inline int div_small(int e, int d) {
+    return (int)(((float)e + 0.5f) * __builtin_amdgcn_rcpf((float)d));
+}
+
 __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 // acc + a b as four fused multiply-adds
 __device__ inline double2 cfma(double2 a, double2 b, double2 acc) {

@@ -18,7 +18,7 @@ namespace shlr {
 
 constexpr int FFT_THREADS = 512;
 __device__ inline int64_t line_off(const LineAddr& a, int g) {
-    const int g1 = g / a.n0, g0 = g - (g / a.n0) * a.n0;
+    const int g1 = g < (1 << 21) ? div_small(g, a.n0) : g / a.n0, g0 = g - g1 * a.n0;
     return a.base + (int64_t)g1 * a.s1 + (int64_t)g0 * a.s0;
 }
 
@@ -48,17 +48,18 @@ __device__ C* fft_run(C* b0, C* b1, const C* tw, int n, int NL, const FftPlan& p
         const int nb = n / r;
         const int tsc = n / (Ns * r);
         for (int e = tid; e < NL * nb; e += nth) {
-            const int line = e / nb, j = e - line * nb;
+            const int line = div_small(e, nb), j = e - line * nb;
             const C* in = b0 + line * n;
             C* out = b1 + line * n;
-            const int kq = j % Ns;
+            const int jq = div_small(j, Ns), kq = j - jq * Ns;
             const int tstep = kq * tsc;
-            const int od = (j / Ns) * Ns * r + kq;
+            const int od = jq * Ns * r + kq;
             if (r == 4) {
                 C x0 = in[j];
-                C x1 = cmul(in[j + nb], twid(tw, tstep % n, n, inv));
-                C x2 = cmul(in[j + 2 * nb], twid(tw, (2 * tstep) % n, n, inv));
-                C x3 = cmul(in[j + 3 * nb], twid(tw, (3 * tstep) % n, n, inv));
+                // kq < Ns gives tstep < n / r, so u tstep < n for u < r: no reduction mod n
+                C x1 = cmul(in[j + nb], twid(tw, tstep, n, inv));
+                C x2 = cmul(in[j + 2 * nb], twid(tw, 2 * tstep, n, inv));
+                C x3 = cmul(in[j + 3 * nb], twid(tw, 3 * tstep, n, inv));
                 C s02 = cadd(x0, x2), d02 = csub(x0, x2);
                 C s13 = cadd(x1, x3), d13 = csub(x1, x3);
                 // forward: -i * d13 ; inverse: +i * d13
@@ -69,16 +70,19 @@ __device__ C* fft_run(C* b0, C* b1, const C* tw, int n, int NL, const FftPlan& p
                 out[od + 3 * Ns] = csub(d02, jd);
             } else if (r == 2) {
                 C x0 = in[j];
-                C x1 = cmul(in[j + nb], twid(tw, tstep % n, n, inv));
+                C x1 = cmul(in[j + nb], twid(tw, tstep, n, inv));
                 out[od] = cadd(x0, x1);
                 out[od + Ns] = csub(x0, x1);
             } else {
                 for (int u = 0; u < r; ++u) {
                     C acc = cmk<C>(0, 0);
+                    // t step mod n, stepped: step = tstep + u nb < n / r + (r - 1) n / r = n
                     const int step = tstep + u * nb;
+                    int idx = 0;
                     for (int t = 0; t < r; ++t) {
-                        const int idx = (int)(((int64_t)t * step) % n);
                         acc = cadd(acc, cmul(in[j + t * nb], twid(tw, idx, n, inv)));
+                        idx += step;
+                        if (idx >= n) idx -= n;
                     }
                     out[od + u * Ns] = acc;
                 }
@@ -141,7 +145,7 @@ __device__ C* dft_run(const FftLds<C>& L, int NL, const FftPlan& pl, bool inv, i
     const int n = pl.n, f = pl.f;
     // inverse by conjugation: conj(DFT(conj(x)))
     for (int e = tid; e < NL * f; e += nth) {
-        const int line = e / f, j = e - line * f;
+        const int line = div_small(e, f), j = e - line * f;
         C v = cmk<C>(0, 0);
         if (j < n) {
             C x = L.b0[line * f + j];
@@ -152,13 +156,13 @@ __device__ C* dft_run(const FftLds<C>& L, int NL, const FftPlan& pl, bool inv, i
     }
     __syncthreads();
     C* r = fft_run(L.b0, L.b1, L.tw, f, NL, pl, false, tid, nth);
-    for (int e = tid; e < NL * f; e += nth) r[e] = cmul(r[e], L.bt[e % f]);
+    for (int e = tid; e < NL * f; e += nth) r[e] = cmul(r[e], L.bt[e - div_small(e, f) * f]);
     __syncthreads();
     C* o = (r == L.b0) ? L.b1 : L.b0;
     C* r2 = fft_run(r, o, L.tw, f, NL, pl, true, tid, nth);
     const double invf = 1.0 / (double)f;
     for (int e = tid; e < NL * n; e += nth) {
-        const int line = e / n, k = e - line * n;
+        const int line = div_small(e, n), k = e - line * n;
         C v = cmulc(L.wch[k], r2[line * f + k]);   // conj(w_k) c_k
         v.x *= invf;
         v.y *= invf;
@@ -177,7 +181,7 @@ __device__ inline void load_lines_centred(C* dst, const C* src, const LineAddr& 
     if (a.es == 1) {
 #pragma unroll 4
         for (int e = tid; e < nl * n; e += nth) {
-            const int line = e / n, i = e - line * n;
+            const int line = div_small(e, n), i = e - line * n;
             int t = i - c;
             if (t < 0) t += n;
             dst[line * ls + t] = src[line_off(a, g0 + line) + i];
@@ -185,7 +189,7 @@ __device__ inline void load_lines_centred(C* dst, const C* src, const LineAddr& 
     } else {
 #pragma unroll 4
         for (int e = tid; e < nl * n; e += nth) {
-            const int line = e % nl, i = e / nl;
+            const int i = div_small(e, nl), line = e - i * nl;
             int t = i - c;
             if (t < 0) t += n;
             dst[line * ls + t] = src[line_off(a, g0 + line) + (int64_t)i * a.es];
@@ -200,7 +204,7 @@ __device__ inline void store_lines_centred(C* dstg, const C* res, const LineAddr
     if (a.es == 1) {
 #pragma unroll 4
         for (int e = tid; e < nl * n; e += nth) {
-            const int line = e / n, i = e - line * n;
+            const int line = div_small(e, n), i = e - line * n;
             int f = i - c;
             if (f < 0) f += n;
             dstg[line_off(a, g0 + line) + i] = cscale(res[line * ls + f], scale);
@@ -208,7 +212,7 @@ __device__ inline void store_lines_centred(C* dstg, const C* res, const LineAddr
     } else {
 #pragma unroll 4
         for (int e = tid; e < nl * n; e += nth) {
-            const int line = e % nl, i = e / nl;
+            const int i = div_small(e, nl), line = e - i * nl;
             int f = i - c;
             if (f < 0) f += n;
             dstg[line_off(a, g0 + line) + (int64_t)i * a.es] = cscale(res[line * ls + f], scale);
@@ -303,7 +307,7 @@ __device__ inline void xupd_rows_block(unsigned char* smem_raw, const cplx_t<R>*
     if (x.bo.es == 1) {
 #pragma unroll 4
         for (int e = tid; e < nl * n; e += FFT_THREADS) {
-            const int line = e / n, i = e - line * n;
+            const int line = div_small(e, n), i = e - line * n;
             int d2, d1, d0;
             row_digits(x, g0 + line, d2, d1, d0);
             int t = i - c;
@@ -313,7 +317,7 @@ __device__ inline void xupd_rows_block(unsigned char* smem_raw, const cplx_t<R>*
     } else {
 #pragma unroll 4
         for (int e = tid; e < nl * n; e += FFT_THREADS) {
-            const int line = e % nl, i = e / nl;
+            const int i = div_small(e, nl), line = e - i * nl;
             int d2, d1, d0;
             row_digits(x, g0 + line, d2, d1, d0);
             int t = i - c;
@@ -332,7 +336,7 @@ __device__ inline void xupd_rows_block(unsigned char* smem_raw, const cplx_t<R>*
     bool cur_act = true;
 #pragma unroll 4
     for (int e = tid; e < nl * n; e += FFT_THREADS) {
-        const int line = e / n, i = e - line * n;
+        const int line = div_small(e, n), i = e - line * n;
         int d2, d1, d0;
         row_digits(x, g0 + line, d2, d1, d0);
         int f = i - c;
@@ -410,7 +414,7 @@ __device__ inline void xupd_rows_block(unsigned char* smem_raw, const cplx_t<R>*
     if (x.out.es == 1) {
 #pragma unroll 4
         for (int e = tid; e < nl * n; e += FFT_THREADS) {
-            const int line = e / n, i = e - line * n;
+            const int line = div_small(e, n), i = e - line * n;
             int d2, d1, d0;
             row_digits(x, g0 + line, d2, d1, d0);
             int f = i - c;
@@ -420,7 +424,7 @@ __device__ inline void xupd_rows_block(unsigned char* smem_raw, const cplx_t<R>*
     } else {
 #pragma unroll 4
         for (int e = tid; e < nl * n; e += FFT_THREADS) {
-            const int line = e % nl, i = e / nl;
+            const int i = div_small(e, nl), line = e - i * nl;
             int d2, d1, d0;
             row_digits(x, g0 + line, d2, d1, d0);
             int f = i - c;
@@ -491,7 +495,7 @@ __global__ __launch_bounds__(SPC_THREADS) void k_spirit_cols(const cplx_t<R>* __
     const FftLds<C> L = fft_setup<C>(smem_raw, pl, J, tid, SPC_THREADS);
 #pragma unroll 4
     for (int e = tid; e < J * M; e += SPC_THREADS) {
-        const int j = e / M, m = e - j * M;
+        const int j = div_small(e, M), m = e - j * M;
         int q = m - c;
         if (q < 0) q += M;
         L.b0[j * ls + q] = t[j * MN + (int64_t)m * N + n];
@@ -511,7 +515,7 @@ __global__ __launch_bounds__(SPC_THREADS) void k_spirit_cols(const cplx_t<R>* __
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int e = min(e0 + h * SPC_THREADS, M * J - 1);
-            const int m = e / J, a = e - m * J;
+            const int m = div_small(e, J), a = e - m * J;
             int q = m - c;
             if (q < 0) q += M;
             qq[h] = q;
@@ -546,7 +550,7 @@ __global__ __launch_bounds__(SPC_THREADS) void k_spirit_cols(const cplx_t<R>* __
     C* r2 = dft_run(L2, J, pl, false, tid, SPC_THREADS);
 #pragma unroll 4
     for (int e = tid; e < J * M; e += SPC_THREADS) {
-        const int j = e / M, m = e - j * M;
+        const int j = div_small(e, M), m = e - j * M;
         int q = m - c;
         if (q < 0) q += M;
         y[j * MN + (int64_t)m * N + n] = cscale(r2[j * ls + q], sc);
@@ -583,7 +587,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_dir(cplx_t<R>* __restr
     const int nl = min(NL, n_lines - g0);
 #pragma unroll 4
     for (int e = tid; e < nl * N; e += FFT_THREADS) {
-        const int line = e / N, i = e - line * N;
+        const int line = div_small(e, N), i = e - line * N;
         int q = i - c;
         if (q < 0) q += N;
         const int64_t ge = (int64_t)(g0 + line) * N + i;
@@ -597,7 +601,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_dir(cplx_t<R>* __restr
     const R sc = (R)(1.0 / sqrt((double)N));
 #pragma unroll 4
     for (int e = tid; e < nl * N; e += FFT_THREADS) {
-        const int line = e / N, i = e - line * N;
+        const int line = div_small(e, N), i = e - line * N;
         int q = i - c;
         if (q < 0) q += N;
         t[(int64_t)(g0 + line) * N + i] = cscale(res[line * ls + q], sc);
@@ -620,7 +624,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_apply(cplx_t<R>* __res
     const int nl = min(NL, J * M - g0);
 #pragma unroll 4
     for (int e = tid; e < nl * N; e += FFT_THREADS) {
-        const int line = e / N, i = e - line * N;
+        const int line = div_small(e, N), i = e - line * N;
         int q = i - c;
         if (q < 0) q += N;
         L.b0[line * ls + q] = io[(int64_t)(g0 + line) * N + i];
@@ -631,7 +635,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_apply(cplx_t<R>* __res
     double acc = 0;
 #pragma unroll 4
     for (int e = tid; e < nl * N; e += FFT_THREADS) {
-        const int line = e / N, i = e - line * N;
+        const int line = div_small(e, N), i = e - line * N;
         int q = i - c;
         if (q < 0) q += N;
         const int m = (g0 + line) % M;

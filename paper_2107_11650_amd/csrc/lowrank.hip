@@ -53,14 +53,6 @@ __device__ inline void load_line_table(cplx_t<R>* U, const cplx_t<R>* hb, const 
     load_line_table_at<R>(U, hb, d.h_off, d.h_cs, d.h_es, wtab, d, tid, nth);
 }
 
-// e / d without an integer division, for 0 <= e < 2^21 and 1 <= d < 2^24, from a reciprocal of d
-// good to an ulp (v_rcp_f32): (e + 1/2) / d lies at least 1/(2d) from an integer, while the
-// product's relative error (under 2^-22) moves it by less than (e + 1/2) 2^-22 / d < 1/(2d), so
-// truncation gives the exact quotient.
-__device__ inline int div_small(int e, int d) {
-    return (int)(((float)e + 0.5f) * __builtin_amdgcn_rcpf((float)d));
-}
-
 // Value of T (without the D term) at (a, col).
 template <typename C>
 __device__ inline C lift_val(const C* U, int n, int k, int a, int col) {
