@@ -471,7 +471,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_xupd_rows_seg(cplx_t<R>* cbase,
 // SPIRiT operator of the X-update (Eq. 3 inside Eq. 15) with fewer passes:
 //   k_spirit_cols: for one image column n of all J coils, the inverse column
 //     transform, the per-pixel product with Aimg = (Gimg - I)^H (Gimg - I)
-//     (J x J, [pixel][a][b]) and the forward column transform, in one block;
+//     (J x J per pixel, stored [n][b][m][a]) and the forward column transform, in one block;
 //     t and y are [J][M][N] with t already transformed along its rows;
 //   k_fft_rows_apply: the forward row transform of y fused with the PCG
 //     operator Ap = den p + lambda1 y, in place, and one partial Re<p, Ap>
@@ -504,9 +504,10 @@ __global__ __launch_bounds__(SPC_THREADS) void k_spirit_cols(const cplx_t<R>* __
     C* res = dft_run(L, J, pl, true, tid, SPC_THREADS);
     C* oth = (res == L.b0) ? L.b1 : L.b0;
     const R sc = (R)(1.0 / sqrt((double)M));
-    // one (pixel, output coil) pair per thread: the J threads of a pixel read its J x J block
-    // coalesced.  Two pairs per thread at a time, their operator rows read in groups of 8 entries
-    // before the products, so that a group waits for memory once rather than once per entry.
+    // one (pixel m, output coil a) pair per thread, e = m J + a: entry b of the operator rows of
+    // all pairs of the column is contiguous in e, so every operator read is coalesced.  Two pairs per
+    // thread at a time, their rows read in groups of 8 entries before the products, so that a group
+    // waits for memory once rather than once per entry.
     constexpr int GB = 8;
     for (int e0 = tid; e0 < M * J; e0 += 2 * SPC_THREADS) {
         R sr[2] = {0, 0}, si[2] = {0, 0};
@@ -520,14 +521,14 @@ __global__ __launch_bounds__(SPC_THREADS) void k_spirit_cols(const cplx_t<R>* __
             if (q < 0) q += M;
             qq[h] = q;
             aa[h] = a;
-            Ar[h] = A + (((int64_t)m * N + n) * J + a) * J;
+            Ar[h] = A + (int64_t)n * J * M * J + e;   // entry b of this row at + b M J
         }
         for (int b0 = 0; b0 < J; b0 += GB) {
             C mv[2][GB];
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int u = 0; u < GB; ++u) mv[h][u] = b0 + u < J ? Ar[h][b0 + u] : cmk<C>(0, 0);
+                for (int u = 0; u < GB; ++u) mv[h][u] = b0 + u < J ? Ar[h][(int64_t)(b0 + u) * M * J] : cmk<C>(0, 0);
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll

@@ -46,9 +46,12 @@ __global__ void k_spirit_gimg(const double2* __restrict__ g, int J, int ks, int 
     }
 }
 
-// A[pix][a][b] = sum_t conj(Gm[pix][t][a]) Gm[pix][t][b]
+// A_pix[a][b] = sum_t conj(Gm[pix][t][a]) Gm[pix][t][b], pix = m N + n, stored at A[n][b][m][a]: the
+// operator of image column n is one block, and within it entry b of the rows of all (m, a) pairs is
+// contiguous in m J + a, the order in which one thread per (m, a) reads it
 template <typename R>
-__global__ void k_spirit_gram(const cplx_t<R>* __restrict__ Gm, int J, int64_t npix, cplx_t<R>* __restrict__ A) {
+__global__ void k_spirit_gram(const cplx_t<R>* __restrict__ Gm, int J, int M, int N, cplx_t<R>* __restrict__ A) {
+    const int64_t npix = (int64_t)M * N;
     const int64_t total = npix * J * J;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int b = (int)(e % J);
@@ -61,22 +64,25 @@ __global__ void k_spirit_gram(const cplx_t<R>* __restrict__ Gm, int J, int64_t n
             sr += (double)x.x * y.x + (double)x.y * y.y;
             si += (double)x.x * y.y - (double)x.y * y.x;
         }
-        A[e] = cmk<cplx_t<R>>(sr, si);
+        const int m = (int)(pix / N), n = (int)(pix - (int64_t)m * N);
+        A[(((int64_t)n * J + b) * M + m) * J + a] = cmk<cplx_t<R>>(sr, si);
     }
 }
 
-// y_a(r) = sum_b A[r][a][b] x_b(r), images in layout [J][npix]
+// y_a(r) = sum_b A_r[a][b] x_b(r), images in layout [J][npix], A in the layout of k_spirit_gram
 template <typename R>
 __global__ void k_spirit_matvec(const cplx_t<R>* __restrict__ A, const cplx_t<R>* __restrict__ x,
-                                cplx_t<R>* __restrict__ y, int J, int64_t npix) {
+                                cplx_t<R>* __restrict__ y, int J, int M, int N) {
     using C = cplx_t<R>;
+    const int64_t npix = (int64_t)M * N;
     for (int64_t pix = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; pix < npix;
          pix += (int64_t)gridDim.x * blockDim.x) {
-        const C* Ap = A + pix * J * J;
+        const int pm = (int)(pix / N), pn = (int)(pix - (int64_t)pm * N);
+        const C* Ap = A + ((int64_t)pn * J * M + pm) * J;   // + (b M + 0) J + a
         for (int a = 0; a < J; ++a) {
             R sr = 0, si = 0;
             for (int b = 0; b < J; ++b) {
-                const C m = Ap[a * J + b], v = x[(int64_t)b * npix + pix];
+                const C m = Ap[(int64_t)b * M * J + a], v = x[(int64_t)b * npix + pix];
                 sr += m.x * v.x - m.y * v.y;
                 si += m.x * v.y + m.y * v.x;
             }
@@ -269,14 +275,14 @@ hipError_t launch_spirit_build(hipStream_t st, const double2* g_dev, int J, int 
     hipLaunchKernelGGL((k_spirit_gimg<R>), dim3(ew_grid(tot)), dim3(256), 0, st, g_dev, J, ks, M, N, Gtmp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_spirit_gram<R>), dim3(ew_grid(tot)), dim3(256), 0, st, Gtmp, J, (int64_t)M * N, A);
+    hipLaunchKernelGGL((k_spirit_gram<R>), dim3(ew_grid(tot)), dim3(256), 0, st, Gtmp, J, M, N, A);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_spirit_matvec(hipStream_t st, const cplx_t<R>* A, const cplx_t<R>* x, cplx_t<R>* y, int J,
-                                int64_t npix) {
-    hipLaunchKernelGGL((k_spirit_matvec<R>), dim3(ew_grid(npix)), dim3(256), 0, st, A, x, y, J, npix);
+hipError_t launch_spirit_matvec(hipStream_t st, const cplx_t<R>* A, const cplx_t<R>* x, cplx_t<R>* y, int J, int M,
+                                int N) {
+    hipLaunchKernelGGL((k_spirit_matvec<R>), dim3(ew_grid((int64_t)M * N)), dim3(256), 0, st, A, x, y, J, M, N);
     return hipGetLastError();
 }
 
@@ -332,8 +338,8 @@ hipError_t launch_pcg_dir(hipStream_t st, cplx_t<R>* p, const cplx_t<R>* z, int6
 #define SPIRIT_INST(R)                                                                                                \
     template hipError_t launch_spirit_build<R>(hipStream_t, const double2*, int, int, int, int, cplx_t<R>*,           \
                                                cplx_t<R>*);                                                           \
-    template hipError_t launch_spirit_matvec<R>(hipStream_t, const cplx_t<R>*, const cplx_t<R>*, cplx_t<R>*, int,     \
-                                                int64_t);                                                             \
+    template hipError_t launch_spirit_matvec<R>(hipStream_t, const cplx_t<R>*, const cplx_t<R>*, cplx_t<R>*, int, int, \
+                                                int);                                                                 \
     template hipError_t launch_pcg_apply<R>(hipStream_t, const cplx_t<R>*, const cplx_t<R>*, cplx_t<R>*, int64_t, int, \
                                             int, const uint8_t*, const R*, int64_t, int64_t, double, double, double,  \
                                             double*);                                                                 \

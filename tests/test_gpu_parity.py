@@ -395,6 +395,33 @@ def test_spirit_calibrated_on_device(prec, tol):
     check(out, ref, min(tol, RUN_BARS[prec][0]), RUN_BARS[prec][1], label=f"SPIRiT calibrated {prec}")
 
 
+_UNFUSED_REF = {}
+
+
+def unfused_spirit_case(M):
+    """4 coils of M x 24.  The column pass of the SPIRiT operator would need (M + 8 M) complex entries
+    of LDS: for M = 1152 in FP64 and M = 2304 in FP32 that is over 160 KB, so the operator runs as
+    separate column transforms and a per-pixel matrix-vector kernel."""
+    if M not in _UNFUSED_REF:
+        k = inputs.phantom_kspace(4, M, 24, seed=1012)
+        mask = inputs.mask_poisson_disc(M, 24, R=3.0, acs=16, seed=2012)
+        Y = inputs.undersample(k, mask)
+        g = O.spirit_calibrate(Y / np.abs(Y).max(), acs=16, ks=5)
+        prm = O.PIParams(k_row=4, k_col=4, lam=1e4, lam1=10.0, beta=10.0, n_cg=3, iters=1)
+        _UNFUSED_REF[M] = dict(Y=Y, mask=mask, g=g, prm=prm, ref=O.shlr_pi(Y, mask, prm, g=g))
+    return _UNFUSED_REF[M]
+
+
+@pytest.mark.parametrize("prec,M,tol", [("fp64", 1152, 1e-20), ("mixed", 2304, 1e-12)])
+def test_spirit_unfused_operator(prec, M, tol):
+    shlr = _lib()
+    c = unfused_spirit_case(M)
+    out = run_spirit_gpu(c["Y"], c["mask"], c["prm"], shlr.PREC_FP64 if prec == "fp64" else shlr.PREC_MIXED,
+                         g=c["g"])
+    check(out, c["ref"], min(tol, RUN_BARS[prec][0]), RUN_BARS[prec][1],
+          label=f"SPIRiT unfused operator M={M} {prec}")
+
+
 # ---------------------------------------------------------------------------
 # autotuned launch parameters
 # ---------------------------------------------------------------------------
