@@ -305,11 +305,16 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
 #define tile_I(t) ((t) < E0 ? I0 : ((t) < E1 ? I1 : I2))
 #define tile_J(t) ((t) < E0 ? J0 + (t) : ((t) < E1 ? J1 + ((t) - E0) : J2 + ((t) - E1)))
 
-    A4 accR[MAXT], accI[MAXT];
+    // Entries of conj(a) b with three real products (Gauss) where the registers allow the third
+    // accumulator: P1 = ar br, P2 = ai bi, P3 = (ar - ai)(br + bi), Re = P1 + P2, Im = P3 - P1 + P2.
+    // Otherwise four: acc1 = Re, acc2 = Im.
+    constexpr bool G3 = (sizeof(R) == 4 && MAXT <= 12) || MAXT <= 4;
+    A4 acc1[MAXT], acc2[MAXT], acc3[MAXT];
 #pragma unroll
     for (int t = 0; t < MAXT; ++t) {
-        accR[t] = A4{0, 0, 0, 0};
-        accI[t] = A4{0, 0, 0, 0};
+        acc1[t] = A4{0, 0, 0, 0};
+        acc2[t] = A4{0, 0, 0, 0};
+        if constexpr (G3) acc3[t] = A4{0, 0, 0, 0};
     }
 
     load_line_table<R>(U, hb, wtab, d, tid, LR_THREADS);
@@ -353,10 +358,16 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
                         if (t < count) {
                             const R ar = t < E0 ? pr0 : (t < E1 ? pr1 : pr2);
                             const R ai = t < E0 ? pm0 : (t < E1 ? pm1 : pm2);
-                            accR[t] = mfma16(ar, br[t], accR[t]);
-                            accR[t] = mfma16(ai, bi[t], accR[t]);
-                            accI[t] = mfma16(ar, bi[t], accI[t]);
-                            accI[t] = mfma16(-ai, br[t], accI[t]);
+                            if constexpr (G3) {
+                                acc1[t] = mfma16(ar, br[t], acc1[t]);
+                                acc2[t] = mfma16(ai, bi[t], acc2[t]);
+                                acc3[t] = mfma16(ar - ai, br[t] + bi[t], acc3[t]);
+                            } else {
+                                acc1[t] = mfma16(ar, br[t], acc1[t]);
+                                acc1[t] = mfma16(ai, bi[t], acc1[t]);
+                                acc2[t] = mfma16(ar, bi[t], acc2[t]);
+                                acc2[t] = mfma16(-ai, br[t], acc2[t]);
+                            }
                         }
                     }
                 } else {
@@ -366,10 +377,16 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
                             const int Ib = tile_I(t), Jb = tile_J(t);
                             const R ar = Ar[row + Ib * 16], ai = Ai[row + Ib * 16];
                             const R br = Ar[row + Jb * 16], bi = Ai[row + Jb * 16];
-                            accR[t] = mfma16(ar, br, accR[t]);
-                            accR[t] = mfma16(ai, bi, accR[t]);
-                            accI[t] = mfma16(ar, bi, accI[t]);
-                            accI[t] = mfma16(-ai, br, accI[t]);
+                            if constexpr (G3) {
+                                acc1[t] = mfma16(ar, br, acc1[t]);
+                                acc2[t] = mfma16(ai, bi, acc2[t]);
+                                acc3[t] = mfma16(ar - ai, br + bi, acc3[t]);
+                            } else {
+                                acc1[t] = mfma16(ar, br, acc1[t]);
+                                acc1[t] = mfma16(ai, bi, acc1[t]);
+                                acc2[t] = mfma16(ar, bi, acc2[t]);
+                                acc2[t] = mfma16(-ai, br, acc2[t]);
+                            }
                         }
                     }
                 }
@@ -388,9 +405,11 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
             for (int r = 0; r < 4; ++r) {
                 const int row = Ib * 16 + acc_row<R>(lk, r);
                 if (row < s && col < s) {
+                    const R gr = G3 ? acc1[t][r] + acc2[t][r] : acc1[t][r];
+                    const R gi = G3 ? acc3[t][r] - acc1[t][r] + acc2[t][r] : acc2[t][r];
                     // packed lower triangle; the diagonal tiles hold both halves
-                    if (row >= col) G[pk(row, col, s)] = make_double2((double)accR[t][r], (double)accI[t][r]);
-                    else if (Ib != Jb) G[pk(col, row, s)] = make_double2((double)accR[t][r], -(double)accI[t][r]);
+                    if (row >= col) G[pk(row, col, s)] = make_double2((double)gr, (double)gi);
+                    else if (Ib != Jb) G[pk(col, row, s)] = make_double2((double)gr, -(double)gi);
                 }
             }
         }
@@ -450,11 +469,16 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
         __syncthreads();
         stage_A_chunk<R, 8>(Ar, Ai, ldA, U, Dm, d, inv_beta, r0, KC, s_pad, tid, LR_THREADS);
         __syncthreads();
-        A4 accR[MAXT], accI[MAXT];
+        // Complex products with three real ones (Gauss) where the registers allow the third
+        // accumulator: P1 = Ar Sr, P2 = Ai Si, P3 = (Ar + Ai)(Sr + Si), Re Y = P1 - P2,
+        // Im Y = P3 - P1 - P2.  Otherwise four: acc1 = Re Y, acc2 = Im Y.
+        constexpr bool G3 = (sizeof(R) == 4 && MAXT <= 8) || MAXT <= 2;
+        A4 acc1[MAXT], acc2[MAXT], acc3[MAXT];
 #pragma unroll
         for (int t = 0; t < MAXT; ++t) {
-            accR[t] = A4{0, 0, 0, 0};
-            accI[t] = A4{0, 0, 0, 0};
+            acc1[t] = A4{0, 0, 0, 0};
+            acc2[t] = A4{0, 0, 0, 0};
+            if constexpr (G3) acc3[t] = A4{0, 0, 0, 0};
         }
         // tiles of this wave: t-th tile = wave + t * LR_WAVES.  The four rows of S that step kk
         // needs are staged in LDS (two buffers); the rows of step kk + 4 are loaded from L2 into
@@ -494,10 +518,16 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
                             sr = svv.x;
                             si = svv.y;
                         }
-                        accR[t] = mfma16(ar, sr, accR[t]);
-                        accR[t] = mfma16(-ai, si, accR[t]);
-                        accI[t] = mfma16(ar, si, accI[t]);
-                        accI[t] = mfma16(ai, sr, accI[t]);
+                        if constexpr (G3) {
+                            acc1[t] = mfma16(ar, sr, acc1[t]);
+                            acc2[t] = mfma16(ai, si, acc2[t]);
+                            acc3[t] = mfma16(ar + ai, sr + si, acc3[t]);
+                        } else {
+                            acc1[t] = mfma16(ar, sr, acc1[t]);
+                            acc1[t] = mfma16(-ai, si, acc1[t]);
+                            acc2[t] = mfma16(ar, si, acc2[t]);
+                            acc2[t] = mfma16(ai, sr, acc2[t]);
+                        }
                     }
                 }
             }
@@ -512,17 +542,23 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
             if (kk + 4 < s_pad) load_rows(kk + 4);
             // every operand of the step is read before the products (one wait per step)
             const int arow = (It_w * 16 + li) * ldA + kidx;
-            const R ar = Ar[arow], ai = Ai[arow];
+            const R ar = Ar[arow], ai = Ai[arow], as = ar + ai;
             C sb[MAXT];
 #pragma unroll
             for (int t = 0; t < MAXT; ++t) sb[t] = cur[lk * s_pad + min(kw + nwi * t, nt - 1) * 16 + li];
 #pragma unroll
             for (int t = 0; t < MAXT; ++t) {
                 if (kw + nwi * t < nt) {   // uniform over the wave
-                    accR[t] = mfma16(ar, sb[t].x, accR[t]);
-                    accR[t] = mfma16(-ai, sb[t].y, accR[t]);
-                    accI[t] = mfma16(ar, sb[t].y, accI[t]);
-                    accI[t] = mfma16(ai, sb[t].x, accI[t]);
+                    if constexpr (G3) {
+                        acc1[t] = mfma16(ar, sb[t].x, acc1[t]);
+                        acc2[t] = mfma16(ai, sb[t].y, acc2[t]);
+                        acc3[t] = mfma16(as, sb[t].x + sb[t].y, acc3[t]);
+                    } else {
+                        acc1[t] = mfma16(ar, sb[t].x, acc1[t]);
+                        acc1[t] = mfma16(-ai, sb[t].y, acc1[t]);
+                        acc2[t] = mfma16(ar, sb[t].y, acc2[t]);
+                        acc2[t] = mfma16(ai, sb[t].x, acc2[t]);
+                    }
                 }
             }
             if (kk + 4 < s_pad) store_rows(nxt);
@@ -558,8 +594,10 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
                     if (row < l && col < s) {
                         int a, c;
                         C z;
-                        if (side == 0) { a = row; c = col; z = cmk<C>(accR[t][r], accI[t][r]); }
-                        else { a = col; c = row; z = cmk<C>(accR[t][r], -accI[t][r]); }
+                        const R yr = G3 ? acc1[t][r] - acc2[t][r] : acc1[t][r];
+                        const R yi = G3 ? acc3[t][r] - acc1[t][r] - acc2[t][r] : acc2[t][r];
+                        if (side == 0) { a = row; c = col; z = cmk<C>(yr, yi); }
+                        else { a = col; c = row; z = cmk<C>(yr, -yi); }
                         const C lv = lift_val(U, n, k, a, c);
                         const int64_t di = (int64_t)a * q + c;
                         if constexpr (!BATCH) dv[r] = Dm[di];
