@@ -305,10 +305,10 @@ __global__ __launch_bounds__(LR_THREADS) void k_lift_gram(const cplx_t<R>* __res
 #define tile_I(t) ((t) < E0 ? I0 : ((t) < E1 ? I1 : I2))
 #define tile_J(t) ((t) < E0 ? J0 + (t) : ((t) < E1 ? J1 + ((t) - E0) : J2 + ((t) - E1)))
 
-    // Entries of conj(a) b with three real products (Gauss) where the registers allow the third
-    // accumulator: P1 = ar br, P2 = ai bi, P3 = (ar - ai)(br + bi), Re = P1 + P2, Im = P3 - P1 + P2.
-    // Otherwise four: acc1 = Re, acc2 = Im.
-    constexpr bool G3 = (sizeof(R) == 4 && MAXT <= 12) || MAXT <= 4;
+    // Entries of conj(a) b with three real products (Gauss) in FP32 where the registers allow the
+    // third accumulator: P1 = ar br, P2 = ai bi, P3 = (ar - ai)(br + bi), Re = P1 + P2,
+    // Im = P3 - P1 + P2.  Otherwise (and in FP64) four: acc1 = Re, acc2 = Im.
+    constexpr bool G3 = sizeof(R) == 4 && MAXT <= 12;
     A4 acc1[MAXT], acc2[MAXT], acc3[MAXT];
 #pragma unroll
     for (int t = 0; t < MAXT; ++t) {
@@ -469,10 +469,10 @@ __global__ __launch_bounds__(LR_THREADS) void k_reproj(const cplx_t<R>* __restri
         __syncthreads();
         stage_A_chunk<R, 8>(Ar, Ai, ldA, U, Dm, d, inv_beta, r0, KC, s_pad, tid, LR_THREADS);
         __syncthreads();
-        // Complex products with three real ones (Gauss) where the registers allow the third
+        // Complex products with three real ones (Gauss) in FP32 where the registers allow the third
         // accumulator: P1 = Ar Sr, P2 = Ai Si, P3 = (Ar + Ai)(Sr + Si), Re Y = P1 - P2,
-        // Im Y = P3 - P1 - P2.  Otherwise four: acc1 = Re Y, acc2 = Im Y.
-        constexpr bool G3 = (sizeof(R) == 4 && MAXT <= 8) || MAXT <= 2;
+        // Im Y = P3 - P1 - P2.  Otherwise (and in FP64) four: acc1 = Re Y, acc2 = Im Y.
+        constexpr bool G3 = sizeof(R) == 4 && MAXT <= 8;
         A4 acc1[MAXT], acc2[MAXT], acc3[MAXT];
 #pragma unroll
         for (int t = 0; t < MAXT; ++t) {
