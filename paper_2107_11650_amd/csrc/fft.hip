@@ -558,57 +558,6 @@ __global__ __launch_bounds__(SPC_THREADS) void k_spirit_cols(const cplx_t<R>* __
     }
 }
 
-// PCG direction update fused with the first (inverse, row) pass of the SPIRiT operator:
-// rz_new = sum of the previous update's partials (fixed order), beta = rz_new / rz_prev,
-// p = z + beta p (written back), t = F_n^-1 p along rows.  Block 0 stores rz_new for the next
-// step length.  Rows of length N, J*M of them, contiguous.
-template <typename R>
-__global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_dir(cplx_t<R>* __restrict__ p, const cplx_t<R>* __restrict__ z,
-                                                              cplx_t<R>* __restrict__ t, int n_lines, int N,
-                                                              FftPlan pl, int NL, const double* __restrict__ upart,
-                                                              int n_upart, const double* __restrict__ rz_prev,
-                                                              double* __restrict__ rz_out) {
-    using C = cplx_t<R>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[FFT_THREADS];
-    const int tid = threadIdx.x, ls = pl.f, c = N / 2;
-    double a = 0;
-    for (int i = tid; i < n_upart; i += FFT_THREADS) a += upart[i];
-    red[tid] = a;
-    __syncthreads();
-    for (int h = FFT_THREADS / 2; h > 0; h >>= 1) {
-        if (tid < h) red[tid] += red[tid + h];
-        __syncthreads();
-    }
-    const double rz_new = red[0], rz0 = *rz_prev;
-    if (blockIdx.x == 0 && tid == 0) *rz_out = rz_new;
-    const R bc = (R)(rz0 != 0.0 ? rz_new / rz0 : 0.0);
-    const FftLds<C> L = fft_setup<C>(smem_raw, pl, NL, tid, FFT_THREADS);
-    const int g0 = blockIdx.x * NL;
-    const int nl = min(NL, n_lines - g0);
-#pragma unroll 4
-    for (int e = tid; e < nl * N; e += FFT_THREADS) {
-        const int line = div_small(e, N), i = e - line * N;
-        int q = i - c;
-        if (q < 0) q += N;
-        const int64_t ge = (int64_t)(g0 + line) * N + i;
-        const C pv = p[ge], zv = z[ge];
-        const C np = cmk<C>(zv.x + bc * pv.x, zv.y + bc * pv.y);
-        p[ge] = np;
-        L.b0[line * ls + q] = np;
-    }
-    __syncthreads();
-    C* res = dft_run(L, nl, pl, true, tid, FFT_THREADS);
-    const R sc = (R)(1.0 / sqrt((double)N));
-#pragma unroll 4
-    for (int e = tid; e < nl * N; e += FFT_THREADS) {
-        const int line = div_small(e, N), i = e - line * N;
-        int q = i - c;
-        if (q < 0) q += N;
-        t[(int64_t)(g0 + line) * N + i] = cscale(res[line * ls + q], sc);
-    }
-}
-
 template <typename R>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_apply(cplx_t<R>* __restrict__ io,
                                                                 const cplx_t<R>* __restrict__ p, int J, int M, int N,
@@ -655,6 +604,197 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_apply(cplx_t<R>* __res
         double tsum = 0;
         for (int w = 0; w < FFT_THREADS / 64; ++w) tsum += red[w];
         partials[blockIdx.x] = tsum;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// PCG of the SPIRiT X-update in the Chronopoulos-Gear form (one reduction phase per step: both
+// inner products of a step are formed before its direction update), so that a step is three
+// launches: first row pass, column pass (k_spirit_cols), second row pass.  With u = M^-1 r,
+// w = A u, gamma = <r, u>, delta = <u, w>:
+//   beta_i = gamma_i / gamma_{i-1},  alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}),
+//   p_i = u_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1}  (s_i = A p_i),
+//   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i;
+// in exact arithmetic the iterates of PCG.  Inner products are sums of per-block partials in a
+// fixed order, formed again in every block that needs them.
+// ---------------------------------------------------------------------------
+
+// fixed-order sum of n partials (the same bits in every block); all FFT_THREADS threads call
+__device__ inline double rows_sum(const double* __restrict__ v, int n, double* red) {
+    const int tid = threadIdx.x;
+    double a = 0;
+    for (int i = tid; i < n; i += FFT_THREADS) a += v[i];
+    red[tid] = a;
+    __syncthreads();
+    for (int h = FFT_THREADS / 2; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    const double t = red[0];
+    __syncthreads();
+    return t;
+}
+
+// alpha of step cs.step; block 0 keeps its gamma and alpha in the slots of the step's parity (the
+// previous step's slots are the other pair, so no block reads a slot this launch writes)
+__device__ inline double cg_alpha(const CgStep& cs, double* red) {
+    const double g = cs.step == 0 ? *cs.gam0 : rows_sum(cs.gpart_in, cs.np, red);
+    const double d = rows_sum(cs.dpart_in, cs.np, red);
+    double den = d;
+    if (cs.step > 0) {
+        const double gp = cs.slots[(cs.step - 1) & 1], ap = cs.slots[2 + ((cs.step - 1) & 1)];
+        const double b = gp != 0.0 ? g / gp : 0.0;
+        den = ap != 0.0 ? d - b * g / ap : 0.0;
+    }
+    const double a = (den != 0.0 && g != 0.0) ? g / den : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        cs.slots[cs.step & 1] = g;
+        cs.slots[2 + (cs.step & 1)] = a;
+    }
+    return a;
+}
+
+// preconditioner: the X-update's diagonal den at (row m, column i)
+template <typename R>
+__device__ inline R cg_den(const uint8_t* __restrict__ mask, const R* __restrict__ rtab, int64_t rr_off,
+                           int64_t rc_off, R lam, R beta, int m, int i, int N) {
+    return (mask[(int64_t)m * N + i] ? lam : (R)0) + beta * (rtab[rr_off + i] + rtab[rc_off + m]);
+}
+
+// block partial of a per-thread sum into out[blockIdx.x]; all threads call
+__device__ inline void rows_partial(double acc, double* red, double* out) {
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int w = 0; w < FFT_THREADS / 64; ++w) t += red[w];
+        out[blockIdx.x] = t;
+    }
+}
+
+// First row pass of step i: alpha_i, x += alpha_i p, r -= alpha_i s, u = r / den, partials of
+// <r, u> (gamma_{i+1}), t = F_n^-1 u along rows.  Rows are the J*M lines of length N.
+template <typename R>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_cg1(cplx_t<R>* __restrict__ x, cplx_t<R>* __restrict__ r,
+                                                              const cplx_t<R>* __restrict__ p,
+                                                              const cplx_t<R>* __restrict__ s,
+                                                              cplx_t<R>* __restrict__ t, int J, int M, int N,
+                                                              FftPlan pl, int NL, const uint8_t* __restrict__ mask,
+                                                              const R* __restrict__ rtab, int64_t rr_off,
+                                                              int64_t rc_off, R lam, R beta, CgStep cs) {
+    using C = cplx_t<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[FFT_THREADS];
+    const int tid = threadIdx.x, ls = pl.f, c = N / 2;
+    const R al = (R)cg_alpha(cs, red);
+    const FftLds<C> L = fft_setup<C>(smem_raw, pl, NL, tid, FFT_THREADS);
+    const int g0 = blockIdx.x * NL;
+    const int nl = min(NL, J * M - g0);
+    double acc = 0;
+#pragma unroll 4
+    for (int e = tid; e < nl * N; e += FFT_THREADS) {
+        const int line = div_small(e, N), i = e - line * N;
+        int q = i - c;
+        if (q < 0) q += N;
+        const int g = g0 + line, m = g - div_small(g, M) * M;
+        const int64_t ge = (int64_t)g * N + i;
+        const R d = cg_den(mask, rtab, rr_off, rc_off, lam, beta, m, i, N);
+        const C pv = p[ge], sv = s[ge];
+        C xv = x[ge], rv = r[ge];
+        xv.x += al * pv.x;
+        xv.y += al * pv.y;
+        rv.x -= al * sv.x;
+        rv.y -= al * sv.y;
+        const C uv = cscale(rv, (R)1 / d);
+        x[ge] = xv;
+        r[ge] = rv;
+        L.b0[line * ls + q] = uv;
+        acc += (double)rv.x * uv.x + (double)rv.y * uv.y;
+    }
+    rows_partial(acc, red, cs.gpart_out);   // ends with a barrier: the staged rows are complete
+    C* res = dft_run(L, nl, pl, true, tid, FFT_THREADS);
+    const R sc = (R)(1.0 / sqrt((double)N));
+#pragma unroll 4
+    for (int e = tid; e < nl * N; e += FFT_THREADS) {
+        const int line = div_small(e, N), i = e - line * N;
+        int q = i - c;
+        if (q < 0) q += N;
+        t[(int64_t)(g0 + line) * N + i] = cscale(res[line * ls + q], sc);
+    }
+}
+
+// Second row pass of step i (set-up: of step -1, beta = 0): y is the column pass's output, so that
+// F_n y along rows completes the SPIRiT part of w = A u = den u + lambda1 F (G-I)^H (G-I) F^-1 u;
+// u = r / den again, partials of <u, w> (delta_{i+1}), beta_{i+1} = gamma_{i+1} / gamma_i,
+// p = u + beta p, s = w + beta s.
+template <typename R>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_cg3(const cplx_t<R>* __restrict__ y,
+                                                              const cplx_t<R>* __restrict__ r,
+                                                              cplx_t<R>* __restrict__ p, cplx_t<R>* __restrict__ s,
+                                                              int J, int M, int N, FftPlan pl, int NL,
+                                                              const uint8_t* __restrict__ mask,
+                                                              const R* __restrict__ rtab, int64_t rr_off,
+                                                              int64_t rc_off, R lam, R beta, R lam1, CgStep cs) {
+    using C = cplx_t<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[FFT_THREADS];
+    const int tid = threadIdx.x, ls = pl.f, c = N / 2;
+    R bc = 0;
+    if (!cs.setup) {   // uniform
+        const double gn = rows_sum(cs.gpart_in, cs.np, red), go = cs.slots[cs.step & 1];
+        bc = (R)(go != 0.0 ? gn / go : 0.0);
+    }
+    const FftLds<C> L = fft_setup<C>(smem_raw, pl, NL, tid, FFT_THREADS);
+    const int g0 = blockIdx.x * NL;
+    const int nl = min(NL, J * M - g0);
+#pragma unroll 4
+    for (int e = tid; e < nl * N; e += FFT_THREADS) {
+        const int line = div_small(e, N), i = e - line * N;
+        int q = i - c;
+        if (q < 0) q += N;
+        L.b0[line * ls + q] = y[(int64_t)(g0 + line) * N + i];
+    }
+    __syncthreads();
+    C* res = dft_run(L, nl, pl, false, tid, FFT_THREADS);
+    const R sc = (R)(1.0 / sqrt((double)N));
+    double acc = 0;
+#pragma unroll 4
+    for (int e = tid; e < nl * N; e += FFT_THREADS) {
+        const int line = div_small(e, N), i = e - line * N;
+        int q = i - c;
+        if (q < 0) q += N;
+        const int g = g0 + line, m = g - div_small(g, M) * M;
+        const int64_t ge = (int64_t)g * N + i;
+        const R d = cg_den(mask, rtab, rr_off, rc_off, lam, beta, m, i, N);
+        const C uv = cscale(r[ge], (R)1 / d);
+        const C tv = cscale(res[line * ls + q], sc);
+        const C wv = cmk<C>(d * uv.x + lam1 * tv.x, d * uv.y + lam1 * tv.y);
+        acc += (double)uv.x * wv.x + (double)uv.y * wv.y;
+        if (cs.setup) {
+            p[ge] = uv;
+            s[ge] = wv;
+        } else {
+            const C pv = p[ge], sv = s[ge];
+            p[ge] = cmk<C>(uv.x + bc * pv.x, uv.y + bc * pv.y);
+            s[ge] = cmk<C>(wv.x + bc * sv.x, wv.y + bc * sv.y);
+        }
+    }
+    rows_partial(acc, red, cs.dpart_out);
+}
+
+// the last step's x += alpha p (its r, u and w are not needed)
+template <typename R>
+__global__ __launch_bounds__(FFT_THREADS) void k_cg_final(cplx_t<R>* __restrict__ x, const cplx_t<R>* __restrict__ p,
+                                                          int64_t count, CgStep cs) {
+    __shared__ double red[FFT_THREADS];
+    const R al = (R)cg_alpha(cs, red);
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
+        const cplx_t<R> pv = p[e];
+        cplx_t<R> xv = x[e];
+        xv.x += al * pv.x;
+        xv.y += al * pv.y;
+        x[e] = xv;
     }
 }
 
@@ -1008,17 +1148,44 @@ hipError_t launch_spirit_cols(hipStream_t st, const cplx_t<R>* t, cplx_t<R>* y, 
 }
 
 template <typename R>
-hipError_t launch_fft_rows_dir(hipStream_t st, cplx_t<R>* p, const cplx_t<R>* z, cplx_t<R>* t, int n_lines, int N,
-                               const double* upart, int n_upart, const double* rz_prev, double* rz_out) {
+hipError_t launch_fft_rows_cg1(hipStream_t st, cplx_t<R>* x, cplx_t<R>* r, const cplx_t<R>* p, const cplx_t<R>* s,
+                               cplx_t<R>* t, int J, int M, int N, const uint8_t* mask, const R* rtab, int64_t rr_off,
+                               int64_t rc_off, double lam, double beta, const CgStep& cs) {
     const FftPlan pl = make_fft_plan(N);
     const int NL = fft_lines_per_block<R>(pl, false);
     const size_t lds = fft_lds_bytes<R>(pl, NL);
-    hipError_t e = hipFuncSetAttribute((const void*)k_fft_rows_dir<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    const int blocks = (J * M + NL - 1) / NL;
+    if (blocks != cs.np) return hipErrorInvalidValue;   // the partial sets are one entry per block
+    hipError_t e = hipFuncSetAttribute((const void*)k_fft_rows_cg1<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
-    const int blocks = (n_lines + NL - 1) / NL;
-    hipLaunchKernelGGL((k_fft_rows_dir<R>), dim3(blocks), dim3(FFT_THREADS), lds, st, p, z, t, n_lines, N, pl, NL,
-                       upart, n_upart, rz_prev, rz_out);
+    hipLaunchKernelGGL((k_fft_rows_cg1<R>), dim3(blocks), dim3(FFT_THREADS), lds, st, x, r, p, s, t, J, M, N, pl, NL,
+                       mask, rtab, rr_off, rc_off, (R)lam, (R)beta, cs);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_fft_rows_cg3(hipStream_t st, const cplx_t<R>* y, const cplx_t<R>* r, cplx_t<R>* p, cplx_t<R>* s,
+                               int J, int M, int N, const uint8_t* mask, const R* rtab, int64_t rr_off, int64_t rc_off,
+                               double lam, double beta, double lam1, const CgStep& cs) {
+    const FftPlan pl = make_fft_plan(N);
+    const int NL = fft_lines_per_block<R>(pl, false);
+    const size_t lds = fft_lds_bytes<R>(pl, NL);
+    const int blocks = (J * M + NL - 1) / NL;
+    if (blocks != cs.np) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void*)k_fft_rows_cg3<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fft_rows_cg3<R>), dim3(blocks), dim3(FFT_THREADS), lds, st, y, r, p, s, J, M, N, pl, NL,
+                       mask, rtab, rr_off, rc_off, (R)lam, (R)beta, (R)lam1, cs);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_cg_final(hipStream_t st, cplx_t<R>* x, const cplx_t<R>* p, int64_t count, const CgStep& cs) {
+    const int64_t need = (count + FFT_THREADS - 1) / FFT_THREADS;
+    const int blocks = (int)std::min<int64_t>(std::max<int64_t>(need, 1), 1024);
+    hipLaunchKernelGGL((k_cg_final<R>), dim3(blocks), dim3(FFT_THREADS), 0, st, x, p, count, cs);
     return hipGetLastError();
 }
 
@@ -1062,8 +1229,13 @@ hipError_t launch_fft_rows_apply(hipStream_t st, cplx_t<R>* io, const cplx_t<R>*
                                                 int, int, size_t, double, double, int, double*, const int32_t*);  \
     template hipError_t launch_change_pair<R>(hipStream_t, const cplx_t<R>*, const cplx_t<R>*, int64_t, double*,     \
                                               const int32_t*, cplx_t<R>*);                                           \
-    template hipError_t launch_fft_rows_dir<R>(hipStream_t, cplx_t<R>*, const cplx_t<R>*, cplx_t<R>*, int, int,        \
-                                               const double*, int, const double*, double*);                          \
+    template hipError_t launch_fft_rows_cg1<R>(hipStream_t, cplx_t<R>*, cplx_t<R>*, const cplx_t<R>*, const cplx_t<R>*, \
+                                               cplx_t<R>*, int, int, int, const uint8_t*, const R*, int64_t, int64_t, \
+                                               double, double, const CgStep&);                                       \
+    template hipError_t launch_fft_rows_cg3<R>(hipStream_t, const cplx_t<R>*, const cplx_t<R>*, cplx_t<R>*,           \
+                                               cplx_t<R>*, int, int, int, const uint8_t*, const R*, int64_t, int64_t, \
+                                               double, double, double, const CgStep&);                               \
+    template hipError_t launch_cg_final<R>(hipStream_t, cplx_t<R>*, const cplx_t<R>*, int64_t, const CgStep&);        \
     template hipError_t launch_spirit_cols<R>(hipStream_t, const cplx_t<R>*, cplx_t<R>*, const cplx_t<R>*, int, int, \
                                               int);                                                                  \
     template hipError_t launch_fft_rows_apply<R>(hipStream_t, cplx_t<R>*, const cplx_t<R>*, int, int, int,           \

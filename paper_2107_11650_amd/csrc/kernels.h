@@ -91,9 +91,29 @@ int spirit_fused_blocks(int J, int M, int N);
 template <typename R>
 hipError_t launch_spirit_cols(hipStream_t st, const cplx_t<R>* t, cplx_t<R>* y, const cplx_t<R>* A, int J, int M,
                               int N);
+// One step of the Chronopoulos-Gear form of preconditioned CG: partial-sum sets and scalar slots.
+// gamma = <r, u>, delta = <u, A u>, u = r / den; slots = {gamma, gamma, alpha, alpha} by step parity.
+struct CgStep {
+    const double* gam0;       // gamma_0 (read by the first step)
+    const double* gpart_in;   // partials of the gamma the kernel needs
+    double* gpart_out;        // partials of gamma written by the first row pass
+    const double* dpart_in;   // partials of delta_i (first row pass, final update)
+    double* dpart_out;        // partials of delta written by the second row pass
+    double* slots;
+    int np;                   // partials per set (blocks of the row passes)
+    int step;
+    int setup;                // second row pass of the set-up: beta = 0
+};
 template <typename R>
-hipError_t launch_fft_rows_dir(hipStream_t st, cplx_t<R>* p, const cplx_t<R>* z, cplx_t<R>* t, int n_lines, int N,
-                               const double* upart, int n_upart, const double* rz_prev, double* rz_out);
+hipError_t launch_fft_rows_cg1(hipStream_t st, cplx_t<R>* x, cplx_t<R>* r, const cplx_t<R>* p, const cplx_t<R>* s,
+                               cplx_t<R>* t, int J, int M, int N, const uint8_t* mask, const R* rtab, int64_t rr_off,
+                               int64_t rc_off, double lam, double beta, const CgStep& cs);
+template <typename R>
+hipError_t launch_fft_rows_cg3(hipStream_t st, const cplx_t<R>* y, const cplx_t<R>* r, cplx_t<R>* p, cplx_t<R>* s,
+                               int J, int M, int N, const uint8_t* mask, const R* rtab, int64_t rr_off, int64_t rc_off,
+                               double lam, double beta, double lam1, const CgStep& cs);
+template <typename R>
+hipError_t launch_cg_final(hipStream_t st, cplx_t<R>* x, const cplx_t<R>* p, int64_t count, const CgStep& cs);
 template <typename R>
 hipError_t launch_fft_rows_apply(hipStream_t st, cplx_t<R>* io, const cplx_t<R>* p, int J, int M, int N,
                                  const uint8_t* mask, const R* rtab, int64_t rr_off, int64_t rc_off, double lam,

@@ -202,54 +202,6 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_update(cplx_t<R>* __restric
     block_partial(acc, partials);
 }
 
-// sum of n partials in a fixed order (every block of a grid gets the same bits); all threads call
-__device__ inline double sum_partials(const double* __restrict__ v, int n) {
-    __shared__ double red2[PCG_THREADS];
-    double a = 0;
-    for (int i = threadIdx.x; i < n; i += PCG_THREADS) a += v[i];
-    red2[threadIdx.x] = a;
-    __syncthreads();
-    for (int h = PCG_THREADS / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) red2[threadIdx.x] += red2[threadIdx.x + h];
-        __syncthreads();
-    }
-    const double t = red2[0];
-    __syncthreads();
-    return t;
-}
-
-// k_pcg_update with its step length formed in every block: alpha = rz / sum(partials of A p)
-template <typename R>
-__global__ __launch_bounds__(PCG_THREADS) void k_pcg_update_a(cplx_t<R>* __restrict__ x, cplx_t<R>* __restrict__ r,
-                                                              cplx_t<R>* __restrict__ z,
-                                                              const cplx_t<R>* __restrict__ p,
-                                                              const cplx_t<R>* __restrict__ Ap, int64_t count, int M,
-                                                              int N, const uint8_t* mask, const R* rtab,
-                                                              int64_t rr_off, int64_t rc_off, R lam, R beta,
-                                                              const double* __restrict__ pap_partials, int n_pap,
-                                                              const double* __restrict__ rz, double* partials) {
-    const double pap = sum_partials(pap_partials, n_pap);
-    const double rz0 = *rz;
-    const R alpha = (R)((pap != 0.0 && rz0 != 0.0) ? rz0 / pap : 0.0);
-    double acc = 0;
-#pragma unroll 4
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
-        const R d = den_at(e, M, N, mask, rtab, rr_off, rc_off, lam, beta);
-        const cplx_t<R> pv = p[e], av = Ap[e];
-        cplx_t<R> xv = x[e], rv = r[e];
-        xv.x += alpha * pv.x;
-        xv.y += alpha * pv.y;
-        rv.x -= alpha * av.x;
-        rv.y -= alpha * av.y;
-        const cplx_t<R> zv = cscale(rv, (R)1 / d);
-        x[e] = xv;
-        r[e] = rv;
-        z[e] = zv;
-        acc += (double)rv.x * zv.x + (double)rv.y * zv.y;
-    }
-    block_partial(acc, partials);
-}
-
 // p = z + beta_cg p
 template <typename R>
 __global__ void k_pcg_dir(cplx_t<R>* __restrict__ p, const cplx_t<R>* __restrict__ z, int64_t count,
@@ -320,16 +272,6 @@ hipError_t launch_pcg_update(hipStream_t st, cplx_t<R>* x, cplx_t<R>* r, cplx_t<
 }
 
 template <typename R>
-hipError_t launch_pcg_update_a(hipStream_t st, cplx_t<R>* x, cplx_t<R>* r, cplx_t<R>* z, const cplx_t<R>* p,
-                               const cplx_t<R>* Ap, int64_t count, int M, int N, const uint8_t* mask, const R* rtab,
-                               int64_t rr_off, int64_t rc_off, double lam, double beta, const double* pap_partials,
-                               int n_pap, const double* rz, double* partials) {
-    hipLaunchKernelGGL((k_pcg_update_a<R>), dim3(PCG_BLOCKS), dim3(PCG_THREADS), 0, st, x, r, z, p, Ap, count, M, N,
-                       mask, rtab, rr_off, rc_off, (R)lam, (R)beta, pap_partials, n_pap, rz, partials);
-    return hipGetLastError();
-}
-
-template <typename R>
 hipError_t launch_pcg_dir(hipStream_t st, cplx_t<R>* p, const cplx_t<R>* z, int64_t count, const double* scal) {
     hipLaunchKernelGGL((k_pcg_dir<R>), dim3(ew_grid(count)), dim3(256), 0, st, p, z, count, scal);
     return hipGetLastError();
@@ -350,10 +292,7 @@ hipError_t launch_pcg_dir(hipStream_t st, cplx_t<R>* p, const cplx_t<R>* z, int6
                                              const cplx_t<R>*, int64_t, int, int, const uint8_t*, const R*, int64_t,  \
                                              int64_t, double, double, const double*, double*);                        \
     template hipError_t launch_pcg_dir<R>(hipStream_t, cplx_t<R>*, const cplx_t<R>*, int64_t, const double*);       \
-    template hipError_t launch_pcg_update_a<R>(hipStream_t, cplx_t<R>*, cplx_t<R>*, cplx_t<R>*, const cplx_t<R>*,     \
-                                               const cplx_t<R>*, int64_t, int, int, const uint8_t*, const R*,        \
-                                               int64_t, int64_t, double, double, const double*, int, const double*, \
-                                               double*);
+
 SPIRIT_INST(float)
 SPIRIT_INST(double)
 
