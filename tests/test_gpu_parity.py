@@ -395,6 +395,20 @@ def test_spirit_calibrated_on_device(prec, tol):
     check(out, ref, min(tol, RUN_BARS[prec][0]), RUN_BARS[prec][1], label=f"SPIRiT calibrated {prec}")
 
 
+@pytest.mark.parametrize("n_cg", [1, 2, 3])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-20), ("mixed", 1e-12)])
+def test_spirit_short_pcg(n_cg, prec, tol):
+    """The fused X-update's PCG with one step (set-up pass straight to the last update), two (one
+    three-pass step) and three (both parities of its scalar slots), against the oracle's plain PCG."""
+    shlr = _lib()
+    Y, mask = spirit_problem(J=3, M=40, N=36, seed=9)
+    g = O.spirit_calibrate(Y / np.abs(Y).max(), acs=16, ks=5)
+    prm = O.PIParams(k_row=5, k_col=5, lam=1e4, lam1=10.0, beta=10.0, n_cg=n_cg, iters=3)
+    ref = O.shlr_pi(Y, mask, prm, g=g)
+    out = run_spirit_gpu(Y, mask, prm, shlr.PREC_FP64 if prec == "fp64" else shlr.PREC_MIXED, g=g)
+    check(out, ref, min(tol, RUN_BARS[prec][0]), RUN_BARS[prec][1], label=f"SPIRiT n_cg={n_cg} {prec}")
+
+
 _UNFUSED_REF = {}
 
 
