@@ -619,27 +619,42 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_apply(cplx_t<R>* __res
 // fixed order, formed again in every block that needs them.
 // ---------------------------------------------------------------------------
 
-// fixed-order sum of n partials (the same bits in every block); all FFT_THREADS threads call
-__device__ inline double rows_sum(const double* __restrict__ v, int n, double* red) {
+// fixed-order sums of two sets of n partials (the same bits in every block): per-thread strided
+// sums, lane 0's butterfly sum per wave, then the waves in order; a null set sums to 0.  All
+// FFT_THREADS threads call; red holds 2 * FFT_THREADS / 64 doubles.
+__device__ inline double2 rows_sum2(const double* __restrict__ va, const double* __restrict__ vb, int n,
+                                    double* red) {
+    constexpr int NW = FFT_THREADS / 64;
     const int tid = threadIdx.x;
-    double a = 0;
-    for (int i = tid; i < n; i += FFT_THREADS) a += v[i];
-    red[tid] = a;
-    __syncthreads();
-    for (int h = FFT_THREADS / 2; h > 0; h >>= 1) {
-        if (tid < h) red[tid] += red[tid + h];
-        __syncthreads();
+    double a = 0, b = 0;
+    for (int i = tid; i < n; i += FFT_THREADS) {
+        if (va) a += va[i];
+        if (vb) b += vb[i];
     }
-    const double t = red[0];
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    if ((tid & 63) == 0) {
+        red[tid >> 6] = a;
+        red[NW + (tid >> 6)] = b;
+    }
     __syncthreads();
-    return t;
+    double sa = 0, sb = 0;
+    for (int w = 0; w < NW; ++w) {
+        sa += red[w];
+        sb += red[NW + w];
+    }
+    __syncthreads();   // red is free again
+    return make_double2(sa, sb);
 }
 
 // alpha of step cs.step; block 0 keeps its gamma and alpha in the slots of the step's parity (the
 // previous step's slots are the other pair, so no block reads a slot this launch writes)
 __device__ inline double cg_alpha(const CgStep& cs, double* red) {
-    const double g = cs.step == 0 ? *cs.gam0 : rows_sum(cs.gpart_in, cs.np, red);
-    const double d = rows_sum(cs.dpart_in, cs.np, red);
+    const double2 gd = rows_sum2(cs.step == 0 ? nullptr : cs.gpart_in, cs.dpart_in, cs.np, red);
+    const double g = cs.step == 0 ? *cs.gam0 : gd.x;
+    const double d = gd.y;
     double den = d;
     if (cs.step > 0) {
         const double gp = cs.slots[(cs.step - 1) & 1], ap = cs.slots[2 + ((cs.step - 1) & 1)];
@@ -742,7 +757,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_cg3(const cplx_t<R>* _
     const int tid = threadIdx.x, ls = pl.f, c = N / 2;
     R bc = 0;
     if (!cs.setup) {   // uniform
-        const double gn = rows_sum(cs.gpart_in, cs.np, red), go = cs.slots[cs.step & 1];
+        const double gn = rows_sum2(cs.gpart_in, nullptr, cs.np, red).x, go = cs.slots[cs.step & 1];
         bc = (R)(go != 0.0 ? gn / go : 0.0);
     }
     const FftLds<C> L = fft_setup<C>(smem_raw, pl, NL, tid, FFT_THREADS);
